@@ -1,0 +1,205 @@
+/*
+ * nbx.h -- C ABI of the nbx direct N-body force library (MI355X / gfx950).
+ *
+ * The library is the GPU half of a GRAPE-style direct N-body code, as in
+ * Bedorf, Gaburov & Portegies Zwart, "Sapporo2: A versatile direct N-body
+ * library" (arXiv:1510.04068).  The host integrator (block time-steps,
+ * Hermite corrector, time-step choice) stays with the caller (Background;
+ * Results > Block time-step simulations).  One force evaluation is:
+ *
+ *   1. nbx_set_j      copy updated sources ("j-particles") into the library
+ *                     (the copy kernel of Methods > Other differences);
+ *   2. nbx_predict    choose the time t every source is predicted to (the
+ *                     predict kernel; prediction runs on the GPU, which cuts
+ *                     host traffic, Background, Yebisu paragraph);
+ *   3. nbx_force      forces on N_i active sinks ("i-particles") from all
+ *                     nj sources (the gravity kernel; Methods >
+ *                     Parallelisation method);
+ *   4. nbx_get_force  read the results back.
+ *
+ * Force law (the paper prints none; this is the reading used): Newtonian
+ * gravity, G = 1, Plummer softening R^2 = |r|^2 + eps2, r = x_j - x_i,
+ * v = v_j - v_i, a = a_j - a_i (predicted), alpha = r.v / R^2,
+ * beta = (v.v + r.a) / R^2 + alpha^2:
+ *     acc  += m_j r / R^3
+ *     jerk += m_j v / R^3 - 3 alpha (m_j r / R^3)
+ *     snap += m_j a / R^3 - 6 alpha A1 - 3 beta A0          (order 6)
+ *     pot  -= m_j / R
+ * Sources with the sink's own id are excluded from every output.  Jerk and
+ * snap are the time derivatives of the softened acceleration along the
+ * predicted motion, as a 4th/6th-order Hermite integrator needs them
+ * (Results; Results > Sixth order performance).
+ *
+ * Nearest neighbour (Results; Discussion > CPU: particle id and distance):
+ * the other source with the smallest |r|^2, returned as (id, |r|^2 in FP64);
+ * none: id -1, r2 +inf.  In NBX_FP64 the choice is made on the exact FP64
+ * |r|^2 (ties to the lower source address); in NBX_MIXED it is made on the
+ * FP32 value of R^2, so sources whose R^2 agree to FP32 rounding may be
+ * returned in either order.  Neighbour list (Background; Results, perturber
+ * lists): every other source with |r|^2 < h2_i, at most nbr_max per sink;
+ * the count is exact, and when it exceeds nbr_max the stored ids are an
+ * unspecified subset and the call returns NBX_WARN_NBR_OVERFLOW.
+ *
+ * Precision (Methods > Numerical Accuracy; chosen at run time, Background):
+ * sources are always stored in FP64.
+ *   NBX_FP64   every operation in IEEE double.
+ *   NBX_MIXED  predictor in FP64; positions split into double-single
+ *              (hi = fl32(x), lo = fl32(x - hi)) and differenced as
+ *              (hi_j - hi_i) + (lo_j - lo_i); everything else in FP32 with
+ *              compensated (TwoSum) accumulation.  Results are FP64 arrays.
+ *
+ * Conventions shared by every entry point:
+ *   - Return value: NBX_OK (0), a negative NBX_ERR_* code, or a positive
+ *     NBX_WARN_* code.  Nothing aborts and no C++ exception crosses the ABI;
+ *     nbx_last_error gives a per-context message for the last failure.
+ *   - Vectors are FP64 row-major [n][3] (a contiguous (n, 3) array).
+ *   - Host pointers: inputs are read and copied before the call returns, so
+ *     the caller may reuse them at once; outputs are caller-owned and written
+ *     only by nbx_get_*.
+ *   - Device pointers (the *_dev entry points): the caller owns the memory,
+ *     which must be device memory of the context's device, and the stream
+ *     (a hipStream_t passed as void*, NULL = the null stream).  Those calls
+ *     only enqueue work; the caller keeps every buffer alive until the stream
+ *     has finished it.
+ *   - A context is not thread-safe: use one context per host thread.
+ *   - NaN and inf in inputs propagate as IEEE values; they are not checked.
+ */
+#ifndef NBX_H
+#define NBX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NBX_OK 0
+#define NBX_WARN_NBR_OVERFLOW 1 /* a neighbour list was truncated to nbr_max (counts stay exact) */
+#define NBX_ERR_ARG (-1)        /* NULL pointer, negative size, bad order/precision, address out of range */
+#define NBX_ERR_CAPACITY (-2)   /* n > nj_max or ni > ni_max */
+#define NBX_ERR_STATE (-3)      /* call out of order (force before predict, get before force, ...) */
+#define NBX_ERR_DEVICE (-4)     /* a HIP call failed; see nbx_last_error */
+#define NBX_ERR_NO_DEVICE (-5)  /* no usable GPU (or the requested device does not exist) */
+#define NBX_ERR_OOM (-6)        /* device memory allocation failed */
+
+#define NBX_FP64 0
+#define NBX_MIXED 1
+
+typedef struct nbx_ctx nbx_ctx; /* opaque; owns every device buffer it allocates */
+
+typedef struct nbx_config {
+  int device;    /* HIP device ordinal */
+  int order;     /* 4: acc, jerk, pot;  6: also snap (needs snap and crackle of the sources) */
+  int precision; /* NBX_FP64 or NBX_MIXED; can be changed later with nbx_set_precision */
+  int nj_max;    /* source capacity (addresses 0 .. nj_max-1) */
+  int ni_max;    /* largest number of sinks in one nbx_force call */
+  int nbr_max;   /* neighbour-list capacity per sink; 0 disables neighbour lists */
+} nbx_config;
+
+/* Library ABI version (major * 10000 + minor * 100 + patch). */
+int nbx_version(void);
+
+/* Number of visible HIP devices; NBX_ERR_NO_DEVICE (and *count = 0) when none. */
+int nbx_device_count(int *count);
+
+/* Create a context on cfg->device and allocate its source/sink buffers.
+ * Errors: NBX_ERR_ARG (NULL, order not 4/6, bad precision, nj_max < 1,
+ * ni_max < 1, nbr_max < 0), NBX_ERR_NO_DEVICE, NBX_ERR_OOM, NBX_ERR_DEVICE.
+ * On error *out is NULL. */
+int nbx_open(nbx_ctx **out, const nbx_config *cfg);
+
+/* Release the context and all its device memory (waits for its own stream). NULL is a no-op. */
+int nbx_close(nbx_ctx *ctx);
+
+/* Message describing the last failure on this context (never NULL; "" if none).  Valid until the
+ * next call on the same context.  With ctx NULL: the message of the last failed nbx_open. */
+const char *nbx_last_error(const nbx_ctx *ctx);
+
+/* Switch the arithmetic of later nbx_force calls (NBX_FP64 or NBX_MIXED). */
+int nbx_set_precision(nbx_ctx *ctx, int precision);
+
+/* Set the number of sources in use: addresses 0 .. nj-1 take part in every force evaluation.
+ * 0 <= nj <= nj_max, else NBX_ERR_CAPACITY. */
+int nbx_set_nj(nbx_ctx *ctx, int nj);
+
+/* Copy n sources from host arrays into addresses addr[k] (the copy step).  id[n], m[n], t[n]
+ * (the time the Taylor data refers to), x, v, a, jerk [n][3]; snap and crackle [n][3] for order 6
+ * (NULL for order 4).  Every addr must be in [0, nj_max) (else NBX_ERR_ARG, nothing copied); the
+ * number of sources in use grows to cover the highest address written.  Synchronous. */
+int nbx_set_j(nbx_ctx *ctx, int n, const int32_t *addr, const int64_t *id, const double *m,
+              const double *t, const double *x, const double *v, const double *a,
+              const double *jerk, const double *snap, const double *crackle);
+
+/* Select the prediction time: every later force evaluation first predicts each source, and each
+ * by-address sink, from its own time t_j to t with its Taylor polynomial (FP64, fused into the
+ * force kernel).  Must be called after the sources are set and before nbx_force. */
+int nbx_predict(nbx_ctx *ctx, double t);
+
+/* Forces on ni sinks taken by address from the source set (the sink's state is its own
+ * predicted source state, so the self pair has r = 0 exactly and is excluded).
+ * i_addr[ni] host array, each in [0, nj); eps2 >= 0; h2[ni] squared neighbour radii or NULL
+ * (no lists).  Results stay on the device until nbx_get_force / nbx_get_nbr.  Enqueued on the
+ * context's stream; returns without waiting for the GPU. */
+int nbx_force(nbx_ctx *ctx, int ni, const int32_t *i_addr, double eps2, const double *h2);
+
+/* Forces on ni sinks given explicitly (they need not be sources): id[ni], x, v [ni][3], a [ni][3]
+ * for order 6 (else NULL).  A source with the sink's id is excluded.  The sink state is used as
+ * given (no prediction).  Otherwise as nbx_force. */
+int nbx_force_ext(nbx_ctx *ctx, int ni, const int64_t *id, const double *x, const double *v,
+                  const double *a, double eps2, const double *h2);
+
+/* Wait for the last nbx_force / nbx_force_ext and copy its results to caller-owned host arrays:
+ * acc, jerk [ni][3], snap [ni][3] (order 6), pot [ni], nn_id [ni], nn_r2 [ni].  Any pointer may be
+ * NULL to skip that output.  Returns NBX_WARN_NBR_OVERFLOW if a neighbour list overflowed. */
+int nbx_get_force(nbx_ctx *ctx, double *acc, double *jerk, double *snap, double *pot,
+                  int64_t *nn_id, double *nn_r2);
+
+/* Neighbour lists of the last force call: count[ni] (exact) and ids[ni][nbr_max] (the first
+ * min(count, nbr_max) entries of each row are valid, in no particular order). */
+int nbx_get_nbr(nbx_ctx *ctx, int32_t *count, int64_t *ids);
+
+/* Predicted FP64 state of n sources at the current prediction time: xp, vp [n][3]; ap [n][3]
+ * (order 6; NULL to skip).  addr[n] in [0, nj).  Synchronous.  Uses the same predictor as the
+ * force kernel. */
+int nbx_get_predicted(nbx_ctx *ctx, int n, const int32_t *addr, double *xp, double *vp, double *ap);
+
+/* Read back the stored (unpredicted) state of n sources, e.g. to checkpoint: any output may be
+ * NULL.  addr[n] in [0, nj_max).  Synchronous. */
+int nbx_get_j(nbx_ctx *ctx, int n, const int32_t *addr, int64_t *id, double *m, double *t,
+              double *x, double *v, double *a, double *jerk, double *snap, double *crackle);
+
+/* ---- device-pointer variants (caller-owned device memory and stream; enqueue only) ---------- */
+
+/* As nbx_set_j, from device arrays.  Out-of-range addresses are skipped and counted; the next
+ * nbx_sync reports them as NBX_ERR_ARG.  The number of sources in use is not changed: call
+ * nbx_set_nj. */
+int nbx_set_j_dev(nbx_ctx *ctx, void *stream, int n, const int32_t *d_addr, const int64_t *d_id,
+                  const double *d_m, const double *d_t, const double *d_x, const double *d_v,
+                  const double *d_a, const double *d_jerk, const double *d_snap,
+                  const double *d_crackle);
+
+/* As nbx_force, with the sink addresses and every output in caller device memory:
+ * d_acc, d_jerk [ni][3] (required), d_snap [ni][3] (order 6, else may be NULL), d_pot [ni],
+ * d_nn_id [ni], d_nn_r2 [ni] (required); d_nbr_count [ni] and d_nbr_ids [ni][nbr_max] when d_h2
+ * is given.  Sink addresses outside [0, nj) make the kernel skip that sink (its outputs are left
+ * untouched) and are counted for nbx_sync. */
+int nbx_force_dev(nbx_ctx *ctx, void *stream, int ni, const int32_t *d_i_addr, double eps2,
+                  const double *d_h2, double *d_acc, double *d_jerk, double *d_snap,
+                  double *d_pot, int64_t *d_nn_id, double *d_nn_r2, int32_t *d_nbr_count,
+                  int64_t *d_nbr_ids);
+
+/* Wait for all work this context enqueued (on its own stream and on stream) and report
+ * device-side argument errors (NBX_ERR_ARG) or neighbour-list overflow (NBX_WARN_NBR_OVERFLOW)
+ * recorded since the last nbx_sync. */
+int nbx_sync(nbx_ctx *ctx, void *stream);
+
+/* Launch shape the library would use for ni sinks against the current sources: lanes per sink,
+ * sinks per lane, source splits, workgroups.  Lets callers and benchmarks report it. */
+int nbx_launch_shape(nbx_ctx *ctx, int ni, int *lanes_per_sink, int *sinks_per_lane,
+                     int *splits, int *workgroups);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NBX_H */

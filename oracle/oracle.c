@@ -1,0 +1,192 @@
+/*
+ * oracle.c -- plain, slow, FP64 CPU oracle for the direct N-body force path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or helper with the HIP library; neither includes the other.
+ *
+ * What it computes (Bedorf, Gaburov & Portegies Zwart, "Sapporo2: A versatile
+ * direct N-body library", arXiv:1510.04068):
+ *
+ *  - oracle_predict: the source ("j-particle") predictor run before every
+ *    force evaluation (Background, Yebisu paragraph; Methods > Other
+ *    differences: copy, predict and gravity kernels).  The paper does not
+ *    print the predictor; it is the Taylor polynomial of the particle's orbit
+ *    about its own time t_j, truncated at the integrator's order: position and
+ *    velocity for 4th order, position, velocity and acceleration for 6th.
+ *
+ *  - oracle_force: direct summation of the forces exerted by the sources on
+ *    the sinks ("i-particles") (Methods > Parallelisation method), with the
+ *    quantities the Results section lists: acceleration, its time derivative
+ *    (jerk) for 4th-order Hermite, the second derivative (snap) for 6th order
+ *    (Results > Sixth order performance), the potential, the nearest
+ *    neighbour (particle id and distance, Discussion > CPU) and the list of
+ *    particles within a radius (Background; Results, NBODY4/Kira perturber
+ *    lists).  The paper prints no force law; the reading used is Newtonian
+ *    gravity with G = 1 and Plummer softening, R^2 = |r|^2 + eps^2, with jerk
+ *    and snap the exact time derivatives of the softened acceleration along
+ *    the predicted motion:
+ *        r = x_j - x_i,  v = v_j - v_i,  a = a_j - a_i
+ *        A0 = m_j r / R^3
+ *        alpha = (r.v) / R^2
+ *        A1 = m_j v / R^3 - 3 alpha A0
+ *        beta = (v.v + r.a) / R^2 + alpha^2
+ *        A2 = m_j a / R^3 - 6 alpha A1 - 3 beta A0
+ *        acc = sum A0, jerk = sum A1, snap = sum A2, pot = -sum m_j / R
+ *    Sources whose id equals the sink's id are left out of every output.
+ *
+ * Arithmetic: every per-pair term is evaluated in IEEE double exactly as
+ * written above (1/sqrt for R^-1, no fused multiply-add, no reassociation);
+ * the sums over sources run in source index order and are kept in
+ * long double (x87 80-bit) so that their rounding is negligible next to the
+ * GPU's.  Sinks are independent and are spread over OpenMP threads; a sink's
+ * result does not depend on the thread count.
+ *
+ * Nearest neighbour: the source j != i with the smallest unsoftened |r|^2,
+ * ties to the smallest source index; none -> id -1, r^2 = +inf.
+ * Neighbour list: every source j != i with |r|^2 < h_i^2 (strict,
+ * unsoftened), in source index order, the first nbr_max stored, the count
+ * exact.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORACLE_OK 0
+#define ORACLE_ERR_ARG -1
+
+/* Taylor predictor: for each particle, dt = t - t_j and
+ *   x_p = x + v dt + a dt^2/2 + jerk dt^3/6 [+ snap dt^4/24 + crackle dt^5/120]
+ *   v_p = v + a dt + jerk dt^2/2 [+ snap dt^3/6 + crackle dt^4/24]
+ *   a_p = a + jerk dt + snap dt^2/2 + crackle dt^3/6          (6th order)
+ * Arrays are [n][3] row-major; tj is [n].  ap may be NULL for order 4. */
+int oracle_predict(int n, int order, double t, const double *tj, const double *x, const double *v,
+                   const double *a, const double *jerk, const double *snap, const double *crackle,
+                   double *xp, double *vp, double *ap) {
+  if (n < 0 || (order != 4 && order != 6) || !tj || !x || !v || !a || !jerk || !xp || !vp)
+    return ORACLE_ERR_ARG;
+  if (order == 6 && (!snap || !crackle || !ap)) return ORACLE_ERR_ARG;
+  for (int p = 0; p < n; ++p) {
+    const double dt = t - tj[p];
+    const double dt2 = dt * dt, dt3 = dt2 * dt, dt4 = dt3 * dt, dt5 = dt4 * dt;
+    for (int k = 0; k < 3; ++k) {
+      const int q = 3 * p + k;
+      if (order == 4) {
+        xp[q] = x[q] + v[q] * dt + a[q] * dt2 / 2.0 + jerk[q] * dt3 / 6.0;
+        vp[q] = v[q] + a[q] * dt + jerk[q] * dt2 / 2.0;
+        if (ap) ap[q] = a[q] + jerk[q] * dt;
+      } else {
+        xp[q] = x[q] + v[q] * dt + a[q] * dt2 / 2.0 + jerk[q] * dt3 / 6.0 + snap[q] * dt4 / 24.0 +
+                crackle[q] * dt5 / 120.0;
+        vp[q] = v[q] + a[q] * dt + jerk[q] * dt2 / 2.0 + snap[q] * dt3 / 6.0 + crackle[q] * dt4 / 24.0;
+        ap[q] = a[q] + jerk[q] * dt + snap[q] * dt2 / 2.0 + crackle[q] * dt3 / 6.0;
+      }
+    }
+  }
+  return ORACLE_OK;
+}
+
+/* Direct summation.  Sources: nj, idj[nj], mj[nj], xj/vj[nj][3], aj[nj][3]
+ * (6th order only).  Sinks: ni, idi[ni], xi/vi[ni][3], ai[ni][3] (6th only),
+ * h2[ni] (NULL: no neighbour lists).  Outputs (any may be NULL except acc):
+ * acc/jerk/snap[ni][3], pot[ni], nn_id[ni], nn_r2[ni], nbr_count[ni],
+ * nbr_ids[ni][nbr_max], cond[ni][3] = (sum |A0|, sum |A1|, sum |A2|) for
+ * condition-normalised error measures.  nthreads <= 0: OpenMP default. */
+int oracle_force(int order, double eps2, int nj, const int64_t *idj, const double *mj, const double *xj,
+                 const double *vj, const double *aj, int ni, const int64_t *idi, const double *xi,
+                 const double *vi, const double *ai, const double *h2, int nbr_max, double *acc,
+                 double *jerk, double *snap, double *pot, int64_t *nn_id, double *nn_r2,
+                 int32_t *nbr_count, int64_t *nbr_ids, double *cond, int nthreads) {
+  if ((order != 4 && order != 6) || nj < 0 || ni < 0 || !idj || !mj || !xj || !vj || !idi || !xi ||
+      !vi || !acc)
+    return ORACLE_ERR_ARG;
+  if (order == 6 && (!aj || !ai)) return ORACLE_ERR_ARG;
+  if (h2 && (nbr_max < 0 || !nbr_count || (nbr_max > 0 && !nbr_ids))) return ORACLE_ERR_ARG;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+
+#pragma omp parallel for schedule(static)
+  for (int i = 0; i < ni; ++i) {
+    long double s_acc[3] = {0, 0, 0}, s_jerk[3] = {0, 0, 0}, s_snap[3] = {0, 0, 0}, s_pot = 0;
+    long double s_c0 = 0, s_c1 = 0, s_c2 = 0;
+    double best_r2 = INFINITY;
+    int64_t best_id = -1;
+    int32_t count = 0;
+    const double *x0 = xi + 3 * (size_t)i, *v0 = vi + 3 * (size_t)i;
+    const double *a0 = (order == 6) ? ai + 3 * (size_t)i : NULL;
+    for (int j = 0; j < nj; ++j) {
+      if (idj[j] == idi[i]) continue;
+      double r[3], v[3], a[3] = {0, 0, 0};
+      for (int k = 0; k < 3; ++k) {
+        r[k] = xj[3 * (size_t)j + k] - x0[k];
+        v[k] = vj[3 * (size_t)j + k] - v0[k];
+        if (order == 6) a[k] = aj[3 * (size_t)j + k] - a0[k];
+      }
+      const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+      const double R2 = r2 + eps2;
+      const double Rinv = 1.0 / sqrt(R2);
+      const double Rinv2 = Rinv * Rinv;
+      const double mR3 = mj[j] * Rinv * Rinv2;
+      const double alpha = (r[0] * v[0] + r[1] * v[1] + r[2] * v[2]) * Rinv2;
+      double A0[3], A1[3], A2[3];
+      for (int k = 0; k < 3; ++k) {
+        A0[k] = mR3 * r[k];
+        A1[k] = mR3 * v[k] - 3.0 * alpha * A0[k];
+      }
+      if (order == 6) {
+        const double beta =
+            (v[0] * v[0] + v[1] * v[1] + v[2] * v[2] + r[0] * a[0] + r[1] * a[1] + r[2] * a[2]) * Rinv2 +
+            alpha * alpha;
+        for (int k = 0; k < 3; ++k) A2[k] = mR3 * a[k] - 6.0 * alpha * A1[k] - 3.0 * beta * A0[k];
+      }
+      for (int k = 0; k < 3; ++k) {
+        s_acc[k] += A0[k];
+        s_jerk[k] += A1[k];
+        if (order == 6) s_snap[k] += A2[k];
+      }
+      s_pot -= mj[j] * Rinv;
+      s_c0 += sqrt(A0[0] * A0[0] + A0[1] * A0[1] + A0[2] * A0[2]);
+      s_c1 += sqrt(A1[0] * A1[0] + A1[1] * A1[1] + A1[2] * A1[2]);
+      if (order == 6) s_c2 += sqrt(A2[0] * A2[0] + A2[1] * A2[1] + A2[2] * A2[2]);
+      if (r2 < best_r2) { /* strict: an equal r^2 later in index order loses */
+        best_r2 = r2;
+        best_id = idj[j];
+      }
+      if (h2 && r2 < h2[i]) {
+        if (count < nbr_max) nbr_ids[(size_t)i * nbr_max + count] = idj[j];
+        ++count;
+      }
+    }
+    for (int k = 0; k < 3; ++k) {
+      acc[3 * (size_t)i + k] = (double)s_acc[k];
+      if (jerk) jerk[3 * (size_t)i + k] = (double)s_jerk[k];
+      if (snap && order == 6) snap[3 * (size_t)i + k] = (double)s_snap[k];
+    }
+    if (pot) pot[i] = (double)s_pot;
+    if (nn_id) nn_id[i] = best_id;
+    if (nn_r2) nn_r2[i] = best_r2;
+    if (h2) nbr_count[i] = count;
+    if (cond) {
+      cond[3 * (size_t)i + 0] = (double)s_c0;
+      cond[3 * (size_t)i + 1] = (double)s_c1;
+      cond[3 * (size_t)i + 2] = (double)s_c2;
+    }
+  }
+  return ORACLE_OK;
+}
+
+/* Number of OpenMP threads a parallel region would use (1 without OpenMP). */
+int oracle_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

@@ -1,0 +1,326 @@
+"""Pins of the FP64 oracle against facts that do not come from its own formulas.
+
+Each test checks the oracle against something fixed independently of the code
+under test: kinematics of an exact orbit, Newton's third law, the potential
+whose gradient the acceleration must be, finite differences in time,
+polynomial exactness of the Taylor predictor, brute-force nearest neighbours
+from scipy, the known energy of the Plummer model and the convergence order of
+the Hermite scheme.  A dropped term, a wrong sign, index or power in any output
+fails at least one of them.
+"""
+
+import math
+
+import numpy as np
+import pytest
+from scipy.spatial.distance import cdist
+
+import nbody_ics
+import oracle
+
+pytestmark = pytest.mark.usefixtures("oracle_lib")
+
+
+def _all_pairs(order, eps2, m, x, v, a=None, ids=None, **kw):
+    n = len(m)
+    ids = np.arange(n, dtype=np.int64) if ids is None else ids
+    return oracle.force(order, eps2, ids, m, x, v, ids, x, v, aj=a, ai=a, **kw)
+
+
+# --------------------------------------------------------------------------------------------
+# Two-body circular orbit: an exact solution of the softened two-body problem.  With separation
+# d and softening eps2 the separation R = sqrt(d^2 + eps2) stays constant, the relative orbit
+# r(t) = d (cos wt, sin wt, 0) has w^2 = M / R^3, and particle 1 sits at -(m2/M) r(t).  Its
+# acceleration, jerk and snap are the 2nd, 3rd and 4th time derivatives of that position.
+# --------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("eps2", [0.0, 1e-2, 0.3])
+@pytest.mark.parametrize("m1,m2", [(0.5, 0.5), (0.9, 0.1), (1e-3, 2.0)])
+def test_circular_binary_kinematics(eps2, m1, m2):
+    d, M = 0.7, m1 + m2
+    R = math.sqrt(d * d + eps2)
+    w = math.sqrt(M / R**3)
+    th = 0.37  # arbitrary phase
+
+    def r_deriv(k):  # k-th time derivative of r(t) = d (cos wt, sin wt, 0) at phase th
+        c, s = math.cos(th + k * math.pi / 2), math.sin(th + k * math.pi / 2)
+        return d * w**k * np.array([c, s, 0.0])
+
+    x = np.array([-(m2 / M) * r_deriv(0), (m1 / M) * r_deriv(0)])
+    v = np.array([-(m2 / M) * r_deriv(1), (m1 / M) * r_deriv(1)])
+    acc_true = np.array([-(m2 / M) * r_deriv(2), (m1 / M) * r_deriv(2)])
+    jerk_true = np.array([-(m2 / M) * r_deriv(3), (m1 / M) * r_deriv(3)])
+    snap_true = np.array([-(m2 / M) * r_deriv(4), (m1 / M) * r_deriv(4)])
+    m = np.array([m1, m2])
+    out = _all_pairs(6, eps2, m, x, v, a=acc_true)
+    scale = np.abs(acc_true).max()
+    np.testing.assert_allclose(out["acc"], acc_true, rtol=0, atol=1e-14 * scale)
+    np.testing.assert_allclose(out["jerk"], jerk_true, rtol=0, atol=1e-14 * scale * w)
+    np.testing.assert_allclose(out["snap"], snap_true, rtol=0, atol=1e-14 * scale * w * w)
+    np.testing.assert_allclose(out["pot"], [-m2 / R, -m1 / R], rtol=1e-15)
+    assert list(out["nn_id"]) == [1, 0]
+    np.testing.assert_allclose(out["nn_r2"], [d * d, d * d], rtol=1e-15)
+    out4 = _all_pairs(4, eps2, m, x, v)
+    np.testing.assert_array_equal(out4["acc"], out["acc"])
+    np.testing.assert_array_equal(out4["jerk"], out["jerk"])
+
+
+# --------------------------------------------------------------------------------------------
+# Newton's third law: the pair terms are antisymmetric, so the mass-weighted sums of acc, jerk
+# and snap over a closed system vanish; the potential energy is symmetric.
+# --------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("order", [4, 6])
+def test_newton_third_law(order):
+    src = nbody_ics.make_sources(96, seed=11, order=6, masses="salpeter")
+    a = src.a
+    out = _all_pairs(order, 1e-4, src.m, src.x, src.v, a=a if order == 6 else None)
+    for key in ["acc", "jerk"] + (["snap"] if order == 6 else []):
+        q = out[key]
+        total = np.sum(src.m[:, None] * q, axis=0)
+        scale = np.sum(src.m[:, None] * np.abs(q))
+        assert np.all(np.abs(total) <= 1e-14 * scale), (key, total, scale)
+
+
+def test_potential_energy_pair_symmetry():
+    src = nbody_ics.make_sources(64, seed=12)
+    out = _all_pairs(4, 1e-3, src.m, src.x, src.v)
+    # W counted once per pair from row sums must equal the same from column order (reverse ids).
+    rev = np.arange(63, -1, -1)
+    out_r = _all_pairs(4, 1e-3, src.m[rev], src.x[rev], src.v[rev])
+    w1 = 0.5 * np.sum(src.m * out["pot"])
+    w2 = 0.5 * np.sum(src.m[rev] * out_r["pot"])
+    assert abs(w1 - w2) <= 1e-15 * abs(w1)
+
+
+# --------------------------------------------------------------------------------------------
+# The acceleration is minus the gradient of the potential at the sink position.  A foreign sink
+# (id not among the sources) is moved along each axis; central differences with Richardson
+# extrapolation give the gradient to ~h^4.
+# --------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("eps2", [1e-3, 0.05])
+def test_acceleration_is_minus_grad_potential(eps2):
+    src = nbody_ics.make_sources(40, seed=13, masses="salpeter")
+    rng = np.random.default_rng(5)
+    y = rng.normal(0, 0.4, size=(5, 3))
+    vy = np.zeros_like(y)
+    ids = np.arange(1000, 1005, dtype=np.int64)
+    base = oracle.force(4, eps2, src.ids, src.m, src.x, src.v, ids, y, vy)
+    h = 1e-3
+    grad = np.zeros_like(y)
+    for k in range(3):
+        def pot_at(s):
+            yy = y.copy()
+            yy[:, k] += s
+            return oracle.force(4, eps2, src.ids, src.m, src.x, src.v, ids, yy, vy)["pot"]
+        grad[:, k] = (-pot_at(2 * h) + 8 * pot_at(h) - 8 * pot_at(-h) + pot_at(-2 * h)) / (12 * h)
+    np.testing.assert_allclose(base["acc"], -grad, rtol=0, atol=2e-8 * np.abs(base["acc"]).max())
+
+
+# --------------------------------------------------------------------------------------------
+# Jerk is the time derivative of the acceleration when every particle moves on x + v t; snap is
+# the derivative of the jerk when every particle moves on x + v t + a t^2/2 with velocity v + a t.
+# --------------------------------------------------------------------------------------------
+def _fd(f, h):
+    return (-f(2 * h) + 8 * f(h) - 8 * f(-h) + f(-2 * h)) / (12 * h)
+
+
+@pytest.mark.parametrize("eps2", [1e-2, 1e-1])
+def test_jerk_is_time_derivative_of_acc(eps2):
+    src = nbody_ics.make_sources(24, seed=14, masses="salpeter")
+    out = _all_pairs(4, eps2, src.m, src.x, src.v)
+    fd = _fd(lambda s: _all_pairs(4, eps2, src.m, src.x + src.v * s, src.v)["acc"], 4e-4)
+    np.testing.assert_allclose(out["jerk"], fd, rtol=0, atol=1e-7 * np.abs(out["jerk"]).max())
+
+
+@pytest.mark.parametrize("eps2", [1e-2, 1e-1])
+def test_snap_is_time_derivative_of_jerk(eps2):
+    src = nbody_ics.make_sources(24, seed=15, order=6, masses="salpeter")
+    a = src.a
+    out = _all_pairs(6, eps2, src.m, src.x, src.v, a=a)
+
+    def jerk_at(s):
+        return _all_pairs(6, eps2, src.m, src.x + src.v * s + 0.5 * a * s * s, src.v + a * s, a=a)["jerk"]
+
+    fd = _fd(jerk_at, 4e-4)
+    np.testing.assert_allclose(out["snap"], fd, rtol=0, atol=1e-7 * np.abs(out["snap"]).max())
+
+
+# --------------------------------------------------------------------------------------------
+# The Taylor predictor is exact for motion that is a polynomial of the predictor's degree
+# (cubic for 4th order, quintic for 6th) and is the identity at dt = 0.
+# --------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("order,deg", [(4, 3), (6, 5)])
+def test_predictor_exact_on_polynomials(order, deg):
+    rng = np.random.default_rng(6)
+    n = 50
+    c = rng.normal(0, 1, size=(deg + 1, n, 3))  # x(t) = sum_k c_k (t - tj)^k
+    tj = rng.uniform(-1, 0, size=n)
+    t = 0.25
+    fact = [math.factorial(k) for k in range(6)]
+    derivs = [c[k] * fact[k] if k <= deg else np.zeros((n, 3)) for k in range(6)]
+    xp, vp, ap = oracle.predict(order, t, tj, derivs[0], derivs[1], derivs[2], derivs[3], derivs[4], derivs[5])
+    dt = (t - tj)[:, None]
+    x_true = sum(np.polynomial.polynomial.polyval(0, [0]) + c[k] * dt**k for k in range(deg + 1))
+    v_true = sum(k * c[k] * dt ** (k - 1) for k in range(1, deg + 1))
+    a_true = sum(k * (k - 1) * c[k] * dt ** (k - 2) for k in range(2, deg + 1))
+    np.testing.assert_allclose(xp, x_true, rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(vp, v_true, rtol=1e-13, atol=1e-13)
+    if order == 6:
+        np.testing.assert_allclose(ap, a_true, rtol=1e-13, atol=1e-13)
+    # identity at t = tj
+    xp0, vp0, ap0 = oracle.predict(order, 0.0, np.zeros(n), *derivs)
+    np.testing.assert_array_equal(xp0, derivs[0])
+    np.testing.assert_array_equal(vp0, derivs[1])
+    if order == 6:
+        np.testing.assert_array_equal(ap0, derivs[2])
+
+
+# --------------------------------------------------------------------------------------------
+# Nearest neighbour and neighbour lists against scipy's brute-force distance matrix.
+# --------------------------------------------------------------------------------------------
+def test_nn_and_neighbour_lists_brute_force():
+    src = nbody_ics.make_sources(300, seed=16)
+    ids = src.ids * 7 + 3  # ids are not addresses
+    h2 = np.full(300, 0.04)
+    out = _all_pairs(4, 1e-4, src.m, src.x, src.v, ids=ids, h2=h2, nbr_max=300)
+    d2 = cdist(src.x, src.x, "sqeuclidean")
+    np.fill_diagonal(d2, np.inf)
+    nn = np.argmin(d2, axis=1)
+    np.testing.assert_array_equal(out["nn_id"], ids[nn])
+    np.testing.assert_allclose(out["nn_r2"], d2[np.arange(300), nn], rtol=1e-14)
+    for i in range(300):
+        expect = set(ids[np.nonzero(d2[i] < h2[i])[0]])
+        assert out["nbr_count"][i] == len(expect)
+        assert set(out["nbr_ids"][i, : out["nbr_count"][i]]) == expect
+
+
+def test_nn_ties_none_and_overflow():
+    # sink at the origin, equidistant sources at +-x: the lower address wins the tie
+    x = np.array([[0.0, 0, 0], [0.5, 0, 0], [-0.5, 0, 0], [0, 0, 2.0]])
+    v = np.zeros_like(x)
+    m = np.full(4, 0.25)
+    ids = np.array([10, 20, 30, 40], dtype=np.int64)
+    out = oracle.force(4, 0.0, ids, m, x, v, ids[:1], x[:1], v[:1], h2=[1.0], nbr_max=1)
+    assert out["nn_id"][0] == 20 and out["nn_r2"][0] == 0.25
+    assert out["nbr_count"][0] == 2 and out["nbr_ids"][0, 0] == 20  # exact count, first stored
+    # a lone particle has no neighbour
+    one = oracle.force(4, 0.0, ids[:1], m[:1], x[:1], v[:1], ids[:1], x[:1], v[:1])
+    assert one["nn_id"][0] == -1 and np.isinf(one["nn_r2"][0])
+    np.testing.assert_array_equal(one["acc"], 0.0)
+    assert one["pot"][0] == 0.0
+
+
+def test_self_excluded_by_id_not_by_position():
+    # a sink whose id matches a source is not attracted by it even at another position;
+    # a different id at the same position as a source is attracted (softened).
+    xj = np.array([[0.0, 0, 0], [1.0, 0, 0]])
+    vj = np.zeros_like(xj)
+    mj = np.array([1.0, 2.0])
+    idj = np.array([0, 1], dtype=np.int64)
+    xi = np.array([[0.5, 0, 0], [0.0, 0, 0]])
+    vi = np.zeros_like(xi)
+    idi = np.array([0, 99], dtype=np.int64)
+    eps2 = 0.01
+    out = oracle.force(4, eps2, idj, mj, xj, vj, idi, xi, vi)
+    R0 = math.sqrt(0.25 + eps2)
+    np.testing.assert_allclose(out["acc"][0], [2.0 * 0.5 / R0**3, 0, 0], rtol=1e-15)
+    np.testing.assert_allclose(out["pot"][0], -2.0 / R0, rtol=1e-15)
+    R1 = math.sqrt(1.0 + eps2)
+    np.testing.assert_allclose(out["acc"][1], [2.0 / R1**3, 0, 0], rtol=1e-15)
+    np.testing.assert_allclose(out["pot"][1], -1.0 / math.sqrt(eps2) - 2.0 / R1, rtol=1e-15)
+
+
+# --------------------------------------------------------------------------------------------
+# Plummer model in standard units: total energy -1/4 and virial ratio K/|W| = 1/2 (sampling
+# noise ~ N^-1/2).  Pins the normalisation and sign of the potential.
+# --------------------------------------------------------------------------------------------
+def test_plummer_energy_and_virial_ratio():
+    n = 4096
+    m, x, v = nbody_ics.plummer(n, seed=1)
+    ids = np.arange(n, dtype=np.int64)
+    out = oracle.force(4, 0.0, ids, m, x, v, ids, x, v)
+    K = 0.5 * np.sum(m * np.sum(v * v, axis=1))
+    W = 0.5 * np.sum(m * out["pot"])
+    assert abs((K + W) + 0.25) < 0.02
+    assert abs(K / abs(W) - 0.5) < 0.03
+
+
+# --------------------------------------------------------------------------------------------
+# Hermite corrector: a circular binary integrated with the oracle's predictor, forces and the
+# 4th-order corrector follows the exact rotation, and the error falls as dt^4.
+# --------------------------------------------------------------------------------------------
+def _oracle_hermite(m, x, v, dt, nsteps, eps2):
+    n = len(m)
+    ids = np.arange(n, dtype=np.int64)
+    f = oracle.force(4, eps2, ids, m, x, v, ids, x, v)
+    a0, j0 = f["acc"], f["jerk"]
+    t = 0.0
+    for _ in range(nsteps):
+        xp, vp, _ = oracle.predict(4, t + dt, np.full(n, t), x, v, a0, j0)
+        f = oracle.force(4, eps2, ids, m, xp, vp, ids, xp, vp)
+        x, v = oracle.hermite4_correct(dt, xp, vp, a0, j0, f["acc"], f["jerk"])
+        f = oracle.force(4, eps2, ids, m, x, v, ids, x, v)
+        a0, j0 = f["acc"], f["jerk"]
+        t += dt
+    return x, v
+
+
+def test_hermite4_circular_orbit_fourth_order():
+    m = np.array([0.5, 0.5])
+    d = 1.0
+    w = 1.0  # M / d^3 = 1
+    x = np.array([[-0.5, 0, 0], [0.5, 0, 0]])
+    v = np.array([[0, -0.5 * w, 0], [0, 0.5 * w, 0]])
+    errs = []
+    T = 1.0
+    for nsteps in (16, 32, 64):
+        xe, _ = _oracle_hermite(m, x, v, T / nsteps, nsteps, 0.0)
+        exact = 0.5 * d * np.array([math.cos(w * T), math.sin(w * T), 0.0])
+        errs.append(np.abs(xe[1] - exact).max())
+    assert errs[-1] < 1e-8
+    for e1, e2 in zip(errs, errs[1:]):
+        assert 12.0 < e1 / e2 < 20.0, errs  # 2^4 = 16
+
+
+def test_hermite4_config1_energy_drift_small():
+    # 1024-body Plummer sphere, eps2 = 1e-4, 8 shared steps of dt = 1/256: energy drift is tiny.
+    src = nbody_ics.make_sources(1024, seed=1, time_offsets=False)
+    ids = src.ids
+    e0_f = oracle.force(4, 1e-4, ids, src.m, src.x, src.v, ids, src.x, src.v)
+    e0 = oracle.total_energy(src.m, src.v, e0_f["pot"])
+    x, v = _oracle_hermite(src.m, src.x, src.v, 1.0 / 256, 8, 1e-4)
+    e1 = oracle.total_energy(src.m, v, oracle.force(4, 1e-4, ids, src.m, x, v, ids, x, v)["pot"])
+    assert abs((e1 - e0) / e0) < 1e-6
+
+
+# --------------------------------------------------------------------------------------------
+# Rounding: the long-double sums make the oracle agree with a 40-digit evaluation of the same
+# definition to ~1e-15; results do not depend on the OpenMP thread count.
+# --------------------------------------------------------------------------------------------
+def test_oracle_rounding_against_high_precision():
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 40
+    src = nbody_ics.make_sources(20, seed=17, order=6, masses="salpeter")
+    eps2 = 1e-4
+    out = _all_pairs(6, eps2, src.m, src.x, src.v, a=src.a)
+    n = 20
+    for i in (0, 7, 19):
+        acc = [mpmath.mpf(0)] * 3
+        pot = mpmath.mpf(0)
+        for j in range(n):
+            if j == i:
+                continue
+            r = [mpmath.mpf(src.x[j, k]) - mpmath.mpf(src.x[i, k]) for k in range(3)]
+            R2 = sum(c * c for c in r) + mpmath.mpf(eps2)
+            acc = [acc[k] + mpmath.mpf(src.m[j]) * r[k] / R2**1.5 for k in range(3)]
+            pot -= mpmath.mpf(src.m[j]) / mpmath.sqrt(R2)
+        ref = np.array([float(c) for c in acc])
+        assert np.abs(out["acc"][i] - ref).max() <= 4e-16 * np.abs(ref).max() * 4
+        assert abs(out["pot"][i] - float(pot)) <= 4e-16 * abs(float(pot))
+
+
+def test_oracle_independent_of_thread_count():
+    src = nbody_ics.make_sources(200, seed=18, order=6)
+    r1 = _all_pairs(6, 1e-4, src.m, src.x, src.v, a=src.a, nthreads=1)
+    r4 = _all_pairs(6, 1e-4, src.m, src.x, src.v, a=src.a, nthreads=4)
+    for k in ("acc", "jerk", "snap", "pot", "nn_r2"):
+        np.testing.assert_array_equal(r1[k], r4[k])
