@@ -1,0 +1,265 @@
+"""Benchmark of the direct N-body force path on one MI355X.
+
+Workload: 131072-body equal-mass Plummer sphere (standard units), softening eps2 = 1e-6, every
+source with its own time t_j = -2^-k (k uniform in 3..10) and seeded Taylor data so the predictor
+does real work; 4th-order Hermite forces: acceleration, jerk, potential and nearest neighbour.
+
+One step = one pass of the hot path on device-resident data: copy the N_i updated sources into
+the library (copy kernel), select the prediction time, and compute forces on the N_i active sinks
+(fused predictor + gravity kernel), results left in device memory.  The headline line is the
+mixed-precision path with every sink active (N_i = N = 131072); the same run sweeps
+N_i = 1, 2, 4, ..., N in FP64 and mixed precision.
+
+Printed: one JSON line with the metric, the roofline of the gravity kernel (algorithmic flops,
+42 per 4th-order interaction, over the kernel's HIP-event time), the FP64 oracle's throughput on a
+bounded sample of host cores, and the per-N_i sweep.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N = 131072
+EPS2 = 1e-6
+FLOPS_4TH = 42  # algorithmic flops per 4th-order acc+jerk+pot interaction (FMA = 2, rsqrt = 1)
+PEAK_FP32 = 157.3  # TFLOP/s, MI355X FP32 vector
+PEAK_FP64 = 78.6  # TFLOP/s, MI355X FP64 vector
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_force_mixed_plummer131072_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1510_04068_amd", "csrc", f)
+                  for f in ("nbx_kernels.hip", "nbx_internal.h")]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic():
+    """HBM bytes per gravity launch from the committed rocprofv3 counter summary, if it was taken
+    on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-sweep", action="store_true", help="skip the N_i sweep")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target length of the oracle sample")
+    ap.add_argument("--sweep-reps", type=int, default=5)
+    return ap.parse_args()
+
+
+class Workload:
+    def __init__(self, torch, nbx, ics, dev):
+        self.torch, self.nbx = torch, nbx
+        src = ics.make_sources(N, seed=2)
+        self.src = src
+        self.ics = ics
+        import numpy as np
+
+        T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+        f64, i64, i32 = torch.float64, torch.int64, torch.int32
+        self.d = dict(addr=T(np.arange(N), i32), id=T(src.ids, i64), m=T(src.m, f64), t=T(src.t, f64),
+                      x=T(src.x, f64), v=T(src.v, f64), a=T(src.a, f64), jerk=T(src.jerk, f64))
+        self.out = dict(acc=torch.empty((N, 3), dtype=f64, device=dev), jerk=torch.empty((N, 3), dtype=f64, device=dev),
+                        pot=torch.empty(N, dtype=f64, device=dev), nn_id=torch.empty(N, dtype=i64, device=dev),
+                        nn_r2=torch.empty(N, dtype=f64, device=dev))
+        self.sets = {}
+        self.np = np
+        self.T = T
+
+    def active(self, ni):
+        """Sorted addresses of the first ni entries of the seeded permutation, plus the gathered
+        per-source inputs of those addresses (the updated sources of this block step)."""
+        if ni not in self.sets:
+            np, T, torch = self.np, self.T, self.torch
+            sel = self.ics.active_set(N, ni, seed=1002)
+            s = self.src
+            self.sets[ni] = dict(
+                addr=T(sel, torch.int32), id=T(s.ids[sel], torch.int64), m=T(s.m[sel], torch.float64),
+                t=T(s.t[sel], torch.float64), x=T(s.x[sel], torch.float64), v=T(s.v[sel], torch.float64),
+                a=T(s.a[sel], torch.float64), jerk=T(s.jerk[sel], torch.float64))
+        return self.sets[ni]
+
+
+def step(nbx, ctx, w, ni, stream, ev=None):
+    """One pass of the hot path: copy the ni updated sources, predict, forces on the ni sinks."""
+    a = w.active(ni)
+    nbx.nbx_set_j_dev(ctx.ctx, stream, ni, a["addr"], a["id"], a["m"], a["t"], a["x"], a["v"], a["a"], a["jerk"])
+    nbx.nbx_predict(ctx.ctx, 0.0)
+    if ev is not None:
+        ev[0].record(stream)
+    o = w.out
+    nbx.nbx_force_dev(ctx.ctx, stream, ni, a["addr"], EPS2, None, o["acc"], o["jerk"], None, o["pot"], o["nn_id"],
+                      o["nn_r2"])
+    if ev is not None:
+        ev[1].record(stream)
+
+
+def timed(torch, nbx, ctx, w, ni, stream, steps, warmup):
+    """Returns (seconds per step, mean force-kernel seconds per launch)."""
+    for _ in range(warmup):
+        step(nbx, ctx, w, ni, stream)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(nbx, ctx, w, ni, stream, evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern = sum(e0.elapsed_time(e1) for e0, e1 in evs) / steps * 1e-3
+    return (t1 - t0) / steps, kern
+
+
+def cpu_baseline(src, seconds):
+    """FP64 oracle (predict all sources + forces on a sample of sinks) on the host cores."""
+    import numpy as np
+
+    import oracle
+
+    oracle.build(force_rebuild=False)
+    xp, vp, _ = oracle.predict(4, 0.0, src.t, src.x, src.v, src.a, src.jerk)
+    rng = np.random.Generator(np.random.PCG64(7))
+
+    def run(ns):
+        sel = np.sort(rng.choice(N, size=ns, replace=False))
+        t0 = time.perf_counter()
+        xq, vq, _ = oracle.predict(4, 0.0, src.t, src.x, src.v, src.a, src.jerk)
+        oracle.force(4, EPS2, src.ids, src.m, xq, vq, src.ids[sel], xq[sel], vq[sel])
+        return time.perf_counter() - t0
+
+    probe = 256
+    dt = run(probe)
+    ns = int(min(N, max(probe, probe * seconds / max(dt, 1e-6))))
+    dt = run(ns)
+    return {"value": ns * N / dt, "unit": "interactions/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": "FP64 oracle, predictor on all %d sources + acc/jerk/pot/NN of %d seeded random sinks "
+                      "against all %d sources (%.2e interactions, %.1f s)" % (N, ns, N, ns * float(N), dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the source-sharded multi-GPU design is described, not "
+              "built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import nbody_ics
+    import paper_1510_04068_amd as nbx
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(3)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    w = Workload(torch, nbx, nbody_ics, dev)
+    ctx = nbx.Context(order=4, precision=nbx.NBX_MIXED, nj_max=N, ni_max=N)
+    d = w.d
+    nbx.nbx_set_j_dev(ctx.ctx, stream, N, d["addr"], d["id"], d["m"], d["t"], d["x"], d["v"], d["a"], d["jerk"])
+    nbx.nbx_set_nj(ctx.ctx, N)
+    nbx.nbx_sync(ctx.ctx, stream)
+
+    # headline: mixed precision, every sink active
+    ctx.set_precision(nbx.NBX_MIXED)
+    print("bench: mixed N_i=N warmup=%d steps=%d" % (args.warmup, args.steps), file=sys.stderr, flush=True)
+    sec, kern = timed(torch, nbx, ctx, w, N, stream, args.steps, args.warmup)
+    nbx.nbx_sync(ctx.ctx, stream)
+    inter = float(N) * N
+    value = inter / sec
+    achieved = FLOPS_4TH * inter / kern / 1e12
+    shape = ctx.launch_shape(N)
+
+    # FP64 at the same point
+    ctx.set_precision(nbx.NBX_FP64)
+    print("bench: fp64 N_i=N", file=sys.stderr, flush=True)
+    sec64, kern64 = timed(torch, nbx, ctx, w, N, stream, max(3, args.steps // 4), 1)
+
+    sweep = []
+    if not args.no_sweep:
+        for e in range(18):
+            ni = 1 << e
+            row = {"ni": ni}
+            for prec, name in ((nbx.NBX_FP64, "fp64"), (nbx.NBX_MIXED, "mixed")):
+                ctx.set_precision(prec)
+                s, k = timed(torch, nbx, ctx, w, ni, stream, args.sweep_reps, 1)
+                row[name + "_kernel_ms"] = round(k * 1e3, 5)
+                row[name + "_step_ms"] = round(s * 1e3, 5)
+                row[name + "_int_s"] = float("%.4g" % (ni * float(N) / k))
+            row["speedup"] = round(row["fp64_kernel_ms"] / row["mixed_kernel_ms"], 3)
+            sweep.append(row)
+            print("bench: sweep %s" % json.dumps(row), file=sys.stderr, flush=True)
+    nbx.nbx_sync(ctx.ctx, stream)
+    ctx.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(w.src, args.cpu_seconds)
+
+    line = {
+        "metric": "interactions/s (acc+jerk+pot) vs active N_i at N=128k, mixed vs FP64",
+        "value": value,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "Plummer sphere N=131072, eps2=1e-6, per-source times, 4th-order acc+jerk+pot+nearest "
+                        "neighbour, all sinks active (N_i=N), mixed precision (FP64 predictor, double-single "
+                        "position differences, FP32 arithmetic, compensated FP32 sums)",
+            "n_sources": N, "n_active": N, "eps2": EPS2, "order": 4, "precision": "mixed",
+            "launch_shape": shape,
+            "step": "copy N_i updated sources + predict + forces on N_i sinks, device-resident",
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP32,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32,
+            "traffic": load_traffic(),
+            "kernel": "k_force<4,mixed,P=2>",
+            "kernel_ms": kern * 1e3,
+            "flops_per_interaction": FLOPS_4TH,
+        },
+        "fp64": {
+            "value": inter / sec64,
+            "ms_per_step": sec64 * 1e3,
+            "kernel_ms": kern64 * 1e3,
+            "roofline_frac": FLOPS_4TH * inter / kern64 / 1e12 / PEAK_FP64,
+            "speedup_mixed_over_fp64": kern64 / kern,
+        },
+        "cpu_baseline": cpu,
+        "sweep": sweep,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

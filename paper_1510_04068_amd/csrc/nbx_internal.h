@@ -1,0 +1,97 @@
+// nbx_internal.h -- definitions shared by the HIP kernels and the host runtime of libnbx.
+//
+// Device layout of the source ("j-particle") state.  Sources are always stored in FP64
+// (Methods > Numerical Accuracy); the arithmetic precision is chosen per force call.
+// Records are structure-of-arrays so that one thread per source reads them with coalesced
+// 16-byte loads:
+//   pos_mass[a] = (x, y, z, m)            32 B
+//   vel_time[a] = (vx, vy, vz, t_j)       32 B
+//   acc_jrk[a]  = (ax, ay, az, jx, jy, jz) 48 B
+//   snp_crk[a]  = (sx, sy, sz, cx, cy, cz) 48 B   (order 6 only)
+//   id[a]       int64
+// The arrays hold nj_max entries; entries never written hold a massless source at
+// (1e30, 1e30, 1e30) with id -1.  The force kernel reads addresses [0, nj) and substitutes
+// the same massless far-away source for the tail [nj, nj_pad) of the last LDS tile.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nbx {
+
+constexpr int kThreads = 256;  // workgroup size: 4 wave64s
+constexpr int kTile = 256;     // sources per LDS tile (one per thread when staging)
+constexpr double kPadPos = 1e30;
+
+struct SourceArrays {
+  double4 *pos_mass;
+  double4 *vel_time;
+  double *acc_jrk;
+  double *snp_crk;
+  int64_t *id;
+};
+
+// One force launch.  Sinks are either taken by address from the predicted sources (i_addr) or
+// given explicitly (ext_*, with self-exclusion by id).
+struct ForceParams {
+  SourceArrays src;
+  int nj;      // sources in use
+  int nj_pad;  // nj rounded up to kTile
+  double t;    // prediction time
+  double eps2;
+  int ni;
+  const int32_t *i_addr;  // by-address sinks [ni]
+  const int64_t *ext_id;  // explicit sinks: id [ni], x/v/a [ni][3]
+  const double *ext_x;
+  const double *ext_v;
+  const double *ext_a;
+  const double *h2;  // [ni] squared neighbour radii, or nullptr
+  int nbr_max;
+  // launch shape
+  int lanes_log2;  // lanes per sink = 1 << lanes_log2 (1..256)
+  int splits;      // source splits S (workgroups per sink block)
+  // outputs (device)
+  double *acc;
+  double *jrk;
+  double *snp;
+  double *pot;
+  int64_t *nn_id;
+  double *nn_r2;
+  int32_t *nbr_count;
+  int64_t *nbr_ids;
+  // split-combine scratch (S > 1): part[(s*K + k)*ni + q], part_key/part_idx[s*ni + q]
+  double *part;
+  uint64_t *part_key;
+  int32_t *part_idx;
+  unsigned *counters;  // one per sink block, zero between launches
+  int *err;            // device-side error counters: [0] bad sink address, [1] bad source address
+};
+
+struct LaunchShape {
+  int lanes_log2;
+  int sinks_per_lane;
+  int splits;
+  int blocks;  // sink blocks
+};
+
+// Kernel entry points (defined in nbx_kernels.hip).
+hipError_t launch_force(int order, int precision, const ForceParams &fp, const LaunchShape &ls,
+                        hipStream_t stream);
+hipError_t launch_jupdate(int order, const SourceArrays &src, int nj_cap, int n, const int32_t *addr,
+                          const int64_t *id, const double *m, const double *t, const double *x,
+                          const double *v, const double *a, const double *jerk, const double *snap,
+                          const double *crackle, int *err, hipStream_t stream);
+hipError_t launch_pad(int order, const SourceArrays &src, int from, int to, hipStream_t stream);
+hipError_t launch_predict_out(int order, const SourceArrays &src, int nj, double t, int n,
+                              const int32_t *addr, double *xp, double *vp, double *ap, int *err,
+                              hipStream_t stream);
+hipError_t launch_gather_j(int order, const SourceArrays &src, int n, const int32_t *addr,
+                           int64_t *id, double *m, double *t, double *x, double *v, double *a,
+                           double *jerk, double *snap, double *crackle, hipStream_t stream);
+hipError_t launch_fill_i32(int32_t *p, int n, int value, hipStream_t stream);
+
+// Launch-shape rule (defined in nbx_kernels.hip).
+LaunchShape choose_shape(int ni, int nj_pad);
+int values_per_sink(int order);  // doubles per sink in the split-combine scratch
+
+}  // namespace nbx

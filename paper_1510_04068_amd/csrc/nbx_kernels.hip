@@ -1,0 +1,941 @@
+// nbx_kernels.hip -- gfx950 kernels of the direct N-body force path.
+//
+// The three GPU steps of one force evaluation are the ones the paper lists (Methods > Other
+// differences): a copy kernel that scatters updated sources into the device arrays, a
+// predictor, and the gravity kernel.  Here the predictor is fused into the gravity kernel: each
+// workgroup predicts the sources of the LDS tile it is about to use, in FP64, while staging
+// them (Background, Yebisu paragraph: prediction on the GPU), and predicts its by-address sinks
+// with the same code so that a sink and its own source copy agree bit for bit.
+//
+// Work decomposition (Methods > Parallelisation method; Results > Block-size / active-particles):
+//   * a workgroup (256 threads, four wave64s) owns a block of Q sinks and one of S contiguous
+//     source ranges ("j-split"), so that a handful of active sinks still fills the 256 CUs;
+//   * inside the workgroup each sink is handled by L lanes (L = 1..256, "2D thread-blocks")
+//     that stride over the LDS tile, and each lane may hold P = 1 or 2 sinks so that one LDS
+//     broadcast read of a source feeds P interactions;
+//   * partial sums are combined deterministically: a butterfly over the L lanes (all lanes end
+//     with bit-identical values), an LDS pass across waves when L > 64, and, when S > 1, a
+//     fixed-order sum over the S partials done by the workgroup that arrives last at a per-block
+//     counter (the paper combines source subsets with atomics inside the gravity kernel,
+//     Methods > Other differences; this keeps the single kernel but makes the order fixed).
+//
+// Arithmetic per interaction (the pair terms of nbx.h):
+//   MIXED: dx = (xh_j - xh_i) + (xl_j - xl_i) in FP32 from double-single positions, FP32
+//          velocities/masses, v_rsq_f32 with one Newton step, FP32 chunk sums folded into
+//          (hi, lo) TwoSum pairs (acceleration every 16 terms, the rest every 64).  FP32
+//          add/mul/fma issue at twice the FP64 rate on gfx950.
+//   FP64:  all IEEE double; R^-1 from v_rsq_f64 plus one third-order Newton correction; FP64
+//          chunk sums folded with TwoSum.
+// Self-interaction (by-address sinks): a sink and its own source copy are predicted by the same
+// code, so r = 0 exactly; the nearest-neighbour key (bit pattern of |r|^2 minus one) wraps to the
+// maximum.  A wave checks per tile whether the tile holds the own source of one of its sinks
+// (1-2 tiles of nj/256 when the active sinks are consecutive) and only then runs the loop variant
+// that forces R^-1 = 0 for j == self: the self pair never enters a sum, so no -m_i/eps term has
+// to be removed later, and eps2 = 0 needs no special case.
+
+#include "nbx_internal.h"
+
+#include "nbx.h"
+
+namespace nbx {
+
+constexpr int kChunkAcc = 16;  // acceleration terms summed in plain FP32/FP64 before a TwoSum fold
+constexpr int kChunk = 64;     // same for jerk, pot and snap (a multiple of kChunkAcc)
+
+// ---------------------------------------------------------------------------------------------
+// Source state and the FP64 Taylor predictor
+// ---------------------------------------------------------------------------------------------
+struct Raw {
+  double x[3], m, v[3], tj, a[3], j[3], s[3], c[3];
+};
+
+template <int Order>
+__device__ __forceinline__ void load_raw(const SourceArrays &src, int addr, Raw &r) {
+  const double4 pm = src.pos_mass[addr];
+  const double4 vt = src.vel_time[addr];
+  r.x[0] = pm.x; r.x[1] = pm.y; r.x[2] = pm.z; r.m = pm.w;
+  r.v[0] = vt.x; r.v[1] = vt.y; r.v[2] = vt.z; r.tj = vt.w;
+  const double2 *aj = reinterpret_cast<const double2 *>(src.acc_jrk + 6 * (size_t)addr);
+  const double2 q0 = aj[0], q1 = aj[1], q2 = aj[2];
+  r.a[0] = q0.x; r.a[1] = q0.y; r.a[2] = q1.x;
+  r.j[0] = q1.y; r.j[1] = q2.x; r.j[2] = q2.y;
+  if constexpr (Order == 6) {
+    const double2 *sc = reinterpret_cast<const double2 *>(src.snp_crk + 6 * (size_t)addr);
+    const double2 s0 = sc[0], s1 = sc[1], s2 = sc[2];
+    r.s[0] = s0.x; r.s[1] = s0.y; r.s[2] = s1.x;
+    r.c[0] = s1.y; r.c[1] = s2.x; r.c[2] = s2.y;
+  }
+}
+
+// Taylor polynomial about t_j in Horner form with explicit FMAs and contraction disabled, so
+// that every call site computes the same bits for the same source.
+template <int Order>
+__device__ __forceinline__ void predict_raw(const Raw &r, double t, double xp[3], double vp[3],
+                                            double ap[3]) {
+#pragma clang fp contract(off)
+  const double dt = t - r.tj;
+  const double h2 = dt * 0.5;
+  const double h3 = dt * (1.0 / 3.0);
+  if constexpr (Order == 4) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      xp[k] = fma(dt, fma(h2, fma(h3, r.j[k], r.a[k]), r.v[k]), r.x[k]);
+      vp[k] = fma(dt, fma(h2, r.j[k], r.a[k]), r.v[k]);
+      ap[k] = fma(dt, r.j[k], r.a[k]);
+    }
+  } else {
+    const double h4 = dt * 0.25;
+    const double h5 = dt * 0.2;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      xp[k] = fma(dt, fma(h2, fma(h3, fma(h4, fma(h5, r.c[k], r.s[k]), r.j[k]), r.a[k]), r.v[k]), r.x[k]);
+      vp[k] = fma(dt, fma(h2, fma(h3, fma(h4, r.c[k], r.s[k]), r.j[k]), r.a[k]), r.v[k]);
+      ap[k] = fma(dt, fma(h2, fma(h3, r.c[k], r.s[k]), r.j[k]), r.a[k]);
+    }
+  }
+}
+
+template <int Order>
+__device__ __forceinline__ void predict_addr(const SourceArrays &src, int addr, double t,
+                                             double xp[3], double vp[3], double ap[3], double &m) {
+  Raw r;
+  load_raw<Order>(src, addr, r);
+  predict_raw<Order>(r, t, xp, vp, ap);
+  m = r.m;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Compensated accumulation: K running values, each a plain chunk sum plus a (hi, lo) pair that
+// absorbs the chunk with TwoSum (Knuth).  The acceleration (values 0..2) is folded every
+// kChunkAcc terms, the other values every kChunk terms: the summation error of a chunk grows with
+// its length, and the acceleration carries the tightest bound.
+// ---------------------------------------------------------------------------------------------
+template <typename T, int K>
+struct Comp {
+  T part[K], hi[K], lo[K];
+  __device__ __forceinline__ void init() {
+#pragma unroll
+    for (int k = 0; k < K; ++k) part[k] = hi[k] = lo[k] = T(0);
+  }
+  template <int K0, int K1>
+  __device__ __forceinline__ void fold() {
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int k = K0; k < K1; ++k) {
+      const T s = hi[k] + part[k];
+      const T bp = s - hi[k];
+      const T e = (hi[k] - (s - bp)) + (part[k] - bp);
+      hi[k] = s;
+      lo[k] += e;
+      part[k] = T(0);
+    }
+  }
+};
+
+// value slots: 0..2 acc, 3..5 jerk, 6 pot, 7..9 snap
+template <int Order>
+constexpr int kValues = Order == 6 ? 10 : 7;
+
+// ---------------------------------------------------------------------------------------------
+// Precision traits: LDS tile layout, sink representation and the pair interaction
+// ---------------------------------------------------------------------------------------------
+template <int Order>
+struct MixedTile;
+template <>
+struct MixedTile<4> {  // 40 B per source
+  float4 t0[kTile];    // xh.x xh.y xh.z m
+  float4 t1[kTile];    // xl.x xl.y xl.z vx
+  float2 t2[kTile];    // vy vz
+};
+template <>
+struct MixedTile<6> {  // 52 B per source
+  float4 t0[kTile];    // xh.x xh.y xh.z m
+  float4 t1[kTile];    // xl.x xl.y xl.z vx
+  float4 t2[kTile];    // vy vz ax ay
+  float t3[kTile];     // az
+};
+
+__device__ __forceinline__ void ds_split(double x, float &hi, float &lo) {
+  hi = (float)x;
+  lo = (float)(x - (double)hi);
+}
+
+template <int Order>
+struct Mixed {
+  using Real = float;
+  using Key = uint32_t;
+  static constexpr int kK = kValues<Order>;
+  using Tile = MixedTile<Order>;
+  struct Sink {
+    float xh[3], xl[3], v[3], a[3];
+    float m;
+    int64_t id;
+  };
+  struct J {
+    float xh[3], m, xl[3], v[3], a[3];
+  };
+
+  __device__ static __forceinline__ Sink make_sink(const double xp[3], const double vp[3],
+                                                   const double ap[3], double m) {
+    Sink s;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      ds_split(xp[k], s.xh[k], s.xl[k]);
+      s.v[k] = (float)vp[k];
+      s.a[k] = (float)ap[k];
+    }
+    s.m = (float)m;
+    s.id = -1;
+    return s;
+  }
+
+  __device__ static __forceinline__ void store(Tile &tl, int e, const double xp[3], const double vp[3],
+                                               const double ap[3], double m) {
+    float xh[3], xl[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) ds_split(xp[k], xh[k], xl[k]);
+    tl.t0[e] = make_float4(xh[0], xh[1], xh[2], (float)m);
+    tl.t1[e] = make_float4(xl[0], xl[1], xl[2], (float)vp[0]);
+    if constexpr (Order == 4) {
+      tl.t2[e] = make_float2((float)vp[1], (float)vp[2]);
+    } else {
+      tl.t2[e] = make_float4((float)vp[1], (float)vp[2], (float)ap[0], (float)ap[1]);
+      tl.t3[e] = (float)ap[2];
+    }
+  }
+
+  __device__ static __forceinline__ J load(const Tile &tl, int e) {
+    J j;
+    const float4 a = tl.t0[e];
+    const float4 b = tl.t1[e];
+    j.xh[0] = a.x; j.xh[1] = a.y; j.xh[2] = a.z; j.m = a.w;
+    j.xl[0] = b.x; j.xl[1] = b.y; j.xl[2] = b.z; j.v[0] = b.w;
+    if constexpr (Order == 4) {
+      const float2 c = tl.t2[e];
+      j.v[1] = c.x; j.v[2] = c.y;
+    } else {
+      const float4 c = tl.t2[e];
+      j.v[1] = c.x; j.v[2] = c.y; j.a[0] = c.z; j.a[1] = c.w;
+      j.a[2] = tl.t3[e];
+    }
+    return j;
+  }
+
+  template <bool Guard>
+  __device__ static __forceinline__ void interact(const J &j, const Sink &s, float eps2, int jidx, int self,
+                                                  Comp<float, kValues<Order>> &A, Key &nnk, int &nni) {
+    const float dx = (j.xh[0] - s.xh[0]) + (j.xl[0] - s.xl[0]);
+    const float dy = (j.xh[1] - s.xh[1]) + (j.xl[1] - s.xl[1]);
+    const float dz = (j.xh[2] - s.xh[2]) + (j.xl[2] - s.xl[2]);
+    const float dvx = j.v[0] - s.v[0];
+    const float dvy = j.v[1] - s.v[1];
+    const float dvz = j.v[2] - s.v[2];
+    const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+    const float R2 = r2 + eps2;
+    const float rv = __builtin_fmaf(dz, dvz, __builtin_fmaf(dy, dvy, dx * dvx));
+    // v_rsq_f32 estimate plus one Newton step: y (3 - R2 y^2) / 2
+    float rinv = __builtin_amdgcn_rsqf(R2);
+    rinv = rinv * __builtin_fmaf(-0.5f * R2, rinv * rinv, 1.5f);
+    if constexpr (Guard) rinv = jidx != self ? rinv : 0.0f;
+    const float rinv2 = rinv * rinv;
+    const float mr = j.m * rinv;
+    const float mr3 = mr * rinv2;
+    const float al = rv * rinv2;
+    if constexpr (Order == 4) {
+      const float am3 = al * -3.0f;
+      const float wx = __builtin_fmaf(am3, dx, dvx);
+      const float wy = __builtin_fmaf(am3, dy, dvy);
+      const float wz = __builtin_fmaf(am3, dz, dvz);
+      A.part[0] = __builtin_fmaf(mr3, dx, A.part[0]);
+      A.part[1] = __builtin_fmaf(mr3, dy, A.part[1]);
+      A.part[2] = __builtin_fmaf(mr3, dz, A.part[2]);
+      A.part[3] = __builtin_fmaf(mr3, wx, A.part[3]);
+      A.part[4] = __builtin_fmaf(mr3, wy, A.part[4]);
+      A.part[5] = __builtin_fmaf(mr3, wz, A.part[5]);
+      A.part[6] -= mr;
+    } else {
+      const float dax = j.a[0] - s.a[0];
+      const float day = j.a[1] - s.a[1];
+      const float daz = j.a[2] - s.a[2];
+      const float vv = __builtin_fmaf(dvz, dvz, __builtin_fmaf(dvy, dvy, dvx * dvx));
+      const float ra = __builtin_fmaf(dz, daz, __builtin_fmaf(dy, day, dx * dax));
+      const float be = __builtin_fmaf(al, al, (vv + ra) * rinv2);
+      const float am3 = al * -3.0f;
+      const float am6 = al * -6.0f;
+      const float bm3 = be * -3.0f;
+      const float a0x = mr3 * dx, a0y = mr3 * dy, a0z = mr3 * dz;
+      const float a1x = __builtin_fmaf(am3, a0x, mr3 * dvx);
+      const float a1y = __builtin_fmaf(am3, a0y, mr3 * dvy);
+      const float a1z = __builtin_fmaf(am3, a0z, mr3 * dvz);
+      const float a2x = __builtin_fmaf(am6, a1x, __builtin_fmaf(bm3, a0x, mr3 * dax));
+      const float a2y = __builtin_fmaf(am6, a1y, __builtin_fmaf(bm3, a0y, mr3 * day));
+      const float a2z = __builtin_fmaf(am6, a1z, __builtin_fmaf(bm3, a0z, mr3 * daz));
+      A.part[0] += a0x; A.part[1] += a0y; A.part[2] += a0z;
+      A.part[3] += a1x; A.part[4] += a1y; A.part[5] += a1z;
+      A.part[6] -= mr;
+      A.part[7] += a2x; A.part[8] += a2y; A.part[9] += a2z;
+    }
+    const Key key = __float_as_uint(r2) - 1u;  // r2 == 0 (self) wraps to the maximum
+    if (key < nnk) {
+      nnk = key;
+      nni = jidx;
+    }
+  }
+};
+
+template <int Order>
+struct F64Tile;
+template <>
+struct F64Tile<4> {  // 56 B per source
+  double2 t0[kTile];  // x y
+  double2 t1[kTile];  // z m
+  double2 t2[kTile];  // vx vy
+  double t3[kTile];   // vz
+};
+template <>
+struct F64Tile<6> {  // 80 B per source
+  double2 t0[kTile];  // x y
+  double2 t1[kTile];  // z m
+  double2 t2[kTile];  // vx vy
+  double2 t3[kTile];  // vz ax
+  double2 t4[kTile];  // ay az
+};
+
+// R^-1 in FP64: v_rsq_f64 estimate y, e = 1 - x y^2, y (1 + e/2 + 3e^2/8) (third-order Newton).
+__device__ __forceinline__ double rsqrt64(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double xy = x * y;
+  const double e = fma(-xy, y, 1.0);
+  const double c = fma(e, 0.375, 0.5);
+  return fma(y * e, c, y);
+}
+
+template <int Order>
+struct F64 {
+  using Real = double;
+  using Key = uint64_t;
+  static constexpr int kK = kValues<Order>;
+  using Tile = F64Tile<Order>;
+  struct Sink {
+    double x[3], v[3], a[3];
+    double m;
+    int64_t id;
+  };
+  struct J {
+    double x[3], m, v[3], a[3];
+  };
+
+  __device__ static __forceinline__ Sink make_sink(const double xp[3], const double vp[3],
+                                                   const double ap[3], double m) {
+    Sink s;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      s.x[k] = xp[k];
+      s.v[k] = vp[k];
+      s.a[k] = ap[k];
+    }
+    s.m = m;
+    s.id = -1;
+    return s;
+  }
+
+  __device__ static __forceinline__ void store(Tile &tl, int e, const double xp[3], const double vp[3],
+                                               const double ap[3], double m) {
+    tl.t0[e] = make_double2(xp[0], xp[1]);
+    tl.t1[e] = make_double2(xp[2], m);
+    tl.t2[e] = make_double2(vp[0], vp[1]);
+    if constexpr (Order == 4) {
+      tl.t3[e] = vp[2];
+    } else {
+      tl.t3[e] = make_double2(vp[2], ap[0]);
+      tl.t4[e] = make_double2(ap[1], ap[2]);
+    }
+  }
+
+  __device__ static __forceinline__ J load(const Tile &tl, int e) {
+    J j;
+    const double2 a = tl.t0[e];
+    const double2 b = tl.t1[e];
+    const double2 c = tl.t2[e];
+    j.x[0] = a.x; j.x[1] = a.y; j.x[2] = b.x; j.m = b.y;
+    j.v[0] = c.x; j.v[1] = c.y;
+    if constexpr (Order == 4) {
+      j.v[2] = tl.t3[e];
+    } else {
+      const double2 d = tl.t3[e];
+      const double2 f = tl.t4[e];
+      j.v[2] = d.x; j.a[0] = d.y; j.a[1] = f.x; j.a[2] = f.y;
+    }
+    return j;
+  }
+
+  template <bool Guard>
+  __device__ static __forceinline__ void interact(const J &j, const Sink &s, double eps2, int jidx, int self,
+                                                  Comp<double, kValues<Order>> &A, Key &nnk, int &nni) {
+    const double dx = j.x[0] - s.x[0];
+    const double dy = j.x[1] - s.x[1];
+    const double dz = j.x[2] - s.x[2];
+    const double dvx = j.v[0] - s.v[0];
+    const double dvy = j.v[1] - s.v[1];
+    const double dvz = j.v[2] - s.v[2];
+    const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    const double R2 = r2 + eps2;
+    const double rv = fma(dz, dvz, fma(dy, dvy, dx * dvx));
+    double rinv = rsqrt64(R2);
+    if constexpr (Guard) rinv = jidx != self ? rinv : 0.0;
+    const double rinv2 = rinv * rinv;
+    const double mr = j.m * rinv;
+    const double mr3 = mr * rinv2;
+    const double al = rv * rinv2;
+    if constexpr (Order == 4) {
+      const double am3 = al * -3.0;
+      const double wx = fma(am3, dx, dvx);
+      const double wy = fma(am3, dy, dvy);
+      const double wz = fma(am3, dz, dvz);
+      A.part[0] = fma(mr3, dx, A.part[0]);
+      A.part[1] = fma(mr3, dy, A.part[1]);
+      A.part[2] = fma(mr3, dz, A.part[2]);
+      A.part[3] = fma(mr3, wx, A.part[3]);
+      A.part[4] = fma(mr3, wy, A.part[4]);
+      A.part[5] = fma(mr3, wz, A.part[5]);
+      A.part[6] -= mr;
+    } else {
+      const double dax = j.a[0] - s.a[0];
+      const double day = j.a[1] - s.a[1];
+      const double daz = j.a[2] - s.a[2];
+      const double vv = fma(dvz, dvz, fma(dvy, dvy, dvx * dvx));
+      const double ra = fma(dz, daz, fma(dy, day, dx * dax));
+      const double be = fma(al, al, (vv + ra) * rinv2);
+      const double am3 = al * -3.0;
+      const double am6 = al * -6.0;
+      const double bm3 = be * -3.0;
+      const double a0x = mr3 * dx, a0y = mr3 * dy, a0z = mr3 * dz;
+      const double a1x = fma(am3, a0x, mr3 * dvx);
+      const double a1y = fma(am3, a0y, mr3 * dvy);
+      const double a1z = fma(am3, a0z, mr3 * dvz);
+      const double a2x = fma(am6, a1x, fma(bm3, a0x, mr3 * dax));
+      const double a2y = fma(am6, a1y, fma(bm3, a0y, mr3 * day));
+      const double a2z = fma(am6, a1z, fma(bm3, a0z, mr3 * daz));
+      A.part[0] += a0x; A.part[1] += a0y; A.part[2] += a0z;
+      A.part[3] += a1x; A.part[4] += a1y; A.part[5] += a1z;
+      A.part[6] -= mr;
+      A.part[7] += a2x; A.part[8] += a2y; A.part[9] += a2z;
+    }
+    const Key key = (Key)__double_as_longlong(r2) - 1ull;
+    if (key < nnk) {
+      nnk = key;
+      nni = jidx;
+    }
+  }
+};
+
+template <int Order, int Prec>
+struct TraitsSel;
+template <int Order>
+struct TraitsSel<Order, NBX_MIXED> {
+  using type = Mixed<Order>;
+};
+template <int Order>
+struct TraitsSel<Order, NBX_FP64> {
+  using type = F64<Order>;
+};
+
+// ---------------------------------------------------------------------------------------------
+// Deterministic reduction over contiguous groups of `gs` threads (power of two, <= 256):
+// butterfly inside each wave (every lane ends with the same bits), then, for groups spanning
+// several waves, a sum in wave order through LDS.  Must be called by the whole workgroup.
+// NN candidates combine lexicographically on (key, index) with index compared unsigned.
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ bool nn_better(uint64_t k1, int i1, uint64_t k2, int i2) {
+  return k1 < k2 || (k1 == k2 && (unsigned)i1 < (unsigned)i2);
+}
+
+template <int P, int K>
+struct RedLds {
+  double v[4][P][K];
+  uint64_t k[4][P];
+  int i[4][P];
+};
+
+template <int P, int K>
+__device__ __forceinline__ void group_reduce(int gs, double (&v)[P][K], uint64_t (&kk)[P], int (&ii)[P],
+                                             RedLds<P, K> &red) {
+  const int wl = gs < 64 ? gs : 64;
+  for (int off = wl >> 1; off > 0; off >>= 1) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) v[p][k] += __shfl_xor(v[p][k], off);
+      const uint64_t ok = __shfl_xor(kk[p], off);
+      const int oi = __shfl_xor(ii[p], off);
+      if (nn_better(ok, oi, kk[p], ii[p])) {
+        kk[p] = ok;
+        ii[p] = oi;
+      }
+    }
+  }
+  if (gs > 64) {
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) red.v[wave][p][k] = v[p][k];
+        red.k[wave][p] = kk[p];
+        red.i[wave][p] = ii[p];
+      }
+    }
+    __syncthreads();
+    const int wpg = gs >> 6;
+    const int w0 = (wave / wpg) * wpg;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        double s = red.v[w0][p][k];
+        for (int w = 1; w < wpg; ++w) s += red.v[w0 + w][p][k];
+        v[p][k] = s;
+      }
+      uint64_t bk = red.k[w0][p];
+      int bi = red.i[w0][p];
+      for (int w = 1; w < wpg; ++w) {
+        if (nn_better(red.k[w0 + w][p], red.i[w0 + w][p], bk, bi)) {
+          bk = red.k[w0 + w][p];
+          bi = red.i[w0 + w][p];
+        }
+      }
+      kk[p] = bk;
+      ii[p] = bi;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Final write of one sink: results, nearest neighbour id and its exact FP64 |r|^2.
+// ---------------------------------------------------------------------------------------------
+template <int Order>
+__device__ void finalize_sink(const ForceParams &fp, int q, const double *v, int idx) {
+  const int addr = fp.i_addr[q];
+  if (addr < 0 || addr >= fp.nj) {
+    atomicAdd(&fp.err[0], 1);
+    return;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    fp.acc[3 * (size_t)q + k] = v[k];
+    fp.jrk[3 * (size_t)q + k] = v[3 + k];
+    if constexpr (Order == 6) fp.snp[3 * (size_t)q + k] = v[7 + k];
+  }
+  fp.pot[q] = v[6];
+  if (idx >= 0 && idx < fp.nj) {
+    double xi[3], vi[3], ai[3], mi, xj[3], vj[3], aj[3], mj;
+    predict_addr<Order>(fp.src, addr, fp.t, xi, vi, ai, mi);
+    predict_addr<Order>(fp.src, idx, fp.t, xj, vj, aj, mj);
+    double r2;
+    {
+#pragma clang fp contract(off)
+      const double dx = xj[0] - xi[0], dy = xj[1] - xi[1], dz = xj[2] - xi[2];
+      r2 = dx * dx + dy * dy + dz * dz;
+    }
+    fp.nn_id[q] = fp.src.id[idx];
+    fp.nn_r2[q] = r2;
+  } else {
+    fp.nn_id[q] = -1;
+    fp.nn_r2[q] = __builtin_huge_val();
+  }
+}
+
+// One LDS tile against the lane's P sinks.  Guard = true is used only for tiles that hold the
+// own source of some sink of the wave: there R^-1 is forced to 0 for j == self, so the self pair
+// adds exact zeros everywhere (its |r|^2 = 0 key already wraps to the maximum).
+template <class Tr, int P, bool Guard>
+__device__ __forceinline__ void tile_compute(const typename Tr::Tile &tl, int slot, int lg, int jb,
+                                             const typename Tr::Sink (&sink)[P], const int (&self)[P],
+                                             typename Tr::Real eps2,
+                                             Comp<typename Tr::Real, Tr::kK> (&acc)[P],
+                                             typename Tr::Key (&nnk)[P], int (&nni)[P]) {
+  const int per = kTile >> lg;
+  for (int c = 0; c < per; c += kChunkAcc) {
+    const int ce = per < c + kChunkAcc ? per : c + kChunkAcc;
+#pragma unroll 2
+    for (int u = c; u < ce; ++u) {
+      const typename Tr::J j = Tr::load(tl, slot + (u << lg));
+      const int jidx = jb + (u << lg);
+#pragma unroll
+      for (int p = 0; p < P; ++p) Tr::template interact<Guard>(j, sink[p], eps2, jidx, self[p], acc[p], nnk[p], nni[p]);
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) acc[p].template fold<0, 3>();
+    if (ce == per || (ce % kChunk) == 0) {
+#pragma unroll
+      for (int p = 0; p < P; ++p) acc[p].template fold<3, Tr::kK>();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// The gravity kernel.  Grid: blocks * S workgroups; workgroup w handles sink block w / S and
+// source split w % S (split-fastest, so with S a multiple of 8 every split stays on one XCD and
+// its sources stay in that XCD's L2).
+// ---------------------------------------------------------------------------------------------
+template <int Order, int Prec, int P>
+__global__ __launch_bounds__(kThreads) void k_force(const ForceParams fp) {
+  using Tr = typename TraitsSel<Order, Prec>::type;
+  using T = typename Tr::Real;
+  using Key = typename Tr::Key;
+  constexpr int K = kValues<Order>;
+  __shared__ typename Tr::Tile tiles[2];
+  __shared__ RedLds<P, K> red;
+  __shared__ int s_last;
+
+  const int tid = threadIdx.x;
+  const int lg = fp.lanes_log2;
+  const int L = 1 << lg;
+  const int G = kThreads >> lg;
+  const int slot = tid & (L - 1);
+  const int grp = tid >> lg;
+  const int S = fp.splits;
+  const int split = blockIdx.x % S;
+  const int ib = blockIdx.x / S;
+  const int Q = G * P;
+  const int ntiles = fp.nj_pad / kTile;
+  const int t0 = (int)(((int64_t)split * ntiles) / S);
+  const int t1 = (int)(((int64_t)(split + 1) * ntiles) / S);
+
+  typename Tr::Sink sink[P];
+  Comp<T, K> acc[P];
+  Key nnk[P];
+  int nni[P];
+  int q[P];
+  int self[P];  // own source address of each sink (-1: no sink in this slot)
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    q[p] = ib * Q + p * G + grp;
+    int addr = q[p] < fp.ni ? fp.i_addr[q[p]] : -1;
+    if (addr >= fp.nj) addr = -1;  // bad addresses are reported by finalize_sink
+    self[p] = addr;
+    double xp[3], vp[3], ap[3], m;
+    predict_addr<Order>(fp.src, addr < 0 ? 0 : addr, fp.t, xp, vp, ap, m);
+    sink[p] = Tr::make_sink(xp, vp, ap, m);
+    acc[p].init();
+    nnk[p] = ~Key(0);
+    nni[p] = -1;
+  }
+  const T eps2 = (T)fp.eps2;
+
+  // Tile staging with the fused predictor.  Addresses >= nj (the tail of the last tile) get a
+  // padding source: massless, at rest, at (1e30, 1e30, 1e30); all its terms are exact zeros in
+  // both precisions and its address marks "no neighbour".
+  auto stage = [&](int tile, int buf) {
+    const int jj = tile * kTile + tid;
+    double xp[3], vp[3], ap[3], m;
+    if (jj < fp.nj) {
+      predict_addr<Order>(fp.src, jj, fp.t, xp, vp, ap, m);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        xp[k] = kPadPos;
+        vp[k] = 0.0;
+        ap[k] = 0.0;
+      }
+      m = 0.0;
+    }
+    Tr::store(tiles[buf], tid, xp, vp, ap, m);
+  };
+
+  if (t0 < t1) stage(t0, 0);
+  __syncthreads();
+  for (int tile = t0; tile < t1; ++tile) {
+    const int buf = (tile - t0) & 1;
+    bool mine = false;
+#pragma unroll
+    for (int p = 0; p < P; ++p) mine |= (self[p] >> 8) == tile;  // kTile == 256
+    if (__any(mine))
+      tile_compute<Tr, P, true>(tiles[buf], slot, lg, tile * kTile + slot, sink, self, eps2, acc, nnk, nni);
+    else
+      tile_compute<Tr, P, false>(tiles[buf], slot, lg, tile * kTile + slot, sink, self, eps2, acc, nnk, nni);
+    if (tile + 1 < t1) stage(tile + 1, buf ^ 1);
+    __syncthreads();
+  }
+
+  // lanes of a sink -> one value (identical in every lane of the group)
+  double v[P][K];
+  uint64_t kk[P];
+  int ii[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[p][k] = (double)acc[p].hi[k] + (double)acc[p].lo[k];
+    kk[p] = (uint64_t)nnk[p];
+    ii[p] = nni[p];
+  }
+  group_reduce<P, K>(L, v, kk, ii, red);
+
+  if (S == 1) {
+    if (slot == 0) {
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+        if (q[p] < fp.ni) finalize_sink<Order>(fp, q[p], v[p], ii[p]);
+    }
+    return;
+  }
+
+  // S > 1: publish this split's partials, then the last workgroup of the sink block sums the S
+  // partials of each sink in a fixed order.
+  if (slot == 0) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      if (q[p] < fp.ni) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) fp.part[((size_t)split * K + k) * fp.ni + q[p]] = v[p][k];
+        fp.part_key[(size_t)split * fp.ni + q[p]] = kk[p];
+        fp.part_idx[(size_t)split * fp.ni + q[p]] = ii[p];
+      }
+    }
+  }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) s_last = atomicAdd(&fp.counters[ib], 1u) == (unsigned)(S - 1);
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+
+  const int W = Q < kThreads ? Q : kThreads;  // sinks per pass
+  const int R = kThreads / W;                 // threads per sink
+  const int qb = ib * Q;
+  for (int pass = 0; pass < Q / W; ++pass) {
+    const int qg = qb + pass * W + tid / R;
+    const int r = tid % R;
+    double w[1][K];
+    uint64_t wk[1] = {~0ull};
+    int wi[1] = {-1};
+#pragma unroll
+    for (int k = 0; k < K; ++k) w[0][k] = 0.0;
+    if (qg < fp.ni) {
+      for (int s = r; s < S; s += R) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) w[0][k] += fp.part[((size_t)s * K + k) * fp.ni + qg];
+        const uint64_t pk = fp.part_key[(size_t)s * fp.ni + qg];
+        const int pi = fp.part_idx[(size_t)s * fp.ni + qg];
+        if (nn_better(pk, pi, wk[0], wi[0])) {
+          wk[0] = pk;
+          wi[0] = pi;
+        }
+      }
+    }
+    group_reduce<1, K>(R, w, wk, wi, *reinterpret_cast<RedLds<1, K> *>(&red));
+    if (r == 0 && qg < fp.ni) finalize_sink<Order>(fp, qg, w[0], wi[0]);
+  }
+  if (tid == 0) fp.counters[ib] = 0u;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Copy kernel: scatter n updated sources (AoS [n][3] FP64) to their addresses.
+// ---------------------------------------------------------------------------------------------
+template <int Order>
+__global__ __launch_bounds__(256) void k_jupdate(SourceArrays src, int nj_max, int n, const int32_t *addr,
+                                                 const int64_t *id, const double *m, const double *t,
+                                                 const double *x, const double *v, const double *a,
+                                                 const double *jk, const double *sn, const double *cr,
+                                                 int *err) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int ad = addr[k];
+  if (ad < 0 || ad >= nj_max) {
+    atomicAdd(&err[1], 1);
+    return;
+  }
+  const size_t b = 3 * (size_t)k;
+  src.pos_mass[ad] = make_double4(x[b], x[b + 1], x[b + 2], m[k]);
+  src.vel_time[ad] = make_double4(v[b], v[b + 1], v[b + 2], t[k]);
+  double *aj = src.acc_jrk + 6 * (size_t)ad;
+  aj[0] = a[b]; aj[1] = a[b + 1]; aj[2] = a[b + 2];
+  aj[3] = jk[b]; aj[4] = jk[b + 1]; aj[5] = jk[b + 2];
+  if constexpr (Order == 6) {
+    double *sc = src.snp_crk + 6 * (size_t)ad;
+    sc[0] = sn[b]; sc[1] = sn[b + 1]; sc[2] = sn[b + 2];
+    sc[3] = cr[b]; sc[4] = cr[b + 1]; sc[5] = cr[b + 2];
+  }
+  src.id[ad] = id[k];
+}
+
+// Padding sources for addresses [from, to): massless, at rest, far away.
+template <int Order>
+__global__ __launch_bounds__(256) void k_pad(SourceArrays src, int from, int to) {
+  const int ad = from + blockIdx.x * blockDim.x + threadIdx.x;
+  if (ad >= to) return;
+  src.pos_mass[ad] = make_double4(kPadPos, kPadPos, kPadPos, 0.0);
+  src.vel_time[ad] = make_double4(0.0, 0.0, 0.0, 0.0);
+  double *aj = src.acc_jrk + 6 * (size_t)ad;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) aj[k] = 0.0;
+  if constexpr (Order == 6) {
+    double *sc = src.snp_crk + 6 * (size_t)ad;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) sc[k] = 0.0;
+  }
+  src.id[ad] = -1;
+}
+
+// Predicted FP64 state of n sources (the force kernel's predictor, written out).
+template <int Order>
+__global__ __launch_bounds__(256) void k_predict_out(SourceArrays src, int nj, double t, int n,
+                                                     const int32_t *addr, double *xp, double *vp,
+                                                     double *ap, int *err) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int ad = addr[k];
+  if (ad < 0 || ad >= nj) {
+    atomicAdd(&err[1], 1);
+    return;
+  }
+  double x[3], v[3], a[3], m;
+  predict_addr<Order>(src, ad, t, x, v, a, m);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    xp[3 * (size_t)k + c] = x[c];
+    vp[3 * (size_t)k + c] = v[c];
+    if (ap) ap[3 * (size_t)k + c] = a[c];
+  }
+}
+
+// Read back stored (unpredicted) state; any output may be null.
+template <int Order>
+__global__ __launch_bounds__(256) void k_gather_j(SourceArrays src, int n, const int32_t *addr, int64_t *id,
+                                                  double *m, double *t, double *x, double *v, double *a,
+                                                  double *jk, double *sn, double *cr) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int ad = addr[k];
+  const double4 pm = src.pos_mass[ad];
+  const double4 vt = src.vel_time[ad];
+  const double *aj = src.acc_jrk + 6 * (size_t)ad;
+  const size_t b = 3 * (size_t)k;
+  if (id) id[k] = src.id[ad];
+  if (m) m[k] = pm.w;
+  if (t) t[k] = vt.w;
+  if (x) { x[b] = pm.x; x[b + 1] = pm.y; x[b + 2] = pm.z; }
+  if (v) { v[b] = vt.x; v[b + 1] = vt.y; v[b + 2] = vt.z; }
+  if (a) { a[b] = aj[0]; a[b + 1] = aj[1]; a[b + 2] = aj[2]; }
+  if (jk) { jk[b] = aj[3]; jk[b + 1] = aj[4]; jk[b + 2] = aj[5]; }
+  if constexpr (Order == 6) {
+    const double *sc = src.snp_crk + 6 * (size_t)ad;
+    if (sn) { sn[b] = sc[0]; sn[b + 1] = sc[1]; sn[b + 2] = sc[2]; }
+    if (cr) { cr[b] = sc[3]; cr[b + 1] = sc[4]; cr[b + 2] = sc[5]; }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fill_i32(int32_t *p, int n, int value) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = value;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Host-side launchers
+// ---------------------------------------------------------------------------------------------
+int values_per_sink(int order) { return order == 6 ? 10 : 7; }
+
+// Launch shape: sinks per workgroup Q = (256 / L) * P.  Large active sets use L = 1 and two
+// sinks per lane; small ones spread each sink over L lanes so every lane has work.  The source
+// range is then split until there are about 2048 workgroups (8 per CU), at least one tile each.
+LaunchShape choose_shape(int ni, int nj_pad) {
+  LaunchShape ls;
+  const int ntiles = nj_pad / kTile > 0 ? nj_pad / kTile : 1;
+  if (ni >= 2 * kThreads * 8) {
+    ls.lanes_log2 = 0;
+    ls.sinks_per_lane = 2;
+  } else {
+    int lg = 0;
+    while (lg < 8 && (kThreads >> (lg + 1)) >= ni) ++lg;
+    ls.lanes_log2 = lg;
+    ls.sinks_per_lane = 1;
+  }
+  const int Q = (kThreads >> ls.lanes_log2) * ls.sinks_per_lane;
+  ls.blocks = (ni + Q - 1) / Q;
+  const int target = 2048;
+  int S = (target + ls.blocks - 1) / ls.blocks;
+  if (S > ntiles) S = ntiles;
+  if (S < 1) S = 1;
+  ls.splits = S;
+  return ls;
+}
+
+template <int Order, int Prec, int P>
+static hipError_t launch_force_t(const ForceParams &fp, const LaunchShape &ls, hipStream_t stream) {
+  hipLaunchKernelGGL((k_force<Order, Prec, P>), dim3(ls.blocks * ls.splits), dim3(kThreads), 0, stream, fp);
+  return hipGetLastError();
+}
+
+template <int Order, int Prec>
+static hipError_t launch_force_op(const ForceParams &fp, const LaunchShape &ls, hipStream_t stream) {
+  if (ls.sinks_per_lane == 2) return launch_force_t<Order, Prec, 2>(fp, ls, stream);
+  return launch_force_t<Order, Prec, 1>(fp, ls, stream);
+}
+
+hipError_t launch_force(int order, int precision, const ForceParams &fp, const LaunchShape &ls,
+                        hipStream_t stream) {
+  if (order == 4)
+    return precision == NBX_MIXED ? launch_force_op<4, NBX_MIXED>(fp, ls, stream)
+                                  : launch_force_op<4, NBX_FP64>(fp, ls, stream);
+  return precision == NBX_MIXED ? launch_force_op<6, NBX_MIXED>(fp, ls, stream)
+                                : launch_force_op<6, NBX_FP64>(fp, ls, stream);
+}
+
+static inline int grid_for(int n) { return (n + 255) / 256; }
+
+hipError_t launch_jupdate(int order, const SourceArrays &src, int nj_max, int n, const int32_t *addr,
+                          const int64_t *id, const double *m, const double *t, const double *x,
+                          const double *v, const double *a, const double *jerk, const double *snap,
+                          const double *crackle, int *err, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  if (order == 4)
+    hipLaunchKernelGGL(k_jupdate<4>, dim3(grid_for(n)), dim3(256), 0, stream, src, nj_max, n, addr, id, m, t,
+                       x, v, a, jerk, snap, crackle, err);
+  else
+    hipLaunchKernelGGL(k_jupdate<6>, dim3(grid_for(n)), dim3(256), 0, stream, src, nj_max, n, addr, id, m, t,
+                       x, v, a, jerk, snap, crackle, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_pad(int order, const SourceArrays &src, int from, int to, hipStream_t stream) {
+  if (to <= from) return hipSuccess;
+  if (order == 4)
+    hipLaunchKernelGGL(k_pad<4>, dim3(grid_for(to - from)), dim3(256), 0, stream, src, from, to);
+  else
+    hipLaunchKernelGGL(k_pad<6>, dim3(grid_for(to - from)), dim3(256), 0, stream, src, from, to);
+  return hipGetLastError();
+}
+
+hipError_t launch_predict_out(int order, const SourceArrays &src, int nj, double t, int n, const int32_t *addr,
+                              double *xp, double *vp, double *ap, int *err, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  if (order == 4)
+    hipLaunchKernelGGL(k_predict_out<4>, dim3(grid_for(n)), dim3(256), 0, stream, src, nj, t, n, addr, xp, vp,
+                       ap, err);
+  else
+    hipLaunchKernelGGL(k_predict_out<6>, dim3(grid_for(n)), dim3(256), 0, stream, src, nj, t, n, addr, xp, vp,
+                       ap, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_j(int order, const SourceArrays &src, int n, const int32_t *addr, int64_t *id,
+                           double *m, double *t, double *x, double *v, double *a, double *jerk,
+                           double *snap, double *crackle, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  if (order == 4)
+    hipLaunchKernelGGL(k_gather_j<4>, dim3(grid_for(n)), dim3(256), 0, stream, src, n, addr, id, m, t, x, v, a,
+                       jerk, snap, crackle);
+  else
+    hipLaunchKernelGGL(k_gather_j<6>, dim3(grid_for(n)), dim3(256), 0, stream, src, n, addr, id, m, t, x, v, a,
+                       jerk, snap, crackle);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *p, int n, int value, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n)), dim3(256), 0, stream, p, n, value);
+  return hipGetLastError();
+}
+
+}  // namespace nbx

@@ -1,0 +1,535 @@
+// nbx_runtime.hip -- host runtime and C ABI of libnbx (declared in include/nbx.h).
+//
+// A context owns: the FP64 source arrays (Methods > Numerical Accuracy: data always stored in
+// double precision), the sink-side buffers of the host-pointer path, the split-combine scratch
+// of the gravity kernel, and one HIP stream at default priority.  Every entry point validates
+// its arguments, maps HIP failures to NBX_ERR_DEVICE with a message, and never throws.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "nbx.h"
+#include "nbx_internal.h"
+
+using namespace nbx;
+
+namespace {
+
+constexpr int kVersion = 10000;  // 1.0.0
+
+std::string g_open_error;  // message of the last failed nbx_open
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct nbx_ctx {
+  nbx_config cfg{};
+  int precision = NBX_FP64;
+  hipStream_t stream = nullptr;
+  int nj = 0;
+  bool predicted = false;
+  double t_pred = 0.0;
+  SourceArrays src{};
+  // host-pointer path: sink inputs and results
+  int32_t *d_iaddr = nullptr;
+  double *d_h2 = nullptr;
+  int64_t *d_ext_id = nullptr;
+  double *d_ext_x = nullptr, *d_ext_v = nullptr, *d_ext_a = nullptr;
+  double *d_acc = nullptr, *d_jrk = nullptr, *d_snp = nullptr, *d_pot = nullptr, *d_nnr2 = nullptr;
+  int64_t *d_nnid = nullptr;
+  int32_t *d_nbr_cnt = nullptr;
+  int64_t *d_nbr_ids = nullptr;
+  // split-combine scratch
+  DevBuf part, part_key, part_idx;
+  unsigned *counters = nullptr;
+  int *d_err = nullptr;  // [0] bad sink address, [1] bad source address, [2] nbr overflow
+  // set_j staging (host path), grown on demand
+  DevBuf up;
+  int up_cap = 0;
+  // state of the last force call (host path)
+  int last_ni = -1;
+  bool last_nbr = false;
+  std::vector<void *> owned;
+  std::string err;
+};
+
+namespace {
+
+int fail(nbx_ctx *c, int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c)
+    c->err = buf;
+  else
+    g_open_error = buf;
+  return code;
+}
+
+int hip_fail(nbx_ctx *c, hipError_t e, const char *what) {
+  return fail(c, NBX_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(c, expr)                                   \
+  do {                                                     \
+    hipError_t e_ = (expr);                                \
+    if (e_ != hipSuccess) return hip_fail((c), e_, #expr); \
+  } while (0)
+
+int alloc(nbx_ctx *c, void **p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) return NBX_OK;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(c, NBX_ERR_OOM, "hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(e));
+  }
+  c->owned.push_back(*p);
+  return NBX_OK;
+}
+
+template <typename T>
+int alloc_n(nbx_ctx *c, T **p, size_t n) {
+  return alloc(c, reinterpret_cast<void **>(p), n * sizeof(T));
+}
+
+// Grow a scratch buffer to at least `bytes` (contents are not preserved).
+int grow(nbx_ctx *c, DevBuf &b, size_t bytes) {
+  if (b.bytes >= bytes) return NBX_OK;
+  if (b.p) {
+    auto it = std::find(c->owned.begin(), c->owned.end(), b.p);
+    if (it != c->owned.end()) c->owned.erase(it);
+    hipError_t e = hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+    if (e != hipSuccess) return hip_fail(c, e, "hipFree");
+  }
+  int rc = alloc(c, &b.p, bytes);
+  if (rc == NBX_OK) b.bytes = bytes;
+  return rc;
+}
+
+int set_device(nbx_ctx *c) {
+  HIP_TRY(c, hipSetDevice(c->cfg.device));
+  return NBX_OK;
+}
+
+int ensure_scratch(nbx_ctx *c, int ni, const LaunchShape &ls) {
+  if (ls.splits <= 1) return NBX_OK;
+  const size_t K = (size_t)values_per_sink(c->cfg.order);
+  const size_t n = (size_t)ls.splits * (size_t)ni;
+  int rc = grow(c, c->part, n * K * sizeof(double));
+  if (rc) return rc;
+  rc = grow(c, c->part_key, n * sizeof(uint64_t));
+  if (rc) return rc;
+  return grow(c, c->part_idx, n * sizeof(int32_t));
+}
+
+bool valid_prec(int p) { return p == NBX_FP64 || p == NBX_MIXED; }
+
+int check_ctx(nbx_ctx *c) {
+  if (!c) return NBX_ERR_ARG;
+  c->err.clear();
+  return set_device(c);
+}
+
+// Shared by the host and device force paths.
+int enqueue_force(nbx_ctx *c, hipStream_t stream, int ni, const int32_t *d_iaddr, const int64_t *ext_id,
+                  const double *ext_x, const double *ext_v, const double *ext_a, double eps2,
+                  const double *d_h2, double *acc, double *jrk, double *snp, double *pot, int64_t *nn_id,
+                  double *nn_r2, int32_t *nbr_cnt, int64_t *nbr_ids) {
+  if (!c->predicted) return fail(c, NBX_ERR_STATE, "nbx_force before nbx_predict");
+  if (!(eps2 >= 0.0)) return fail(c, NBX_ERR_ARG, "eps2 must be >= 0 (got %g)", eps2);
+  if (ni == 0) return NBX_OK;
+  if (ext_x) return fail(c, NBX_ERR_STATE, "explicit sinks are not supported by this build");
+  if (d_h2) return fail(c, NBX_ERR_STATE, "neighbour lists are not supported by this build");
+  const int nj_pad = (c->nj + kTile - 1) / kTile * kTile;
+  const LaunchShape ls = choose_shape(ni, nj_pad);
+  int rc = ensure_scratch(c, ni, ls);
+  if (rc) return rc;
+  ForceParams fp{};
+  fp.src = c->src;
+  fp.nj = c->nj;
+  fp.nj_pad = nj_pad;
+  fp.t = c->t_pred;
+  fp.eps2 = eps2;
+  fp.ni = ni;
+  fp.i_addr = d_iaddr;
+  fp.ext_id = ext_id;
+  fp.ext_x = ext_x;
+  fp.ext_v = ext_v;
+  fp.ext_a = ext_a;
+  fp.h2 = d_h2;
+  fp.nbr_max = c->cfg.nbr_max;
+  fp.lanes_log2 = ls.lanes_log2;
+  fp.splits = ls.splits;
+  fp.acc = acc;
+  fp.jrk = jrk;
+  fp.snp = snp;
+  fp.pot = pot;
+  fp.nn_id = nn_id;
+  fp.nn_r2 = nn_r2;
+  fp.nbr_count = nbr_cnt;
+  fp.nbr_ids = nbr_ids;
+  fp.part = static_cast<double *>(c->part.p);
+  fp.part_key = static_cast<uint64_t *>(c->part_key.p);
+  fp.part_idx = static_cast<int32_t *>(c->part_idx.p);
+  fp.counters = c->counters;
+  fp.err = c->d_err;
+  hipError_t e = launch_force(c->cfg.order, c->precision, fp, ls, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "force kernel launch");
+  return NBX_OK;
+}
+
+// Read and clear the device error counters (stream must be idle).
+int collect_errors(nbx_ctx *c) {
+  int h[4] = {0, 0, 0, 0};
+  HIP_TRY(c, hipMemcpy(h, c->d_err, sizeof h, hipMemcpyDeviceToHost));
+  if (h[0] || h[1] || h[2]) {
+    HIP_TRY(c, launch_fill_i32(c->d_err, 4, 0, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
+  if (h[0]) return fail(c, NBX_ERR_ARG, "%d sink address(es) outside [0, nj) were skipped", h[0]);
+  if (h[1]) return fail(c, NBX_ERR_ARG, "%d source address(es) out of range were skipped", h[1]);
+  if (h[2]) return NBX_WARN_NBR_OVERFLOW;
+  return NBX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nbx_version(void) { return kVersion; }
+
+int nbx_device_count(int *count) {
+  if (!count) return NBX_ERR_ARG;
+  *count = 0;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n <= 0) {
+    (void)hipGetLastError();
+    return NBX_ERR_NO_DEVICE;
+  }
+  *count = n;
+  return NBX_OK;
+}
+
+int nbx_open(nbx_ctx **out, const nbx_config *cfg) {
+  if (!out) return fail(nullptr, NBX_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!cfg) return fail(nullptr, NBX_ERR_ARG, "cfg is NULL");
+  if (cfg->order != 4 && cfg->order != 6) return fail(nullptr, NBX_ERR_ARG, "order must be 4 or 6");
+  if (!valid_prec(cfg->precision)) return fail(nullptr, NBX_ERR_ARG, "precision must be NBX_FP64 or NBX_MIXED");
+  if (cfg->nj_max < 1 || cfg->ni_max < 1 || cfg->nbr_max < 0)
+    return fail(nullptr, NBX_ERR_ARG, "nj_max and ni_max must be >= 1, nbr_max >= 0");
+  int ndev = 0;
+  if (nbx_device_count(&ndev) != NBX_OK) return fail(nullptr, NBX_ERR_NO_DEVICE, "no HIP device available");
+  if (cfg->device < 0 || cfg->device >= ndev)
+    return fail(nullptr, NBX_ERR_NO_DEVICE, "device %d does not exist (%d visible)", cfg->device, ndev);
+
+  nbx_ctx *c = new (std::nothrow) nbx_ctx;
+  if (!c) return fail(nullptr, NBX_ERR_OOM, "host allocation failed");
+  c->cfg = *cfg;
+  c->precision = cfg->precision;
+  auto bail = [&](int rc) {
+    g_open_error = c->err;
+    nbx_close(c);
+    return rc;
+  };
+  if (int rc = set_device(c)) return bail(rc);
+  {
+    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return bail(hip_fail(c, e, "hipStreamCreate"));
+  }
+  const size_t nj = (size_t)cfg->nj_max, ni = (size_t)cfg->ni_max;
+  int rc = NBX_OK;
+  rc = rc ? rc : alloc_n(c, &c->src.pos_mass, nj);
+  rc = rc ? rc : alloc_n(c, &c->src.vel_time, nj);
+  rc = rc ? rc : alloc_n(c, &c->src.acc_jrk, 6 * nj);
+  if (cfg->order == 6) rc = rc ? rc : alloc_n(c, &c->src.snp_crk, 6 * nj);
+  rc = rc ? rc : alloc_n(c, &c->src.id, nj);
+  rc = rc ? rc : alloc_n(c, &c->d_iaddr, ni);
+  rc = rc ? rc : alloc_n(c, &c->d_acc, 3 * ni);
+  rc = rc ? rc : alloc_n(c, &c->d_jrk, 3 * ni);
+  if (cfg->order == 6) rc = rc ? rc : alloc_n(c, &c->d_snp, 3 * ni);
+  rc = rc ? rc : alloc_n(c, &c->d_pot, ni);
+  rc = rc ? rc : alloc_n(c, &c->d_nnid, ni);
+  rc = rc ? rc : alloc_n(c, &c->d_nnr2, ni);
+  rc = rc ? rc : alloc_n(c, &c->counters, ni + 1);
+  rc = rc ? rc : alloc_n(c, &c->d_err, 4);
+  if (rc) return bail(rc);
+  hipError_t e = launch_pad(cfg->order, c->src, 0, cfg->nj_max, c->stream);
+  if (e == hipSuccess) e = launch_fill_i32(reinterpret_cast<int32_t *>(c->counters), (int)ni + 1, 0, c->stream);
+  if (e == hipSuccess) e = launch_fill_i32(c->d_err, 4, 0, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return bail(hip_fail(c, e, "context initialisation"));
+  *out = c;
+  return NBX_OK;
+}
+
+int nbx_close(nbx_ctx *c) {
+  if (!c) return NBX_OK;
+  (void)hipSetDevice(c->cfg.device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (void *p : c->owned) (void)hipFree(p);
+  if (c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  return NBX_OK;
+}
+
+const char *nbx_last_error(const nbx_ctx *c) { return c ? c->err.c_str() : g_open_error.c_str(); }
+
+int nbx_set_precision(nbx_ctx *c, int precision) {
+  if (!c) return NBX_ERR_ARG;
+  c->err.clear();
+  if (!valid_prec(precision)) return fail(c, NBX_ERR_ARG, "precision must be NBX_FP64 or NBX_MIXED");
+  c->precision = precision;
+  return NBX_OK;
+}
+
+int nbx_set_nj(nbx_ctx *c, int nj) {
+  if (!c) return NBX_ERR_ARG;
+  c->err.clear();
+  if (nj < 0 || nj > c->cfg.nj_max) return fail(c, NBX_ERR_CAPACITY, "nj=%d outside [0, %d]", nj, c->cfg.nj_max);
+  c->nj = nj;
+  return NBX_OK;
+}
+
+int nbx_set_j(nbx_ctx *c, int n, const int32_t *addr, const int64_t *id, const double *m, const double *t,
+              const double *x, const double *v, const double *a, const double *jerk, const double *snap,
+              const double *crackle) {
+  if (int rc = check_ctx(c)) return rc;
+  if (n < 0) return fail(c, NBX_ERR_ARG, "n < 0");
+  if (n == 0) return NBX_OK;
+  if (n > c->cfg.nj_max) return fail(c, NBX_ERR_CAPACITY, "n=%d > nj_max=%d", n, c->cfg.nj_max);
+  if (!addr || !id || !m || !t || !x || !v || !a || !jerk) return fail(c, NBX_ERR_ARG, "NULL input array");
+  const bool six = c->cfg.order == 6;
+  if (six && (!snap || !crackle)) return fail(c, NBX_ERR_ARG, "order 6 needs snap and crackle");
+  int hi = -1;
+  for (int k = 0; k < n; ++k) {
+    if (addr[k] < 0 || addr[k] >= c->cfg.nj_max)
+      return fail(c, NBX_ERR_ARG, "addr[%d]=%d outside [0, %d)", k, addr[k], c->cfg.nj_max);
+    hi = std::max(hi, addr[k]);
+  }
+  // staging layout: addr | id | m | t | x v a jerk [snap crackle]
+  const size_t nv = six ? 6 : 4;
+  const size_t bytes = (size_t)n * (4 + 8 + 8 + 8 + nv * 24) + 256;
+  if (int rc = grow(c, c->up, bytes)) return rc;
+  char *base = static_cast<char *>(c->up.p);
+  int32_t *d_addr = reinterpret_cast<int32_t *>(base);
+  size_t off = ((size_t)n * 4 + 15) / 16 * 16;
+  int64_t *d_id = reinterpret_cast<int64_t *>(base + off);
+  off += (size_t)n * 8;
+  double *d_m = reinterpret_cast<double *>(base + off);
+  off += (size_t)n * 8;
+  double *d_t = reinterpret_cast<double *>(base + off);
+  off += (size_t)n * 8;
+  double *d_vec[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  const double *h_vec[6] = {x, v, a, jerk, snap, crackle};
+  for (size_t k = 0; k < nv; ++k) {
+    d_vec[k] = reinterpret_cast<double *>(base + off);
+    off += (size_t)n * 24;
+  }
+  hipStream_t s = c->stream;
+  HIP_TRY(c, hipMemcpyAsync(d_addr, addr, (size_t)n * 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(c, hipMemcpyAsync(d_id, id, (size_t)n * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(c, hipMemcpyAsync(d_m, m, (size_t)n * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(c, hipMemcpyAsync(d_t, t, (size_t)n * 8, hipMemcpyHostToDevice, s));
+  for (size_t k = 0; k < nv; ++k)
+    HIP_TRY(c, hipMemcpyAsync(d_vec[k], h_vec[k], (size_t)n * 24, hipMemcpyHostToDevice, s));
+  HIP_TRY(c, launch_jupdate(c->cfg.order, c->src, c->cfg.nj_max, n, d_addr, d_id, d_m, d_t, d_vec[0], d_vec[1],
+                            d_vec[2], d_vec[3], d_vec[4], d_vec[5], c->d_err, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  c->nj = std::max(c->nj, hi + 1);
+  return NBX_OK;
+}
+
+int nbx_predict(nbx_ctx *c, double t) {
+  if (!c) return NBX_ERR_ARG;
+  c->err.clear();
+  c->t_pred = t;
+  c->predicted = true;
+  return NBX_OK;
+}
+
+int nbx_force(nbx_ctx *c, int ni, const int32_t *i_addr, double eps2, const double *h2) {
+  if (int rc = check_ctx(c)) return rc;
+  if (ni < 0) return fail(c, NBX_ERR_ARG, "ni < 0");
+  if (ni > c->cfg.ni_max) return fail(c, NBX_ERR_CAPACITY, "ni=%d > ni_max=%d", ni, c->cfg.ni_max);
+  if (ni > 0 && !i_addr) return fail(c, NBX_ERR_ARG, "i_addr is NULL");
+  for (int k = 0; k < ni; ++k)
+    if (i_addr[k] < 0 || i_addr[k] >= c->nj)
+      return fail(c, NBX_ERR_ARG, "i_addr[%d]=%d outside [0, nj=%d)", k, i_addr[k], c->nj);
+  if (h2 && c->cfg.nbr_max == 0) return fail(c, NBX_ERR_ARG, "neighbour lists need nbr_max > 0");
+  if (ni > 0) HIP_TRY(c, hipMemcpyAsync(c->d_iaddr, i_addr, (size_t)ni * 4, hipMemcpyHostToDevice, c->stream));
+  int rc = enqueue_force(c, c->stream, ni, c->d_iaddr, nullptr, nullptr, nullptr, nullptr, eps2, nullptr, c->d_acc,
+                         c->d_jrk, c->d_snp, c->d_pot, c->d_nnid, c->d_nnr2, nullptr, nullptr);
+  if (rc < 0) return rc;
+  c->last_ni = ni;
+  c->last_nbr = h2 != nullptr;
+  return rc;
+}
+
+int nbx_force_ext(nbx_ctx *c, int ni, const int64_t *id, const double *x, const double *v, const double *a,
+                  double eps2, const double *h2) {
+  if (int rc = check_ctx(c)) return rc;
+  (void)ni; (void)id; (void)x; (void)v; (void)a; (void)eps2; (void)h2;
+  return fail(c, NBX_ERR_STATE, "explicit sinks are not supported by this build");
+}
+
+int nbx_get_force(nbx_ctx *c, double *acc, double *jerk, double *snap, double *pot, int64_t *nn_id,
+                  double *nn_r2) {
+  if (int rc = check_ctx(c)) return rc;
+  if (c->last_ni < 0) return fail(c, NBX_ERR_STATE, "nbx_get_force before nbx_force");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const int rc = collect_errors(c);
+  if (rc < 0) return rc;
+  const size_t n = (size_t)c->last_ni;
+  if (n == 0) return rc;
+  if (acc) HIP_TRY(c, hipMemcpy(acc, c->d_acc, n * 24, hipMemcpyDeviceToHost));
+  if (jerk) HIP_TRY(c, hipMemcpy(jerk, c->d_jrk, n * 24, hipMemcpyDeviceToHost));
+  if (snap && c->cfg.order == 6) HIP_TRY(c, hipMemcpy(snap, c->d_snp, n * 24, hipMemcpyDeviceToHost));
+  if (pot) HIP_TRY(c, hipMemcpy(pot, c->d_pot, n * 8, hipMemcpyDeviceToHost));
+  if (nn_id) HIP_TRY(c, hipMemcpy(nn_id, c->d_nnid, n * 8, hipMemcpyDeviceToHost));
+  if (nn_r2) HIP_TRY(c, hipMemcpy(nn_r2, c->d_nnr2, n * 8, hipMemcpyDeviceToHost));
+  return rc;
+}
+
+int nbx_get_nbr(nbx_ctx *c, int32_t *count, int64_t *ids) {
+  if (int rc = check_ctx(c)) return rc;
+  (void)count; (void)ids;
+  return fail(c, NBX_ERR_STATE, "neighbour lists are not supported by this build");
+}
+
+int nbx_get_predicted(nbx_ctx *c, int n, const int32_t *addr, double *xp, double *vp, double *ap) {
+  if (int rc = check_ctx(c)) return rc;
+  if (n < 0) return fail(c, NBX_ERR_ARG, "n < 0");
+  if (n == 0) return NBX_OK;
+  if (!addr || !xp || !vp) return fail(c, NBX_ERR_ARG, "NULL argument");
+  if (!c->predicted) return fail(c, NBX_ERR_STATE, "nbx_get_predicted before nbx_predict");
+  for (int k = 0; k < n; ++k)
+    if (addr[k] < 0 || addr[k] >= c->nj)
+      return fail(c, NBX_ERR_ARG, "addr[%d]=%d outside [0, nj=%d)", k, addr[k], c->nj);
+  const size_t bytes = (size_t)n * (16 + 72);
+  if (int rc = grow(c, c->up, bytes)) return rc;
+  char *base = static_cast<char *>(c->up.p);
+  int32_t *d_addr = reinterpret_cast<int32_t *>(base);
+  double *d_x = reinterpret_cast<double *>(base + ((size_t)n * 4 + 15) / 16 * 16);
+  double *d_v = d_x + 3 * (size_t)n;
+  double *d_a = d_v + 3 * (size_t)n;
+  HIP_TRY(c, hipMemcpyAsync(d_addr, addr, (size_t)n * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, launch_predict_out(c->cfg.order, c->src, c->nj, c->t_pred, n, d_addr, d_x, d_v, d_a, c->d_err,
+                                c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  HIP_TRY(c, hipMemcpy(xp, d_x, (size_t)n * 24, hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(vp, d_v, (size_t)n * 24, hipMemcpyDeviceToHost));
+  if (ap) HIP_TRY(c, hipMemcpy(ap, d_a, (size_t)n * 24, hipMemcpyDeviceToHost));
+  return collect_errors(c);
+}
+
+int nbx_get_j(nbx_ctx *c, int n, const int32_t *addr, int64_t *id, double *m, double *t, double *x, double *v,
+              double *a, double *jerk, double *snap, double *crackle) {
+  if (int rc = check_ctx(c)) return rc;
+  if (n < 0) return fail(c, NBX_ERR_ARG, "n < 0");
+  if (n == 0) return NBX_OK;
+  if (!addr) return fail(c, NBX_ERR_ARG, "addr is NULL");
+  for (int k = 0; k < n; ++k)
+    if (addr[k] < 0 || addr[k] >= c->cfg.nj_max)
+      return fail(c, NBX_ERR_ARG, "addr[%d]=%d outside [0, %d)", k, addr[k], c->cfg.nj_max);
+  const bool six = c->cfg.order == 6;
+  // staging: addr | id | m | t | x v a jerk snap crackle
+  const size_t bytes = (size_t)n * (16 + 8 + 8 + 8 + 6 * 24);
+  if (int rc = grow(c, c->up, bytes)) return rc;
+  char *base = static_cast<char *>(c->up.p);
+  int32_t *d_addr = reinterpret_cast<int32_t *>(base);
+  size_t off = ((size_t)n * 4 + 15) / 16 * 16;
+  int64_t *d_id = reinterpret_cast<int64_t *>(base + off);
+  off += (size_t)n * 8;
+  double *d_m = reinterpret_cast<double *>(base + off);
+  off += (size_t)n * 8;
+  double *d_t = reinterpret_cast<double *>(base + off);
+  off += (size_t)n * 8;
+  double *d_vec[6];
+  for (int k = 0; k < 6; ++k) {
+    d_vec[k] = reinterpret_cast<double *>(base + off);
+    off += (size_t)n * 24;
+  }
+  HIP_TRY(c, hipMemcpyAsync(d_addr, addr, (size_t)n * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, launch_gather_j(c->cfg.order, c->src, n, d_addr, d_id, d_m, d_t, d_vec[0], d_vec[1], d_vec[2],
+                             d_vec[3], six ? d_vec[4] : nullptr, six ? d_vec[5] : nullptr, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  double *h_vec[6] = {x, v, a, jerk, snap, crackle};
+  if (id) HIP_TRY(c, hipMemcpy(id, d_id, (size_t)n * 8, hipMemcpyDeviceToHost));
+  if (m) HIP_TRY(c, hipMemcpy(m, d_m, (size_t)n * 8, hipMemcpyDeviceToHost));
+  if (t) HIP_TRY(c, hipMemcpy(t, d_t, (size_t)n * 8, hipMemcpyDeviceToHost));
+  for (int k = 0; k < (six ? 6 : 4); ++k)
+    if (h_vec[k]) HIP_TRY(c, hipMemcpy(h_vec[k], d_vec[k], (size_t)n * 24, hipMemcpyDeviceToHost));
+  return NBX_OK;
+}
+
+int nbx_set_j_dev(nbx_ctx *c, void *stream, int n, const int32_t *d_addr, const int64_t *d_id, const double *d_m,
+                  const double *d_t, const double *d_x, const double *d_v, const double *d_a,
+                  const double *d_jerk, const double *d_snap, const double *d_crackle) {
+  if (int rc = check_ctx(c)) return rc;
+  if (n < 0) return fail(c, NBX_ERR_ARG, "n < 0");
+  if (n == 0) return NBX_OK;
+  if (n > c->cfg.nj_max) return fail(c, NBX_ERR_CAPACITY, "n=%d > nj_max=%d", n, c->cfg.nj_max);
+  if (!d_addr || !d_id || !d_m || !d_t || !d_x || !d_v || !d_a || !d_jerk)
+    return fail(c, NBX_ERR_ARG, "NULL input array");
+  if (c->cfg.order == 6 && (!d_snap || !d_crackle)) return fail(c, NBX_ERR_ARG, "order 6 needs snap and crackle");
+  HIP_TRY(c, launch_jupdate(c->cfg.order, c->src, c->cfg.nj_max, n, d_addr, d_id, d_m, d_t, d_x, d_v, d_a, d_jerk,
+                            d_snap, d_crackle, c->d_err, static_cast<hipStream_t>(stream)));
+  return NBX_OK;
+}
+
+int nbx_force_dev(nbx_ctx *c, void *stream, int ni, const int32_t *d_i_addr, double eps2, const double *d_h2,
+                  double *d_acc, double *d_jerk, double *d_snap, double *d_pot, int64_t *d_nn_id, double *d_nn_r2,
+                  int32_t *d_nbr_count, int64_t *d_nbr_ids) {
+  if (int rc = check_ctx(c)) return rc;
+  if (ni < 0) return fail(c, NBX_ERR_ARG, "ni < 0");
+  if (ni > c->cfg.ni_max) return fail(c, NBX_ERR_CAPACITY, "ni=%d > ni_max=%d", ni, c->cfg.ni_max);
+  if (ni == 0) return NBX_OK;
+  if (!d_i_addr || !d_acc || !d_jerk || !d_pot || !d_nn_id || !d_nn_r2)
+    return fail(c, NBX_ERR_ARG, "NULL device array");
+  if (c->cfg.order == 6 && !d_snap) return fail(c, NBX_ERR_ARG, "order 6 needs d_snap");
+  if (d_h2 && (c->cfg.nbr_max == 0 || !d_nbr_count || !d_nbr_ids))
+    return fail(c, NBX_ERR_ARG, "neighbour lists need nbr_max > 0 and count/id arrays");
+  if (c->nj < 1) return fail(c, NBX_ERR_STATE, "no sources in use (nbx_set_nj)");
+  return enqueue_force(c, static_cast<hipStream_t>(stream), ni, d_i_addr, nullptr, nullptr, nullptr, nullptr, eps2,
+                       d_h2, d_acc, d_jerk, d_snap, d_pot, d_nn_id, d_nn_r2, d_nbr_count, d_nbr_ids);
+}
+
+int nbx_sync(nbx_ctx *c, void *stream) {
+  if (int rc = check_ctx(c)) return rc;
+  if (stream) HIP_TRY(c, hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  HIP_TRY(c, hipDeviceSynchronize());
+  return collect_errors(c);
+}
+
+int nbx_launch_shape(nbx_ctx *c, int ni, int *lanes_per_sink, int *sinks_per_lane, int *splits, int *workgroups) {
+  if (!c || ni < 1) return NBX_ERR_ARG;
+  const int nj_pad = (c->nj + kTile - 1) / kTile * kTile;
+  const LaunchShape ls = choose_shape(ni, nj_pad);
+  if (lanes_per_sink) *lanes_per_sink = 1 << ls.lanes_log2;
+  if (sinks_per_lane) *sinks_per_lane = ls.sinks_per_lane;
+  if (splits) *splits = ls.splits;
+  if (workgroups) *workgroups = ls.blocks * ls.splits;
+  return NBX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,355 @@
+"""ctypes binding of libnbx (include/nbx.h): same entry-point names, argument marshalling only.
+
+Every computation happens in the HIP library.  If ``libnbx.so`` has not been built, loading
+fails with a RuntimeError: there is no CPU fallback.
+
+Host-array entry points take numpy arrays; the ``*_dev`` entry points take torch device tensors
+(or raw device pointers) and a stream (``torch.cuda.Stream``, a raw hipStream_t integer, or None
+for torch's current stream).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnbx.so")
+
+NBX_OK = 0
+NBX_WARN_NBR_OVERFLOW = 1
+NBX_ERR_ARG = -1
+NBX_ERR_CAPACITY = -2
+NBX_ERR_STATE = -3
+NBX_ERR_DEVICE = -4
+NBX_ERR_NO_DEVICE = -5
+NBX_ERR_OOM = -6
+NBX_FP64 = 0
+NBX_MIXED = 1
+
+_ERR_NAMES = {
+    NBX_ERR_ARG: "NBX_ERR_ARG",
+    NBX_ERR_CAPACITY: "NBX_ERR_CAPACITY",
+    NBX_ERR_STATE: "NBX_ERR_STATE",
+    NBX_ERR_DEVICE: "NBX_ERR_DEVICE",
+    NBX_ERR_NO_DEVICE: "NBX_ERR_NO_DEVICE",
+    NBX_ERR_OOM: "NBX_ERR_OOM",
+}
+
+# Every symbol include/nbx.h declares.
+EXPORTS = (
+    "nbx_version", "nbx_device_count", "nbx_open", "nbx_close", "nbx_last_error", "nbx_set_precision",
+    "nbx_set_nj", "nbx_set_j", "nbx_predict", "nbx_force", "nbx_force_ext", "nbx_get_force", "nbx_get_nbr",
+    "nbx_get_predicted", "nbx_get_j", "nbx_set_j_dev", "nbx_force_dev", "nbx_sync", "nbx_launch_shape",
+)
+
+
+class nbx_config(ctypes.Structure):
+    _fields_ = [
+        ("device", ctypes.c_int),
+        ("order", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("nj_max", ctypes.c_int),
+        ("ni_max", ctypes.c_int),
+        ("nbr_max", ctypes.c_int),
+    ]
+
+
+class NbxError(RuntimeError):
+    def __init__(self, code, message):
+        super().__init__("%s (%d): %s" % (_ERR_NAMES.get(code, "NBX_ERR"), code, message))
+        self.code = code
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+
+
+def load(path: str = LIB_PATH):
+    """Load libnbx.so and declare the signatures of every exported function."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libnbx.so is not built (%s); run __graft_entry__.build()" % path)
+    # torch ships its own HIP runtime with the same SONAME (libamdhip64.so.7) as the one libnbx
+    # links against.  Importing torch first makes the dynamic loader bind libnbx to torch's copy,
+    # so the process has one HIP runtime and torch tensors/streams are valid in libnbx calls.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(path)
+    sig = {
+        "nbx_version": ([], _I),
+        "nbx_device_count": ([_P], _I),
+        "nbx_open": ([_P, ctypes.POINTER(nbx_config)], _I),
+        "nbx_close": ([_P], _I),
+        "nbx_last_error": ([_P], ctypes.c_char_p),
+        "nbx_set_precision": ([_P, _I], _I),
+        "nbx_set_nj": ([_P, _I], _I),
+        "nbx_set_j": ([_P, _I] + [_P] * 10, _I),
+        "nbx_predict": ([_P, _D], _I),
+        "nbx_force": ([_P, _I, _P, _D, _P], _I),
+        "nbx_force_ext": ([_P, _I, _P, _P, _P, _P, _D, _P], _I),
+        "nbx_get_force": ([_P] * 7, _I),
+        "nbx_get_nbr": ([_P, _P, _P], _I),
+        "nbx_get_predicted": ([_P, _I, _P, _P, _P, _P], _I),
+        "nbx_get_j": ([_P, _I] + [_P] * 10, _I),
+        "nbx_set_j_dev": ([_P, _P, _I] + [_P] * 10, _I),
+        "nbx_force_dev": ([_P, _P, _I, _P, _D] + [_P] * 9, _I),
+        "nbx_sync": ([_P, _P], _I),
+        "nbx_launch_shape": ([_P, _I, _P, _P, _P, _P], _I),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(ctx, rc):
+    if rc < 0:
+        msg = load().nbx_last_error(ctx)
+        raise NbxError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_P)
+
+
+def _f64(a, n=None, width=3):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if n is not None:
+        want = (n, width) if width else (n,)
+        if a.shape != want:
+            raise ValueError("expected shape %s, got %s" % (want, a.shape))
+    return a
+
+
+def _dptr(t):
+    """Device pointer of a torch tensor (or an int), None passes through."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(s):
+    if s is None:
+        import torch
+
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+# ------------------------------------------------------------------------------------------------
+# Entry points (same names as the C ABI)
+# ------------------------------------------------------------------------------------------------
+def nbx_version() -> int:
+    return load().nbx_version()
+
+
+def nbx_device_count() -> int:
+    n = ctypes.c_int(0)
+    rc = load().nbx_device_count(ctypes.byref(n))
+    return n.value if rc == NBX_OK else 0
+
+
+def nbx_open(device=0, order=4, precision=NBX_FP64, nj_max=1, ni_max=1, nbr_max=0):
+    cfg = nbx_config(device, order, precision, nj_max, ni_max, nbr_max)
+    ctx = ctypes.c_void_p()
+    rc = load().nbx_open(ctypes.byref(ctx), ctypes.byref(cfg))
+    if rc < 0:
+        raise NbxError(rc, load().nbx_last_error(None).decode())
+    return ctx
+
+
+def nbx_close(ctx):
+    return load().nbx_close(ctx)
+
+
+def nbx_last_error(ctx) -> str:
+    return load().nbx_last_error(ctx).decode()
+
+
+def nbx_set_precision(ctx, precision):
+    return _check(ctx, load().nbx_set_precision(ctx, precision))
+
+
+def nbx_set_nj(ctx, nj):
+    return _check(ctx, load().nbx_set_nj(ctx, int(nj)))
+
+
+def nbx_set_j(ctx, addr, id, m, t, x, v, a, jerk, snap=None, crackle=None):
+    addr = np.ascontiguousarray(addr, dtype=np.int32)
+    n = addr.shape[0]
+    id = np.ascontiguousarray(id, dtype=np.int64)
+    m, t = _f64(m, n, 0), _f64(t, n, 0)
+    x, v, a, jerk = _f64(x, n), _f64(v, n), _f64(a, n), _f64(jerk, n)
+    snap, crackle = _f64(snap, n), _f64(crackle, n)
+    if id.shape != (n,):
+        raise ValueError("id must have shape (n,)")
+    rc = load().nbx_set_j(ctx, n, _ptr(addr), _ptr(id), _ptr(m), _ptr(t), _ptr(x), _ptr(v), _ptr(a), _ptr(jerk),
+                          _ptr(snap), _ptr(crackle))
+    return _check(ctx, rc)
+
+
+def nbx_predict(ctx, t):
+    return _check(ctx, load().nbx_predict(ctx, float(t)))
+
+
+def nbx_force(ctx, i_addr, eps2, h2=None):
+    i_addr = np.ascontiguousarray(i_addr, dtype=np.int32)
+    n = i_addr.shape[0]
+    h2 = None if h2 is None else _f64(np.broadcast_to(np.asarray(h2, dtype=np.float64), (n,)), n, 0)
+    return _check(ctx, load().nbx_force(ctx, n, _ptr(i_addr), float(eps2), _ptr(h2)))
+
+
+def nbx_force_ext(ctx, id, x, v, a, eps2, h2=None):
+    x = _f64(x)
+    n = x.shape[0]
+    id = np.ascontiguousarray(id, dtype=np.int64)
+    v, a = _f64(v, n), _f64(a, n)
+    h2 = None if h2 is None else _f64(np.broadcast_to(np.asarray(h2, dtype=np.float64), (n,)), n, 0)
+    return _check(ctx, load().nbx_force_ext(ctx, n, _ptr(id), _ptr(x), _ptr(v), _ptr(a), float(eps2), _ptr(h2)))
+
+
+def nbx_get_force(ctx, ni, order=4):
+    """Results of the last force call on ni sinks, as a dict of numpy arrays (plus 'status')."""
+    out = {
+        "acc": np.empty((ni, 3)),
+        "jerk": np.empty((ni, 3)),
+        "snap": np.empty((ni, 3)) if order == 6 else None,
+        "pot": np.empty(ni),
+        "nn_id": np.empty(ni, dtype=np.int64),
+        "nn_r2": np.empty(ni),
+    }
+    rc = load().nbx_get_force(ctx, _ptr(out["acc"]), _ptr(out["jerk"]), _ptr(out["snap"]), _ptr(out["pot"]),
+                              _ptr(out["nn_id"]), _ptr(out["nn_r2"]))
+    out["status"] = _check(ctx, rc)
+    return out
+
+
+def nbx_get_nbr(ctx, ni, nbr_max):
+    count = np.empty(ni, dtype=np.int32)
+    ids = np.empty((ni, nbr_max), dtype=np.int64)
+    rc = _check(ctx, load().nbx_get_nbr(ctx, _ptr(count), _ptr(ids)))
+    return count, ids, rc
+
+
+def nbx_get_predicted(ctx, addr, order=4):
+    addr = np.ascontiguousarray(addr, dtype=np.int32)
+    n = addr.shape[0]
+    xp, vp, ap = np.empty((n, 3)), np.empty((n, 3)), np.empty((n, 3))
+    _check(ctx, load().nbx_get_predicted(ctx, n, _ptr(addr), _ptr(xp), _ptr(vp), _ptr(ap)))
+    return xp, vp, ap
+
+
+def nbx_get_j(ctx, addr, order=4):
+    addr = np.ascontiguousarray(addr, dtype=np.int32)
+    n = addr.shape[0]
+    out = {"id": np.empty(n, dtype=np.int64), "m": np.empty(n), "t": np.empty(n)}
+    for k in ("x", "v", "a", "jerk") + (("snap", "crackle") if order == 6 else ()):
+        out[k] = np.empty((n, 3))
+    rc = load().nbx_get_j(ctx, n, _ptr(addr), _ptr(out["id"]), _ptr(out["m"]), _ptr(out["t"]), _ptr(out["x"]),
+                          _ptr(out["v"]), _ptr(out["a"]), _ptr(out["jerk"]), _ptr(out.get("snap")),
+                          _ptr(out.get("crackle")))
+    _check(ctx, rc)
+    return out
+
+
+def nbx_set_j_dev(ctx, stream, n, d_addr, d_id, d_m, d_t, d_x, d_v, d_a, d_jerk, d_snap=None, d_crackle=None):
+    rc = load().nbx_set_j_dev(ctx, _stream(stream), int(n), _dptr(d_addr), _dptr(d_id), _dptr(d_m), _dptr(d_t),
+                              _dptr(d_x), _dptr(d_v), _dptr(d_a), _dptr(d_jerk), _dptr(d_snap), _dptr(d_crackle))
+    return _check(ctx, rc)
+
+
+def nbx_force_dev(ctx, stream, ni, d_i_addr, eps2, d_h2, d_acc, d_jerk, d_snap, d_pot, d_nn_id, d_nn_r2,
+                  d_nbr_count=None, d_nbr_ids=None):
+    rc = load().nbx_force_dev(ctx, _stream(stream), int(ni), _dptr(d_i_addr), float(eps2), _dptr(d_h2),
+                              _dptr(d_acc), _dptr(d_jerk), _dptr(d_snap), _dptr(d_pot), _dptr(d_nn_id),
+                              _dptr(d_nn_r2), _dptr(d_nbr_count), _dptr(d_nbr_ids))
+    return _check(ctx, rc)
+
+
+def nbx_sync(ctx, stream=0):
+    return _check(ctx, load().nbx_sync(ctx, _stream(stream) if stream != 0 else None))
+
+
+def nbx_launch_shape(ctx, ni):
+    vals = [ctypes.c_int(0) for _ in range(4)]
+    rc = load().nbx_launch_shape(ctx, int(ni), *[ctypes.byref(v) for v in vals])
+    if rc < 0:
+        raise NbxError(rc, "bad arguments")
+    return {"lanes_per_sink": vals[0].value, "sinks_per_lane": vals[1].value, "splits": vals[2].value,
+            "workgroups": vals[3].value}
+
+
+class Context:
+    """Owns one nbx context; thin convenience wrapper over the entry points above."""
+
+    def __init__(self, order=4, precision=NBX_FP64, nj_max=1, ni_max=1, nbr_max=0, device=0):
+        self.order = order
+        self.nbr_max = nbr_max
+        self.ctx = nbx_open(device, order, precision, nj_max, ni_max, nbr_max)
+        self._ni = None
+
+    def close(self):
+        if self.ctx is not None:
+            nbx_close(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_precision(self, p):
+        return nbx_set_precision(self.ctx, p)
+
+    def set_nj(self, nj):
+        return nbx_set_nj(self.ctx, nj)
+
+    def set_sources(self, src, addr=None):
+        """Load a nbody_ics.SourceSet-like object (fields ids, m, t, x, v, a, jerk[, snap, crackle])."""
+        addr = np.arange(src.n, dtype=np.int32) if addr is None else addr
+        return nbx_set_j(self.ctx, addr, src.ids, src.m, src.t, src.x, src.v, src.a, src.jerk,
+                         src.snap if self.order == 6 else None, src.crackle if self.order == 6 else None)
+
+    def predict(self, t):
+        return nbx_predict(self.ctx, t)
+
+    def force(self, i_addr, eps2, h2=None):
+        self._ni = len(i_addr)
+        return nbx_force(self.ctx, i_addr, eps2, h2)
+
+    def get_force(self):
+        return nbx_get_force(self.ctx, self._ni, self.order)
+
+    def get_predicted(self, addr):
+        return nbx_get_predicted(self.ctx, addr, self.order)
+
+    def get_j(self, addr):
+        return nbx_get_j(self.ctx, addr, self.order)
+
+    def launch_shape(self, ni):
+        return nbx_launch_shape(self.ctx, ni)

@@ -1,0 +1,74 @@
+"""Shared helpers of the GPU tests: run the HIP path and the oracle on the same seeded inputs and
+measure per-sink errors."""
+
+import sys
+
+import numpy as np
+
+import oracle
+import paper_1510_04068_amd as nbx
+
+PREC_NAME = {nbx.NBX_FP64: "fp64", nbx.NBX_MIXED: "mixed"}
+
+
+def say(*args):
+    print(*args, flush=True)
+    sys.stdout.flush()
+
+
+def oracle_all(src, order, eps2, t, addr=None, h2=None, nbr_max=0):
+    """Oracle forces on sinks taken by address from the predicted sources (all if addr is None)."""
+    xp, vp, ap = oracle.predict(order, t, src.t, src.x, src.v, src.a, src.jerk, src.snap, src.crackle)
+    sel = np.arange(src.n) if addr is None else np.asarray(addr)
+    ref = oracle.force(order, eps2, src.ids, src.m, xp, vp, src.ids[sel], xp[sel], vp[sel],
+                       aj=ap if order == 6 else None, ai=ap[sel] if order == 6 else None,
+                       h2=h2, nbr_max=nbr_max)
+    ref["xp"], ref["vp"], ref["ap"] = xp, vp, ap
+    return ref
+
+
+def subset(ref, sel):
+    out = {}
+    for k, v in ref.items():
+        if k in ("xp", "vp", "ap") or v is None:
+            out[k] = v
+        else:
+            out[k] = v[sel]
+    return out
+
+
+def rel_err_vec(q, r):
+    """Per-sink |q - r| / |r| for [n,3] arrays."""
+    den = np.linalg.norm(r, axis=1)
+    return np.linalg.norm(q - r, axis=1) / np.where(den > 0, den, 1.0)
+
+
+def cond_err_vec(q, r, cond):
+    """Per-sink |q - r| / sum_j |term_ij| (condition-normalised)."""
+    return np.linalg.norm(q - r, axis=1) / np.where(cond > 0, cond, 1.0)
+
+
+def check_nn(out, ref, xp, sel_addr, prec, ids):
+    """Nearest neighbour: exact in FP64; in mixed, any source whose exact |r|^2 is within FP32
+    resolution of the true minimum is accepted.  The reported r2 must be that source's exact
+    FP64 |r|^2."""
+    nn = out["nn_id"]
+    none = ref["nn_id"] < 0
+    assert np.all(nn[none] == -1)
+    assert np.all(np.isinf(out["nn_r2"][none]))
+    ok = ~none
+    id_to_addr = {int(i): a for a, i in enumerate(ids)}
+    addr_nn = np.array([id_to_addr[int(i)] for i in nn[ok]])
+    d = xp[addr_nn] - xp[sel_addr[ok]]
+    r2_exact = np.sum(d * d, axis=1)
+    np.testing.assert_allclose(out["nn_r2"][ok], r2_exact, rtol=1e-13, atol=0)  # r2 from the GPU predictor vs the oracle's
+    if prec == nbx.NBX_FP64:
+        assert np.all(r2_exact <= ref["nn_r2"][ok] * (1 + 1e-14))
+    else:
+        assert np.all(r2_exact <= ref["nn_r2"][ok] * (1 + 4e-7))
+    return int(np.sum(nn[ok] != ref["nn_id"][ok]))
+
+
+def run_gpu(ctx, i_addr, eps2):
+    ctx.force(np.asarray(i_addr, dtype=np.int32), eps2)
+    return ctx.get_force()

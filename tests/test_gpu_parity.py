@@ -1,0 +1,260 @@
+"""Parity of the HIP force path with the FP64 oracle, element by element, on seeded inputs.
+
+Bounds (per sink, max over sinks): FP64 acc and pot relative error <= 1e-13; mixed acc and pot
+<= 1e-6.  Jerk and snap have no stated bound; they are checked against looser, condition-
+normalised bounds derived from the arithmetic (FP32 velocities in mixed mode).
+"""
+
+import numpy as np
+import pytest
+
+import nbody_ics
+import oracle
+import paper_1510_04068_amd as nbx
+from gpu_helpers import PREC_NAME, check_nn, cond_err_vec, oracle_all, rel_err_vec, run_gpu, say, subset
+
+pytestmark = pytest.mark.gpu
+
+TOL = {
+    nbx.NBX_FP64: dict(acc=1e-13, pot=1e-13, jerk_cond=1e-13, snap_cond=1e-12),
+    nbx.NBX_MIXED: dict(acc=1e-6, pot=1e-6, jerk_cond=2e-6, snap_cond=1e-5),
+}
+
+
+def _compare(out, ref, prec, order, sel_addr, ids, label):
+    tol = TOL[prec]
+    e_acc = rel_err_vec(out["acc"], ref["acc"])
+    e_pot = np.abs(out["pot"] - ref["pot"]) / np.abs(ref["pot"])
+    e_jc = cond_err_vec(out["jerk"], ref["jerk"], ref["cond"][:, 1])
+    msg = "%s: max rel acc %.2e pot %.2e jerk/cond %.2e" % (label, e_acc.max(), e_pot.max(), e_jc.max())
+    if order == 6:
+        e_sc = cond_err_vec(out["snap"], ref["snap"], ref["cond"][:, 2])
+        msg += " snap/cond %.2e" % e_sc.max()
+        assert e_sc.max() <= tol["snap_cond"], msg
+    mism = check_nn(out, ref, ref["xp"], sel_addr, prec, ids)
+    say(msg + " nn-mismatch %d" % mism)
+    assert e_acc.max() <= tol["acc"], msg
+    assert e_pot.max() <= tol["pot"], msg
+    assert e_jc.max() <= tol["jerk_cond"], msg
+    if prec == nbx.NBX_FP64:
+        assert mism == 0
+
+
+@pytest.mark.parametrize("order", [4, 6])
+def test_predictor_matches_oracle(order):
+    n, t = 3000, 0.01
+    say("predictor order=%d n=%d seed=21" % (order, n))
+    src = nbody_ics.make_sources(n, seed=21, order=order)
+    xp, vp, ap = oracle.predict(order, t, src.t, src.x, src.v, src.a, src.jerk, src.snap, src.crackle)
+    with nbx.Context(order=order, nj_max=n, ni_max=16) as ctx:
+        ctx.set_sources(src)
+        ctx.predict(t)
+        gx, gv, ga = ctx.get_predicted(np.arange(n, dtype=np.int32))
+    np.testing.assert_allclose(gx, xp, rtol=2e-15, atol=1e-15)
+    np.testing.assert_allclose(gv, vp, rtol=2e-15, atol=1e-14)
+    if order == 6:
+        np.testing.assert_allclose(ga, ap, rtol=2e-15, atol=1e-13)
+
+
+NI_CASES = [1, 2, 3, 63, 64, 65, 255, 256, 257, 1000, 3000]
+
+
+@pytest.mark.parametrize("prec", [nbx.NBX_FP64, nbx.NBX_MIXED])
+@pytest.mark.parametrize("order", [4, 6])
+def test_force_parity_active_sets(order, prec):
+    """Active sets of every size class (lanes/wave/split edges) against a ragged source count."""
+    n, t = 3000, 0.0
+    eps2 = 1e-4 if order == 4 else 1e-6
+    masses = "equal" if order == 4 else "salpeter"
+    say("parity order=%d prec=%s n=%d eps2=%g seed=22" % (order, PREC_NAME[prec], n, eps2))
+    src = nbody_ics.make_sources(n, seed=22, order=order, masses=masses)
+    ref_all = oracle_all(src, order, eps2, t)
+    with nbx.Context(order=order, precision=prec, nj_max=n, ni_max=n) as ctx:
+        ctx.set_sources(src)
+        ctx.predict(t)
+        for ni in NI_CASES:
+            sel = nbody_ics.active_set(n, ni, seed=1000 + ni)
+            say("  ni=%d shape=%s" % (ni, ctx.launch_shape(ni)))
+            out = run_gpu(ctx, sel, eps2)
+            _compare(out, subset(ref_all, sel), prec, order, sel, src.ids, "  ni=%d" % ni)
+
+
+@pytest.mark.parametrize("prec", [nbx.NBX_FP64, nbx.NBX_MIXED])
+def test_config1_shared_step(prec):
+    """1024-body equal-mass Plummer sphere, eps2 = 1e-4, t_j = 0, every sink active."""
+    n, eps2 = 1024, 1e-4
+    say("config1 prec=%s" % PREC_NAME[prec])
+    src = nbody_ics.make_sources(n, seed=1, time_offsets=False)
+    ref = oracle_all(src, 4, eps2, 0.0)
+    with nbx.Context(order=4, precision=prec, nj_max=n, ni_max=n) as ctx:
+        ctx.set_sources(src)
+        ctx.predict(0.0)
+        sel = np.arange(n, dtype=np.int32)
+        out = run_gpu(ctx, sel, eps2)
+        _compare(out, ref, prec, 4, sel, src.ids, "config1")
+        again = run_gpu(ctx, sel, eps2)
+        for k in ("acc", "jerk", "pot", "nn_id", "nn_r2"):
+            np.testing.assert_array_equal(out[k], again[k])  # run-to-run determinism
+
+
+def test_config1_hermite_eight_steps():
+    """Eight shared 4th-order Hermite steps (dt = 1/256) driven through the GPU (FP64) and through
+    the oracle agree to 1e-12 in positions and velocities."""
+    n, eps2, dt = 1024, 1e-4, 1.0 / 256
+    say("config1 hermite 8 steps")
+    src = nbody_ics.make_sources(n, seed=1, time_offsets=False)
+    ids = src.ids
+    zeros = np.zeros((n, 3))
+    addr = np.arange(n, dtype=np.int32)
+
+    def corrector(dt, xp, vp, a0, j0, a1, j1):  # the GPU side's own copy of the Hermite corrector
+        d2 = (-6.0 * (a0 - a1) - dt * (4.0 * j0 + 2.0 * j1)) / (dt * dt)
+        d3 = (12.0 * (a0 - a1) + 6.0 * dt * (j0 + j1)) / (dt * dt * dt)
+        return (xp + d2 * dt**4 / 24.0 + d3 * dt**5 / 120.0, vp + d2 * dt**3 / 6.0 + d3 * dt**4 / 24.0)
+
+    # GPU-driven
+    with nbx.Context(order=4, nj_max=n, ni_max=n) as ctx:
+        x, v = src.x.copy(), src.v.copy()
+        nbx.nbx_set_j(ctx.ctx, addr, ids, src.m, np.zeros(n), x, v, zeros, zeros)
+        ctx.predict(0.0)
+        f = run_gpu(ctx, addr, eps2)
+        a0, j0 = f["acc"], f["jerk"]
+        t = 0.0
+        for _ in range(8):
+            nbx.nbx_set_j(ctx.ctx, addr, ids, src.m, np.full(n, t), x, v, a0, j0)
+            ctx.predict(t + dt)
+            xp, vp, _ = ctx.get_predicted(addr)
+            f = run_gpu(ctx, addr, eps2)
+            x, v = corrector(dt, xp, vp, a0, j0, f["acc"], f["jerk"])
+            t += dt
+            nbx.nbx_set_j(ctx.ctx, addr, ids, src.m, np.full(n, t), x, v, zeros, zeros)
+            ctx.predict(t)
+            f = run_gpu(ctx, addr, eps2)
+            a0, j0 = f["acc"], f["jerk"]
+        xg, vg = x, v
+    # oracle-driven
+    x, v = src.x.copy(), src.v.copy()
+    f = oracle.force(4, eps2, ids, src.m, x, v, ids, x, v)
+    a0, j0 = f["acc"], f["jerk"]
+    t = 0.0
+    for _ in range(8):
+        xp, vp, _ = oracle.predict(4, t + dt, np.full(n, t), x, v, a0, j0)
+        f = oracle.force(4, eps2, ids, src.m, xp, vp, ids, xp, vp)
+        x, v = oracle.hermite4_correct(dt, xp, vp, a0, j0, f["acc"], f["jerk"])
+        t += dt
+        f = oracle.force(4, eps2, ids, src.m, x, v, ids, x, v)
+        a0, j0 = f["acc"], f["jerk"]
+    ex = np.abs(xg - x).max() / np.abs(x).max()
+    ev = np.abs(vg - v).max() / np.abs(v).max()
+    say("hermite: max rel dx %.2e dv %.2e" % (ex, ev))
+    assert ex <= 1e-12 and ev <= 1e-12
+
+
+@pytest.mark.parametrize("prec", [nbx.NBX_FP64, nbx.NBX_MIXED])
+def test_edge_cases(prec):
+    say("edge cases prec=%s" % PREC_NAME[prec])
+    # one source, the sink is itself: no force, no potential, no neighbour
+    one = nbody_ics.make_sources(1, seed=30)
+    with nbx.Context(order=4, precision=prec, nj_max=4, ni_max=4) as ctx:
+        ctx.set_sources(one)
+        ctx.predict(0.0)
+        out = run_gpu(ctx, [0], 1e-4)
+        assert np.all(out["acc"] == 0) and np.all(out["jerk"] == 0) and out["pot"][0] == 0
+        assert out["nn_id"][0] == -1 and np.isinf(out["nn_r2"][0])
+        # zero sinks is a no-op
+        out0 = run_gpu(ctx, np.zeros(0, dtype=np.int32), 1e-4)
+        assert out0["acc"].shape == (0, 3)
+    # eps2 = 0 (guarded self term), ragged n
+    n = 500
+    src = nbody_ics.make_sources(n, seed=31)
+    ref = oracle_all(src, 4, 0.0, 0.0)
+    with nbx.Context(order=4, precision=prec, nj_max=n, ni_max=n) as ctx:
+        ctx.set_sources(src)
+        ctx.predict(0.0)
+        sel = np.arange(n, dtype=np.int32)
+        out = run_gpu(ctx, sel, 0.0)
+        _compare(out, ref, prec, 4, sel, src.ids, "eps2=0")
+
+
+def test_error_paths():
+    say("error paths")
+    n = 300
+    src = nbody_ics.make_sources(n, seed=32)
+    with nbx.Context(order=4, nj_max=n, ni_max=100) as ctx:
+        ctx.set_sources(src)
+        with pytest.raises(nbx.NbxError) as e:
+            ctx.force(np.arange(10, dtype=np.int32), 1e-4)
+        assert e.value.code == nbx.NBX_ERR_STATE  # force before predict
+        ctx.predict(0.0)
+        with pytest.raises(nbx.NbxError) as e:
+            ctx.force(np.array([0, n], dtype=np.int32), 1e-4)
+        assert e.value.code == nbx.NBX_ERR_ARG
+        with pytest.raises(nbx.NbxError) as e:
+            ctx.force(np.arange(101, dtype=np.int32), 1e-4)
+        assert e.value.code == nbx.NBX_ERR_CAPACITY
+        with pytest.raises(nbx.NbxError) as e:
+            ctx.force(np.arange(10, dtype=np.int32), -1.0)
+        assert e.value.code == nbx.NBX_ERR_ARG
+        with pytest.raises(nbx.NbxError) as e:
+            nbx.nbx_set_j(ctx.ctx, [n], [0], [1.0], [0.0], np.zeros((1, 3)), np.zeros((1, 3)), np.zeros((1, 3)),
+                          np.zeros((1, 3)))
+        assert e.value.code == nbx.NBX_ERR_ARG
+        # stored state reads back exactly (checkpoint)
+        back = ctx.get_j(np.arange(n, dtype=np.int32))
+        np.testing.assert_array_equal(back["x"], src.x)
+        np.testing.assert_array_equal(back["jerk"], src.jerk)
+        np.testing.assert_array_equal(back["id"], src.ids)
+
+
+def test_device_path_matches_host_path():
+    torch = pytest.importorskip("torch")
+    n, eps2 = 2000, 1e-4
+    say("device path n=%d" % n)
+    src = nbody_ics.make_sources(n, seed=33)
+    sel = nbody_ics.active_set(n, 700, seed=34)
+    dev = torch.device("cuda:0")
+    with nbx.Context(order=4, precision=nbx.NBX_MIXED, nj_max=n, ni_max=n) as ctx:
+        ctx.set_sources(src)
+        ctx.predict(0.0)
+        host = run_gpu(ctx, sel, eps2)
+        # reload the sources through the device path and compute into torch tensors
+        T = lambda a, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+        d_addr = T(np.arange(n), torch.int32)
+        nbx.nbx_set_j_dev(ctx.ctx, None, n, d_addr, T(src.ids, torch.int64), T(src.m), T(src.t), T(src.x), T(src.v),
+                          T(src.a), T(src.jerk))
+        nbx.nbx_set_nj(ctx.ctx, n)
+        ni = len(sel)
+        acc = torch.empty((ni, 3), dtype=torch.float64, device=dev)
+        jrk = torch.empty_like(acc)
+        pot = torch.empty(ni, dtype=torch.float64, device=dev)
+        nnid = torch.empty(ni, dtype=torch.int64, device=dev)
+        nnr2 = torch.empty(ni, dtype=torch.float64, device=dev)
+        nbx.nbx_force_dev(ctx.ctx, None, ni, T(sel, torch.int32), eps2, None, acc, jrk, None, pot, nnid, nnr2)
+        nbx.nbx_sync(ctx.ctx, None)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(acc.cpu().numpy(), host["acc"])
+        np.testing.assert_array_equal(jrk.cpu().numpy(), host["jerk"])
+        np.testing.assert_array_equal(pot.cpu().numpy(), host["pot"])
+        np.testing.assert_array_equal(nnid.cpu().numpy(), host["nn_id"])
+
+
+@pytest.mark.parametrize("prec", [nbx.NBX_FP64, nbx.NBX_MIXED])
+def test_full_size_sampled(prec):
+    """The headline workload at full size (N = 131072 Plummer, eps2 = 1e-6, per-source times) in the
+    launch shapes the benchmark times: every sink active (checked on 256 sampled sinks) and small
+    active sets (checked in full)."""
+    n, eps2, t = 131072, 1e-6, 0.0
+    say("full size prec=%s n=%d" % (PREC_NAME[prec], n))
+    src = nbody_ics.make_sources(n, seed=2)
+    rng = np.random.default_rng(77)
+    with nbx.Context(order=4, precision=prec, nj_max=n, ni_max=n) as ctx:
+        ctx.set_sources(src)
+        ctx.predict(t)
+        for ni in (1, 64, 4096, n):
+            sel = nbody_ics.active_set(n, ni, seed=1002)
+            say("  ni=%d shape=%s" % (ni, ctx.launch_shape(ni)))
+            out = run_gpu(ctx, sel, eps2)
+            pick = np.sort(rng.choice(ni, size=min(ni, 256), replace=False))
+            ref = oracle_all(src, 4, eps2, t, addr=sel[pick])
+            got = {k: (v[pick] if v is not None else None) for k, v in out.items() if k != "status"}
+            _compare(got, ref, prec, 4, sel[pick], src.ids, "  ni=%d" % ni)
