@@ -198,7 +198,9 @@ def main():
     if not args.no_sweep:
         for e in range(18):
             ni = 1 << e
-            row = {"ni": ni}
+            sh = ctx.launch_shape(ni)
+            row = {"ni": ni, "shape": "L%d P%d S%d wg%d" % (sh["lanes_per_sink"], sh["sinks_per_lane"], sh["splits"],
+                                                          sh["workgroups"])}
             for prec, name in ((nbx.NBX_FP64, "fp64"), (nbx.NBX_MIXED, "mixed")):
                 ctx.set_precision(prec)
                 s, k = timed(torch, nbx, ctx, w, ni, stream, args.sweep_reps, 1)

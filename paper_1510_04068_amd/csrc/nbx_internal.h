@@ -10,7 +10,7 @@
 //   snp_crk[a]  = (sx, sy, sz, cx, cy, cz) 48 B   (order 6 only)
 //   id[a]       int64
 // The arrays hold nj_max entries; entries never written hold a massless source at
-// (1e30, 1e30, 1e30) with id -1.  The force kernel reads addresses [0, nj) and substitutes
+// (1e18, 1e18, 1e18) with id -1.  The force kernel reads addresses [0, nj) and substitutes
 // the same massless far-away source for the tail [nj, nj_pad) of the last LDS tile.
 #pragma once
 
@@ -21,7 +21,9 @@ namespace nbx {
 
 constexpr int kThreads = 256;  // workgroup size: 4 wave64s
 constexpr int kTile = 256;     // sources per LDS tile (one per thread when staging)
-constexpr double kPadPos = 1e30;
+// Position of padding sources: far enough that every term is negligible, near enough that R^2
+// (~3e36) stays finite in FP32, so R^-1 and its Newton step stay finite too.
+constexpr double kPadPos = 1e18;
 
 struct SourceArrays {
   double4 *pos_mass;
@@ -59,11 +61,11 @@ struct ForceParams {
   double *nn_r2;
   int32_t *nbr_count;
   int64_t *nbr_ids;
-  // split-combine scratch (S > 1): part[(s*K + k)*ni + q], part_key/part_idx[s*ni + q]
+  // split-combine scratch (S > 1), written by k_force and read by k_combine:
+  // part[(s*K + k)*ni + q], part_key/part_idx[s*ni + q]
   double *part;
   uint64_t *part_key;
   int32_t *part_idx;
-  unsigned *counters;  // one per sink block, zero between launches
   int *err;            // device-side error counters: [0] bad sink address, [1] bad source address
 };
 

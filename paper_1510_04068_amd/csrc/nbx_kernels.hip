@@ -15,9 +15,9 @@
 //     broadcast read of a source feeds P interactions;
 //   * partial sums are combined deterministically: a butterfly over the L lanes (all lanes end
 //     with bit-identical values), an LDS pass across waves when L > 64, and, when S > 1, a
-//     fixed-order sum over the S partials done by the workgroup that arrives last at a per-block
-//     counter (the paper combines source subsets with atomics inside the gravity kernel,
-//     Methods > Other differences; this keeps the single kernel but makes the order fixed).
+//     second kernel that sums the S partials of each sink in a fixed order (the paper folded
+//     the subsets with atomics inside the gravity kernel, Methods > Other differences; on
+//     gfx950 the device-scope fence that would need per workgroup is the expensive part).
 //
 // Arithmetic per interaction (the pair terms of nbx.h):
 //   MIXED: dx = (xh_j - xh_i) + (xl_j - xl_i) in FP32 from double-single positions, FP32
@@ -32,6 +32,9 @@
 // (1-2 tiles of nj/256 when the active sinks are consecutive) and only then runs the loop variant
 // that forces R^-1 = 0 for j == self: the self pair never enters a sum, so no -m_i/eps term has
 // to be removed later, and eps2 = 0 needs no special case.
+
+#include <cstdio>
+#include <cstdlib>
 
 #include "nbx_internal.h"
 
@@ -587,7 +590,6 @@ __global__ __launch_bounds__(kThreads) void k_force(const ForceParams fp) {
   constexpr int K = kValues<Order>;
   __shared__ typename Tr::Tile tiles[2];
   __shared__ RedLds<P, K> red;
-  __shared__ int s_last;
 
   const int tid = threadIdx.x;
   const int lg = fp.lanes_log2;
@@ -625,8 +627,8 @@ __global__ __launch_bounds__(kThreads) void k_force(const ForceParams fp) {
   const T eps2 = (T)fp.eps2;
 
   // Tile staging with the fused predictor.  Addresses >= nj (the tail of the last tile) get a
-  // padding source: massless, at rest, at (1e30, 1e30, 1e30); all its terms are exact zeros in
-  // both precisions and its address marks "no neighbour".
+  // padding source: massless, at rest, at (kPadPos, kPadPos, kPadPos); all its terms are exact
+  // zeros in both precisions and its address marks "no neighbour".
   auto stage = [&](int tile, int buf) {
     const int jj = tile * kTile + tid;
     double xp[3], vp[3], ap[3], m;
@@ -681,8 +683,7 @@ __global__ __launch_bounds__(kThreads) void k_force(const ForceParams fp) {
     return;
   }
 
-  // S > 1: publish this split's partials, then the last workgroup of the sink block sums the S
-  // partials of each sink in a fixed order.
+  // S > 1: publish this split's partials; k_combine sums them in a fixed order.
   if (slot == 0) {
 #pragma unroll
     for (int p = 0; p < P; ++p) {
@@ -694,40 +695,43 @@ __global__ __launch_bounds__(kThreads) void k_force(const ForceParams fp) {
       }
     }
   }
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) s_last = atomicAdd(&fp.counters[ib], 1u) == (unsigned)(S - 1);
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
+}
 
-  const int W = Q < kThreads ? Q : kThreads;  // sinks per pass
-  const int R = kThreads / W;                 // threads per sink
-  const int qb = ib * Q;
-  for (int pass = 0; pass < Q / W; ++pass) {
-    const int qg = qb + pass * W + tid / R;
-    const int r = tid % R;
-    double w[1][K];
-    uint64_t wk[1] = {~0ull};
-    int wi[1] = {-1};
+// ---------------------------------------------------------------------------------------------
+// Combine kernel for S > 1: R = 2^rlog threads per sink (R >= S when S <= 256); thread r of a
+// sink sums partials s = r, r + R, ... in order, then a butterfly over the R threads.  The sum
+// order depends only on S and R, so results are bit-reproducible.  The paper merged this step
+// into the gravity kernel with atomics (Methods > Other differences); on this multi-XCD part
+// the device-scope fence each workgroup would need costs more than a second launch.
+// ---------------------------------------------------------------------------------------------
+template <int Order>
+__global__ __launch_bounds__(kThreads) void k_combine(const ForceParams fp, int rlog) {
+  constexpr int K = kValues<Order>;
+  __shared__ RedLds<1, K> red;
+  const int R = 1 << rlog;
+  const int W = kThreads >> rlog;
+  const int qg = blockIdx.x * W + ((int)threadIdx.x >> rlog);
+  const int r = threadIdx.x & (R - 1);
+  const int S = fp.splits;
+  double w[1][K];
+  uint64_t wk[1] = {~0ull};
+  int wi[1] = {-1};
 #pragma unroll
-    for (int k = 0; k < K; ++k) w[0][k] = 0.0;
-    if (qg < fp.ni) {
-      for (int s = r; s < S; s += R) {
+  for (int k = 0; k < K; ++k) w[0][k] = 0.0;
+  if (qg < fp.ni) {
+    for (int s = r; s < S; s += R) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) w[0][k] += fp.part[((size_t)s * K + k) * fp.ni + qg];
-        const uint64_t pk = fp.part_key[(size_t)s * fp.ni + qg];
-        const int pi = fp.part_idx[(size_t)s * fp.ni + qg];
-        if (nn_better(pk, pi, wk[0], wi[0])) {
-          wk[0] = pk;
-          wi[0] = pi;
-        }
+      for (int k = 0; k < K; ++k) w[0][k] += fp.part[((size_t)s * K + k) * fp.ni + qg];
+      const uint64_t pk = fp.part_key[(size_t)s * fp.ni + qg];
+      const int pi = fp.part_idx[(size_t)s * fp.ni + qg];
+      if (nn_better(pk, pi, wk[0], wi[0])) {
+        wk[0] = pk;
+        wi[0] = pi;
       }
     }
-    group_reduce<1, K>(R, w, wk, wi, *reinterpret_cast<RedLds<1, K> *>(&red));
-    if (r == 0 && qg < fp.ni) finalize_sink<Order>(fp, qg, w[0], wi[0]);
   }
-  if (tid == 0) fp.counters[ib] = 0u;
+  group_reduce<1, K>(R, w, wk, wi, red);
+  if (r == 0 && qg < fp.ni) finalize_sink<Order>(fp, qg, w[0], wi[0]);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -836,26 +840,56 @@ __global__ __launch_bounds__(256) void k_fill_i32(int32_t *p, int n, int value) 
 // ---------------------------------------------------------------------------------------------
 int values_per_sink(int order) { return order == 6 ? 10 : 7; }
 
-// Launch shape: sinks per workgroup Q = (256 / L) * P.  Large active sets use L = 1 and two
-// sinks per lane; small ones spread each sink over L lanes so every lane has work.  The source
-// range is then split until there are about 2048 workgroups (8 per CU), at least one tile each.
+// Launch shape.  A workgroup holds Q = (256 / L) * P sinks and one of S source ranges.
+//   * About 8 workgroups per CU (2048) fill the 256 CUs.
+//   * Partials cost S * ni * 72 bytes of scratch traffic: S * ni <= 2^21.
+//   * Staging a tile costs one FP64 prediction per thread, so a thread should get at least 16
+//     interactions per tile: Q >= 16 unless there are fewer sinks than that.
+// Q runs from min(512, ni rounded up to a power of two; 512 = two sinks per lane) down to that
+// floor and the first Q that reaches the
+// workgroup target wins (the largest reuse of each staged source); if none does, the floor is
+// used with the largest S allowed.  NBX_SHAPE="L,P,S" in the environment overrides the rule.
+static int ilog2(int v) {
+  int l = 0;
+  while ((1 << (l + 1)) <= v) ++l;
+  return l;
+}
+
 LaunchShape choose_shape(int ni, int nj_pad) {
   LaunchShape ls;
   const int ntiles = nj_pad / kTile > 0 ? nj_pad / kTile : 1;
-  if (ni >= 2 * kThreads * 8) {
-    ls.lanes_log2 = 0;
-    ls.sinks_per_lane = 2;
-  } else {
-    int lg = 0;
-    while (lg < 8 && (kThreads >> (lg + 1)) >= ni) ++lg;
-    ls.lanes_log2 = lg;
-    ls.sinks_per_lane = 1;
-  }
-  const int Q = (kThreads >> ls.lanes_log2) * ls.sinks_per_lane;
-  ls.blocks = (ni + Q - 1) / Q;
   const int target = 2048;
+  const int64_t part_cap = (int64_t)1 << 21;
+  int scap = (int)(part_cap / (ni > 0 ? ni : 1));
+  if (scap > ntiles) scap = ntiles;
+  if (scap < 1) scap = 1;
+  if (const char *env = getenv("NBX_SHAPE")) {
+    int L = 0, P = 0, S = 0;
+    if (sscanf(env, "%d,%d,%d", &L, &P, &S) == 3 && L >= 1 && L <= kThreads && (L & (L - 1)) == 0 &&
+        (P == 1 || P == 2) && S >= 1) {
+      ls.lanes_log2 = ilog2(L);
+      ls.sinks_per_lane = P;
+      const int Q = (kThreads >> ls.lanes_log2) * P;
+      ls.blocks = (ni + Q - 1) / Q;
+      ls.splits = S < ntiles ? S : ntiles;
+      return ls;
+    }
+  }
+  int qmin = 1;
+  while (qmin < ni && qmin < 16) qmin *= 2;
+  int qcover = 1;  // never more sink slots than the next power of two of ni
+  while (qcover < ni && qcover < 2 * kThreads) qcover *= 2;
+  int Q = qcover > qmin ? qcover : qmin;
+  for (; Q >= qmin; Q /= 2) {
+    const int64_t blocks = (ni + Q - 1) / Q;
+    if (blocks * scap >= target) break;
+  }
+  if (Q < qmin) Q = qmin;
+  ls.sinks_per_lane = Q > kThreads ? 2 : 1;
+  ls.lanes_log2 = ilog2(kThreads * ls.sinks_per_lane / Q);
+  ls.blocks = (ni + Q - 1) / Q;
   int S = (target + ls.blocks - 1) / ls.blocks;
-  if (S > ntiles) S = ntiles;
+  if (S > scap) S = scap;
   if (S < 1) S = 1;
   ls.splits = S;
   return ls;
@@ -864,6 +898,12 @@ LaunchShape choose_shape(int ni, int nj_pad) {
 template <int Order, int Prec, int P>
 static hipError_t launch_force_t(const ForceParams &fp, const LaunchShape &ls, hipStream_t stream) {
   hipLaunchKernelGGL((k_force<Order, Prec, P>), dim3(ls.blocks * ls.splits), dim3(kThreads), 0, stream, fp);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || ls.splits <= 1) return e;
+  int rlog = 0;
+  while ((1 << rlog) < ls.splits && rlog < 8) ++rlog;
+  const int W = kThreads >> rlog;
+  hipLaunchKernelGGL(k_combine<Order>, dim3((fp.ni + W - 1) / W), dim3(kThreads), 0, stream, fp, rlog);
   return hipGetLastError();
 }
 

@@ -52,7 +52,6 @@ struct nbx_ctx {
   int64_t *d_nbr_ids = nullptr;
   // split-combine scratch
   DevBuf part, part_key, part_idx;
-  unsigned *counters = nullptr;
   int *d_err = nullptr;  // [0] bad sink address, [1] bad source address, [2] nbr overflow
   // set_j staging (host path), grown on demand
   DevBuf up;
@@ -188,7 +187,6 @@ int enqueue_force(nbx_ctx *c, hipStream_t stream, int ni, const int32_t *d_iaddr
   fp.part = static_cast<double *>(c->part.p);
   fp.part_key = static_cast<uint64_t *>(c->part_key.p);
   fp.part_idx = static_cast<int32_t *>(c->part_idx.p);
-  fp.counters = c->counters;
   fp.err = c->d_err;
   hipError_t e = launch_force(c->cfg.order, c->precision, fp, ls, stream);
   if (e != hipSuccess) return hip_fail(c, e, "force kernel launch");
@@ -269,11 +267,9 @@ int nbx_open(nbx_ctx **out, const nbx_config *cfg) {
   rc = rc ? rc : alloc_n(c, &c->d_pot, ni);
   rc = rc ? rc : alloc_n(c, &c->d_nnid, ni);
   rc = rc ? rc : alloc_n(c, &c->d_nnr2, ni);
-  rc = rc ? rc : alloc_n(c, &c->counters, ni + 1);
   rc = rc ? rc : alloc_n(c, &c->d_err, 4);
   if (rc) return bail(rc);
   hipError_t e = launch_pad(cfg->order, c->src, 0, cfg->nj_max, c->stream);
-  if (e == hipSuccess) e = launch_fill_i32(reinterpret_cast<int32_t *>(c->counters), (int)ni + 1, 0, c->stream);
   if (e == hipSuccess) e = launch_fill_i32(c->d_err, 4, 0, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return bail(hip_fail(c, e, "context initialisation"));
