@@ -224,16 +224,45 @@ struct Mixed {
     return j;
   }
 
+  // The source record as the force loop sees it after staging (same conversions as store/load).
+  __device__ static __forceinline__ J make_j(const double xp[3], const double vp[3], const double ap[3], double m) {
+    J j;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      ds_split(xp[k], j.xh[k], j.xl[k]);
+      j.v[k] = (float)vp[k];
+      j.a[k] = (float)ap[k];
+    }
+    j.m = (float)m;
+    return j;
+  }
+
+  // Position difference and unsoftened |r|^2: the one definition used by the force loop and by
+  // the nearest-neighbour re-scan, so both produce the same bits.
+  __device__ static __forceinline__ float diff_r2(const J &j, const Sink &s, float &dx, float &dy, float &dz) {
+    dx = (j.xh[0] - s.xh[0]) + (j.xl[0] - s.xl[0]);
+    dy = (j.xh[1] - s.xh[1]) + (j.xl[1] - s.xl[1]);
+    dz = (j.xh[2] - s.xh[2]) + (j.xl[2] - s.xl[2]);
+    return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+  }
+
+  // Nearest-neighbour key: bit pattern of |r|^2 minus one (r2 == 0, the sink itself, wraps to the
+  // maximum and never wins); unsigned order equals the order of |r|^2.
+  __device__ static __forceinline__ Key key_of(float r2) { return __float_as_uint(r2) - 1u; }
+
+  __device__ static __forceinline__ Key nn_key(const J &j, const Sink &s) {
+    float dx, dy, dz;
+    return key_of(diff_r2(j, s, dx, dy, dz));
+  }
+
   template <bool Guard>
   __device__ static __forceinline__ void interact(const J &j, const Sink &s, float eps2, int jidx, int self,
-                                                  Comp<float, kValues<Order>> &A, Key &nnk, int &nni) {
-    const float dx = (j.xh[0] - s.xh[0]) + (j.xl[0] - s.xl[0]);
-    const float dy = (j.xh[1] - s.xh[1]) + (j.xl[1] - s.xl[1]);
-    const float dz = (j.xh[2] - s.xh[2]) + (j.xl[2] - s.xl[2]);
+                                                  Comp<float, kValues<Order>> &A, Key &gmin) {
+    float dx, dy, dz;
+    const float r2 = diff_r2(j, s, dx, dy, dz);
     const float dvx = j.v[0] - s.v[0];
     const float dvy = j.v[1] - s.v[1];
     const float dvz = j.v[2] - s.v[2];
-    const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
     const float R2 = r2 + eps2;
     const float rv = __builtin_fmaf(dz, dvz, __builtin_fmaf(dy, dvy, dx * dvx));
     // v_rsq_f32 estimate plus one Newton step: y (3 - R2 y^2) / 2
@@ -278,11 +307,8 @@ struct Mixed {
       A.part[6] -= mr;
       A.part[7] += a2x; A.part[8] += a2y; A.part[9] += a2z;
     }
-    const Key key = __float_as_uint(r2) - 1u;  // r2 == 0 (self) wraps to the maximum
-    if (key < nnk) {
-      nnk = key;
-      nni = jidx;
-    }
+    const Key key = key_of(r2);
+    gmin = key < gmin ? key : gmin;
   }
 };
 
@@ -372,16 +398,40 @@ struct F64 {
     return j;
   }
 
+  __device__ static __forceinline__ J make_j(const double xp[3], const double vp[3], const double ap[3], double m) {
+    J j;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      j.x[k] = xp[k];
+      j.v[k] = vp[k];
+      j.a[k] = ap[k];
+    }
+    j.m = m;
+    return j;
+  }
+
+  __device__ static __forceinline__ double diff_r2(const J &j, const Sink &s, double &dx, double &dy, double &dz) {
+    dx = j.x[0] - s.x[0];
+    dy = j.x[1] - s.x[1];
+    dz = j.x[2] - s.x[2];
+    return fma(dz, dz, fma(dy, dy, dx * dx));
+  }
+
+  __device__ static __forceinline__ Key key_of(double r2) { return (Key)__double_as_longlong(r2) - 1ull; }
+
+  __device__ static __forceinline__ Key nn_key(const J &j, const Sink &s) {
+    double dx, dy, dz;
+    return key_of(diff_r2(j, s, dx, dy, dz));
+  }
+
   template <bool Guard>
   __device__ static __forceinline__ void interact(const J &j, const Sink &s, double eps2, int jidx, int self,
-                                                  Comp<double, kValues<Order>> &A, Key &nnk, int &nni) {
-    const double dx = j.x[0] - s.x[0];
-    const double dy = j.x[1] - s.x[1];
-    const double dz = j.x[2] - s.x[2];
+                                                  Comp<double, kValues<Order>> &A, Key &gmin) {
+    double dx, dy, dz;
+    const double r2 = diff_r2(j, s, dx, dy, dz);
     const double dvx = j.v[0] - s.v[0];
     const double dvy = j.v[1] - s.v[1];
     const double dvz = j.v[2] - s.v[2];
-    const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
     const double R2 = r2 + eps2;
     const double rv = fma(dz, dvz, fma(dy, dvy, dx * dvx));
     double rinv = rsqrt64(R2);
@@ -424,11 +474,8 @@ struct F64 {
       A.part[6] -= mr;
       A.part[7] += a2x; A.part[8] += a2y; A.part[9] += a2z;
     }
-    const Key key = (Key)__double_as_longlong(r2) - 1ull;
-    if (key < nnk) {
-      nnk = key;
-      nni = jidx;
-    }
+    const Key key = key_of(r2);
+    gmin = key < gmin ? key : gmin;
   }
 };
 
@@ -552,21 +599,38 @@ __device__ void finalize_sink(const ForceParams &fp, int q, const double *v, int
 // One LDS tile against the lane's P sinks.  Guard = true is used only for tiles that hold the
 // own source of some sink of the wave: there R^-1 is forced to 0 for j == self, so the self pair
 // adds exact zeros everywhere (its |r|^2 = 0 key already wraps to the maximum).
-template <class Tr, int P, bool Guard>
+// The lane's sources are taken in groups of kChunkAcc; inside a group only the minimum
+// nearest-neighbour key is kept, and after the group the (key, first source of the group) pair
+// replaces the running best if the key is smaller.  The exact source is found afterwards by
+// re-scanning that one group (nn_rescan).  L1: one lane per sink (compile-time offsets).
+template <class Tr, int P, bool Guard, bool L1>
 __device__ __forceinline__ void tile_compute(const typename Tr::Tile &tl, int slot, int lg, int jb,
                                              const typename Tr::Sink (&sink)[P], const int (&self)[P],
                                              typename Tr::Real eps2,
                                              Comp<typename Tr::Real, Tr::kK> (&acc)[P],
-                                             typename Tr::Key (&nnk)[P], int (&nni)[P]) {
-  const int per = kTile >> lg;
+                                             typename Tr::Key (&nnk)[P], int (&nng)[P]) {
+  using Key = typename Tr::Key;
+  const int per = L1 ? kTile : kTile >> lg;
   for (int c = 0; c < per; c += kChunkAcc) {
     const int ce = per < c + kChunkAcc ? per : c + kChunkAcc;
+    Key gmin[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) gmin[p] = ~Key(0);
 #pragma unroll 2
     for (int u = c; u < ce; ++u) {
-      const typename Tr::J j = Tr::load(tl, slot + (u << lg));
-      const int jidx = jb + (u << lg);
+      const int e = L1 ? u : slot + (u << lg);
+      const typename Tr::J j = Tr::load(tl, e);
+      const int jidx = L1 ? jb + u : jb + (u << lg);
 #pragma unroll
-      for (int p = 0; p < P; ++p) Tr::template interact<Guard>(j, sink[p], eps2, jidx, self[p], acc[p], nnk[p], nni[p]);
+      for (int p = 0; p < P; ++p) Tr::template interact<Guard>(j, sink[p], eps2, jidx, self[p], acc[p], gmin[p]);
+    }
+    const int g0 = L1 ? jb + c : jb + (c << lg);
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      if (gmin[p] < nnk[p]) {
+        nnk[p] = gmin[p];
+        nng[p] = g0;
+      }
     }
 #pragma unroll
     for (int p = 0; p < P; ++p) acc[p].template fold<0, 3>();
@@ -577,12 +641,45 @@ __device__ __forceinline__ void tile_compute(const typename Tr::Tile &tl, int sl
   }
 }
 
+// Source record of address j exactly as staged by the gravity kernel (padding beyond nj).
+template <class Tr, int Order>
+__device__ __forceinline__ typename Tr::J staged_j(const ForceParams &fp, int jj) {
+  double xp[3], vp[3], ap[3], m;
+  if (jj < fp.nj) {
+    predict_addr<Order>(fp.src, jj, fp.t, xp, vp, ap, m);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      xp[k] = kPadPos;
+      vp[k] = 0.0;
+      ap[k] = 0.0;
+    }
+    m = 0.0;
+  }
+  return Tr::make_j(xp, vp, ap, m);
+}
+
+// Find the first source of the winning group whose key equals the best key (the group start g0
+// and lane stride L identify the group; its length is min(kChunkAcc, 256 / L)).
+template <class Tr, int Order>
+__device__ __forceinline__ int nn_rescan(const ForceParams &fp, const typename Tr::Sink &s, typename Tr::Key key,
+                                         int g0, int lg) {
+  if (g0 < 0) return -1;
+  const int per = kTile >> lg;
+  const int len = per < kChunkAcc ? per : kChunkAcc;
+  for (int k = 0; k < len; ++k) {
+    const int jj = g0 + (k << lg);
+    if (Tr::nn_key(staged_j<Tr, Order>(fp, jj), s) == key) return jj;
+  }
+  return -1;  // not reached: the group's minimum key comes from one of its sources
+}
+
 // ---------------------------------------------------------------------------------------------
 // The gravity kernel.  Grid: blocks * S workgroups; workgroup w handles sink block w / S and
 // source split w % S (split-fastest, so with S a multiple of 8 every split stays on one XCD and
 // its sources stay in that XCD's L2).
 // ---------------------------------------------------------------------------------------------
-template <int Order, int Prec, int P>
+template <int Order, int Prec, int P, bool L1>
 __global__ __launch_bounds__(kThreads) void k_force(const ForceParams fp) {
   using Tr = typename TraitsSel<Order, Prec>::type;
   using T = typename Tr::Real;
@@ -608,7 +705,7 @@ __global__ __launch_bounds__(kThreads) void k_force(const ForceParams fp) {
   typename Tr::Sink sink[P];
   Comp<T, K> acc[P];
   Key nnk[P];
-  int nni[P];
+  int nng[P];  // first source of the group holding the best key (-1: none yet)
   int q[P];
   int self[P];  // own source address of each sink (-1: no sink in this slot)
 #pragma unroll
@@ -622,7 +719,7 @@ __global__ __launch_bounds__(kThreads) void k_force(const ForceParams fp) {
     sink[p] = Tr::make_sink(xp, vp, ap, m);
     acc[p].init();
     nnk[p] = ~Key(0);
-    nni[p] = -1;
+    nng[p] = -1;
   }
   const T eps2 = (T)fp.eps2;
 
@@ -654,14 +751,15 @@ __global__ __launch_bounds__(kThreads) void k_force(const ForceParams fp) {
 #pragma unroll
     for (int p = 0; p < P; ++p) mine |= (self[p] >> 8) == tile;  // kTile == 256
     if (__any(mine))
-      tile_compute<Tr, P, true>(tiles[buf], slot, lg, tile * kTile + slot, sink, self, eps2, acc, nnk, nni);
+      tile_compute<Tr, P, true, L1>(tiles[buf], slot, lg, tile * kTile + slot, sink, self, eps2, acc, nnk, nng);
     else
-      tile_compute<Tr, P, false>(tiles[buf], slot, lg, tile * kTile + slot, sink, self, eps2, acc, nnk, nni);
+      tile_compute<Tr, P, false, L1>(tiles[buf], slot, lg, tile * kTile + slot, sink, self, eps2, acc, nnk, nng);
     if (tile + 1 < t1) stage(tile + 1, buf ^ 1);
     __syncthreads();
   }
 
-  // lanes of a sink -> one value (identical in every lane of the group)
+  // exact nearest-neighbour source of each lane, then lanes of a sink -> one value (identical in
+  // every lane of the group)
   double v[P][K];
   uint64_t kk[P];
   int ii[P];
@@ -670,7 +768,7 @@ __global__ __launch_bounds__(kThreads) void k_force(const ForceParams fp) {
 #pragma unroll
     for (int k = 0; k < K; ++k) v[p][k] = (double)acc[p].hi[k] + (double)acc[p].lo[k];
     kk[p] = (uint64_t)nnk[p];
-    ii[p] = nni[p];
+    ii[p] = nn_rescan<Tr, Order>(fp, sink[p], nnk[p], nng[p], lg);
   }
   group_reduce<P, K>(L, v, kk, ii, red);
 
@@ -865,8 +963,9 @@ LaunchShape choose_shape(int ni, int nj_pad) {
   if (scap < 1) scap = 1;
   if (const char *env = getenv("NBX_SHAPE")) {
     int L = 0, P = 0, S = 0;
+    // two sinks per lane exist only with one lane per sink
     if (sscanf(env, "%d,%d,%d", &L, &P, &S) == 3 && L >= 1 && L <= kThreads && (L & (L - 1)) == 0 &&
-        (P == 1 || P == 2) && S >= 1) {
+        (P == 1 || (P == 2 && L == 1)) && S >= 1) {
       ls.lanes_log2 = ilog2(L);
       ls.sinks_per_lane = P;
       const int Q = (kThreads >> ls.lanes_log2) * P;
@@ -895,9 +994,9 @@ LaunchShape choose_shape(int ni, int nj_pad) {
   return ls;
 }
 
-template <int Order, int Prec, int P>
+template <int Order, int Prec, int P, bool L1>
 static hipError_t launch_force_t(const ForceParams &fp, const LaunchShape &ls, hipStream_t stream) {
-  hipLaunchKernelGGL((k_force<Order, Prec, P>), dim3(ls.blocks * ls.splits), dim3(kThreads), 0, stream, fp);
+  hipLaunchKernelGGL((k_force<Order, Prec, P, L1>), dim3(ls.blocks * ls.splits), dim3(kThreads), 0, stream, fp);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || ls.splits <= 1) return e;
   int rlog = 0;
@@ -909,8 +1008,9 @@ static hipError_t launch_force_t(const ForceParams &fp, const LaunchShape &ls, h
 
 template <int Order, int Prec>
 static hipError_t launch_force_op(const ForceParams &fp, const LaunchShape &ls, hipStream_t stream) {
-  if (ls.sinks_per_lane == 2) return launch_force_t<Order, Prec, 2>(fp, ls, stream);
-  return launch_force_t<Order, Prec, 1>(fp, ls, stream);
+  if (ls.sinks_per_lane == 2) return launch_force_t<Order, Prec, 2, true>(fp, ls, stream);
+  if (ls.lanes_log2 == 0) return launch_force_t<Order, Prec, 1, true>(fp, ls, stream);
+  return launch_force_t<Order, Prec, 1, false>(fp, ls, stream);
 }
 
 hipError_t launch_force(int order, int precision, const ForceParams &fp, const LaunchShape &ls,
