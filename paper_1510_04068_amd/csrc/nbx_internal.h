@@ -43,7 +43,8 @@ struct ForceParams {
   double eps2;
   int ni;
   const int32_t *i_addr;  // by-address sinks [ni]
-  const int64_t *ext_id;  // explicit sinks: id [ni], x/v/a [ni][3]
+  const int32_t *ext_self;  // explicit sinks: address of the source with the sink's id, or -1
+  const int64_t *ext_id;    // explicit sinks: id [ni], x/v/a [ni][3] (ext_x == nullptr: by address)
   const double *ext_x;
   const double *ext_v;
   const double *ext_a;
@@ -91,6 +92,8 @@ hipError_t launch_gather_j(int order, const SourceArrays &src, int n, const int3
                            int64_t *id, double *m, double *t, double *x, double *v, double *a,
                            double *jerk, double *snap, double *crackle, hipStream_t stream);
 hipError_t launch_fill_i32(int32_t *p, int n, int value, hipStream_t stream);
+hipError_t launch_selfmap(const SourceArrays &src, int nj, int ni, const int64_t *ext_id, int32_t *self,
+                          hipStream_t stream);
 
 // Launch-shape rule (defined in nbx_kernels.hip).
 LaunchShape choose_shape(int ni, int nj_pad);

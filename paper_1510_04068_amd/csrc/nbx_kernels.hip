@@ -255,8 +255,9 @@ struct Mixed {
     return key_of(diff_r2(j, s, dx, dy, dz));
   }
 
+  // One pair; returns the unsoftened |r|^2 (for the neighbour-list test).
   template <bool Guard>
-  __device__ static __forceinline__ void interact(const J &j, const Sink &s, float eps2, int jidx, int self,
+  __device__ static __forceinline__ float interact(const J &j, const Sink &s, float eps2, int jidx, int self,
                                                   Comp<float, kValues<Order>> &A, Key &gmin) {
     float dx, dy, dz;
     const float r2 = diff_r2(j, s, dx, dy, dz);
@@ -307,8 +308,10 @@ struct Mixed {
       A.part[6] -= mr;
       A.part[7] += a2x; A.part[8] += a2y; A.part[9] += a2z;
     }
-    const Key key = key_of(r2);
+    Key key = key_of(r2);
+    if constexpr (Guard) key = jidx != self ? key : ~Key(0);
     gmin = key < gmin ? key : gmin;
+    return r2;
   }
 };
 
@@ -424,8 +427,9 @@ struct F64 {
     return key_of(diff_r2(j, s, dx, dy, dz));
   }
 
+  // One pair; returns the unsoftened |r|^2 (for the neighbour-list test).
   template <bool Guard>
-  __device__ static __forceinline__ void interact(const J &j, const Sink &s, double eps2, int jidx, int self,
+  __device__ static __forceinline__ double interact(const J &j, const Sink &s, double eps2, int jidx, int self,
                                                   Comp<double, kValues<Order>> &A, Key &gmin) {
     double dx, dy, dz;
     const double r2 = diff_r2(j, s, dx, dy, dz);
@@ -474,8 +478,10 @@ struct F64 {
       A.part[6] -= mr;
       A.part[7] += a2x; A.part[8] += a2y; A.part[9] += a2z;
     }
-    const Key key = key_of(r2);
+    Key key = key_of(r2);
+    if constexpr (Guard) key = jidx != self ? key : ~Key(0);
     gmin = key < gmin ? key : gmin;
+    return r2;
   }
 };
 
@@ -566,8 +572,9 @@ __device__ __forceinline__ void group_reduce(int gs, double (&v)[P][K], uint64_t
 // ---------------------------------------------------------------------------------------------
 template <int Order>
 __device__ void finalize_sink(const ForceParams &fp, int q, const double *v, int idx) {
-  const int addr = fp.i_addr[q];
-  if (addr < 0 || addr >= fp.nj) {
+  const bool ext = fp.ext_x != nullptr;
+  const int addr = ext ? -1 : fp.i_addr[q];
+  if (!ext && (addr < 0 || addr >= fp.nj)) {
     atomicAdd(&fp.err[0], 1);
     return;
   }
@@ -580,7 +587,12 @@ __device__ void finalize_sink(const ForceParams &fp, int q, const double *v, int
   fp.pot[q] = v[6];
   if (idx >= 0 && idx < fp.nj) {
     double xi[3], vi[3], ai[3], mi, xj[3], vj[3], aj[3], mj;
-    predict_addr<Order>(fp.src, addr, fp.t, xi, vi, ai, mi);
+    if (ext) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) xi[k] = fp.ext_x[3 * (size_t)q + k];
+    } else {
+      predict_addr<Order>(fp.src, addr, fp.t, xi, vi, ai, mi);
+    }
     predict_addr<Order>(fp.src, idx, fp.t, xj, vj, aj, mj);
     double r2;
     {
@@ -603,9 +615,18 @@ __device__ void finalize_sink(const ForceParams &fp, int q, const double *v, int
 // nearest-neighbour key is kept, and after the group the (key, first source of the group) pair
 // replaces the running best if the key is smaller.  The exact source is found afterwards by
 // re-scanning that one group (nn_rescan).  L1: one lane per sink (compile-time offsets).
-template <class Tr, int P, bool Guard, bool L1>
-__device__ __forceinline__ void tile_compute(const typename Tr::Tile &tl, int slot, int lg, int jb,
-                                             const typename Tr::Sink (&sink)[P], const int (&self)[P],
+// Nbr: neighbour lists; each source with |r|^2 < h2 (strict, never the sink's own source, never
+// padding) is appended to the sink's list through an atomic counter.  Sinks without a list slot
+// carry h2 = -1 and never append.
+__device__ __forceinline__ void nbr_append(const ForceParams &fp, int q, int jj) {
+  const int k = atomicAdd(&fp.nbr_count[q], 1);
+  if (k < fp.nbr_max) fp.nbr_ids[(size_t)q * fp.nbr_max + k] = fp.src.id[jj];
+}
+
+template <class Tr, int P, bool Guard, bool L1, bool Nbr>
+__device__ __forceinline__ void tile_compute(const ForceParams &fp, const typename Tr::Tile &tl, int slot, int lg,
+                                             int jb, const typename Tr::Sink (&sink)[P], const int (&self)[P],
+                                             const int (&q)[P], const typename Tr::Real (&h2)[P],
                                              typename Tr::Real eps2,
                                              Comp<typename Tr::Real, Tr::kK> (&acc)[P],
                                              typename Tr::Key (&nnk)[P], int (&nng)[P]) {
@@ -622,7 +643,12 @@ __device__ __forceinline__ void tile_compute(const typename Tr::Tile &tl, int sl
       const typename Tr::J j = Tr::load(tl, e);
       const int jidx = L1 ? jb + u : jb + (u << lg);
 #pragma unroll
-      for (int p = 0; p < P; ++p) Tr::template interact<Guard>(j, sink[p], eps2, jidx, self[p], acc[p], gmin[p]);
+      for (int p = 0; p < P; ++p) {
+        const typename Tr::Real r2 = Tr::template interact<Guard>(j, sink[p], eps2, jidx, self[p], acc[p], gmin[p]);
+        if constexpr (Nbr) {
+          if (r2 < h2[p] && jidx < fp.nj && (!Guard || jidx != self[p])) nbr_append(fp, q[p], jidx);
+        }
+      }
     }
     const int g0 = L1 ? jb + c : jb + (c << lg);
 #pragma unroll
@@ -663,13 +689,13 @@ __device__ __forceinline__ typename Tr::J staged_j(const ForceParams &fp, int jj
 // and lane stride L identify the group; its length is min(kChunkAcc, 256 / L)).
 template <class Tr, int Order>
 __device__ __forceinline__ int nn_rescan(const ForceParams &fp, const typename Tr::Sink &s, typename Tr::Key key,
-                                         int g0, int lg) {
+                                         int g0, int lg, int self) {
   if (g0 < 0) return -1;
   const int per = kTile >> lg;
   const int len = per < kChunkAcc ? per : kChunkAcc;
   for (int k = 0; k < len; ++k) {
     const int jj = g0 + (k << lg);
-    if (Tr::nn_key(staged_j<Tr, Order>(fp, jj), s) == key) return jj;
+    if (jj != self && Tr::nn_key(staged_j<Tr, Order>(fp, jj), s) == key) return jj;
   }
   return -1;  // not reached: the group's minimum key comes from one of its sources
 }
@@ -679,7 +705,7 @@ __device__ __forceinline__ int nn_rescan(const ForceParams &fp, const typename T
 // source split w % S (split-fastest, so with S a multiple of 8 every split stays on one XCD and
 // its sources stay in that XCD's L2).
 // ---------------------------------------------------------------------------------------------
-template <int Order, int Prec, int P, bool L1>
+template <int Order, int Prec, int P, bool L1, bool Nbr>
 __global__ __launch_bounds__(kThreads) void k_force(const ForceParams fp) {
   using Tr = typename TraitsSel<Order, Prec>::type;
   using T = typename Tr::Real;
@@ -707,16 +733,30 @@ __global__ __launch_bounds__(kThreads) void k_force(const ForceParams fp) {
   Key nnk[P];
   int nng[P];  // first source of the group holding the best key (-1: none yet)
   int q[P];
-  int self[P];  // own source address of each sink (-1: no sink in this slot)
+  int self[P];  // own source address of each sink (-1: none, or no sink in this slot)
+  T h2[P];
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     q[p] = ib * Q + p * G + grp;
-    int addr = q[p] < fp.ni ? fp.i_addr[q[p]] : -1;
-    if (addr >= fp.nj) addr = -1;  // bad addresses are reported by finalize_sink
-    self[p] = addr;
-    double xp[3], vp[3], ap[3], m;
-    predict_addr<Order>(fp.src, addr < 0 ? 0 : addr, fp.t, xp, vp, ap, m);
+    const bool live = q[p] < fp.ni;
+    double xp[3], vp[3], ap[3], m = 0.0;
+    if (fp.ext_x) {  // explicit sink state, used as given
+      const int qq = live ? q[p] : 0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        xp[k] = fp.ext_x[3 * (size_t)qq + k];
+        vp[k] = fp.ext_v[3 * (size_t)qq + k];
+        ap[k] = (Order == 6) ? fp.ext_a[3 * (size_t)qq + k] : 0.0;
+      }
+      self[p] = live ? fp.ext_self[qq] : -1;
+    } else {  // by address: the sink's own predicted source state
+      int addr = live ? fp.i_addr[q[p]] : -1;
+      if (addr < 0 || addr >= fp.nj) addr = -1;  // bad addresses are reported by finalize_sink
+      self[p] = addr;
+      predict_addr<Order>(fp.src, addr < 0 ? 0 : addr, fp.t, xp, vp, ap, m);
+    }
     sink[p] = Tr::make_sink(xp, vp, ap, m);
+    h2[p] = (Nbr && live) ? (T)fp.h2[q[p]] : T(-1);
     acc[p].init();
     nnk[p] = ~Key(0);
     nng[p] = -1;
@@ -751,9 +791,11 @@ __global__ __launch_bounds__(kThreads) void k_force(const ForceParams fp) {
 #pragma unroll
     for (int p = 0; p < P; ++p) mine |= (self[p] >> 8) == tile;  // kTile == 256
     if (__any(mine))
-      tile_compute<Tr, P, true, L1>(tiles[buf], slot, lg, tile * kTile + slot, sink, self, eps2, acc, nnk, nng);
+      tile_compute<Tr, P, true, L1, Nbr>(fp, tiles[buf], slot, lg, tile * kTile + slot, sink, self, q, h2, eps2, acc,
+                                         nnk, nng);
     else
-      tile_compute<Tr, P, false, L1>(tiles[buf], slot, lg, tile * kTile + slot, sink, self, eps2, acc, nnk, nng);
+      tile_compute<Tr, P, false, L1, Nbr>(fp, tiles[buf], slot, lg, tile * kTile + slot, sink, self, q, h2, eps2, acc,
+                                          nnk, nng);
     if (tile + 1 < t1) stage(tile + 1, buf ^ 1);
     __syncthreads();
   }
@@ -768,7 +810,7 @@ __global__ __launch_bounds__(kThreads) void k_force(const ForceParams fp) {
 #pragma unroll
     for (int k = 0; k < K; ++k) v[p][k] = (double)acc[p].hi[k] + (double)acc[p].lo[k];
     kk[p] = (uint64_t)nnk[p];
-    ii[p] = nn_rescan<Tr, Order>(fp, sink[p], nnk[p], nng[p], lg);
+    ii[p] = nn_rescan<Tr, Order>(fp, sink[p], nnk[p], nng[p], lg, self[p]);
   }
   group_reduce<P, K>(L, v, kk, ii, red);
 
@@ -830,6 +872,40 @@ __global__ __launch_bounds__(kThreads) void k_combine(const ForceParams fp, int 
   }
   group_reduce<1, K>(R, w, wk, wi, red);
   if (r == 0 && qg < fp.ni) finalize_sink<Order>(fp, qg, w[0], wi[0]);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Explicit sinks: address of the source carrying each sink's id (first match), or -1.  Sources
+// are scanned in LDS tiles of 256 ids.
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_selfmap(SourceArrays src, int nj, int ni, const int64_t *ext_id,
+                                                      int32_t *self) {
+  __shared__ int64_t ids[kTile];
+  const int q = blockIdx.x * kThreads + threadIdx.x;
+  const int64_t mine = q < ni ? ext_id[q] : 0;
+  int found = -1;
+  for (int base = 0; base < nj; base += kTile) {
+    const int jj = base + (int)threadIdx.x;
+    __syncthreads();
+    ids[threadIdx.x] = jj < nj ? src.id[jj] : 0;
+    __syncthreads();
+    const int n = nj - base < kTile ? nj - base : kTile;
+    if (found < 0) {
+      for (int k = 0; k < n; ++k) {
+        if (ids[k] == mine) {
+          found = base + k;
+          break;
+        }
+      }
+    }
+  }
+  if (q < ni) self[q] = found;
+}
+
+// Neighbour-list overflow: any count above nbr_max raises err[2].
+__global__ __launch_bounds__(256) void k_nbr_check(const int32_t *count, int ni, int nbr_max, int *err) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < ni && count[q] > nbr_max) atomicAdd(&err[2], 1);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -996,8 +1072,20 @@ LaunchShape choose_shape(int ni, int nj_pad) {
 
 template <int Order, int Prec, int P, bool L1>
 static hipError_t launch_force_t(const ForceParams &fp, const LaunchShape &ls, hipStream_t stream) {
-  hipLaunchKernelGGL((k_force<Order, Prec, P, L1>), dim3(ls.blocks * ls.splits), dim3(kThreads), 0, stream, fp);
+  const dim3 grid(ls.blocks * ls.splits), block(kThreads);
+  if (fp.h2) {
+    hipError_t e = launch_fill_i32(fp.nbr_count, fp.ni, 0, stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_force<Order, Prec, P, L1, true>), grid, block, 0, stream, fp);
+  } else {
+    hipLaunchKernelGGL((k_force<Order, Prec, P, L1, false>), grid, block, 0, stream, fp);
+  }
   hipError_t e = hipGetLastError();
+  if (e == hipSuccess && fp.h2) {
+    hipLaunchKernelGGL(k_nbr_check, dim3((fp.ni + 255) / 256), dim3(256), 0, stream, fp.nbr_count, fp.ni, fp.nbr_max,
+                       fp.err);
+    e = hipGetLastError();
+  }
   if (e != hipSuccess || ls.splits <= 1) return e;
   int rlog = 0;
   while ((1 << rlog) < ls.splits && rlog < 8) ++rlog;
@@ -1069,6 +1157,13 @@ hipError_t launch_gather_j(int order, const SourceArrays &src, int n, const int3
   else
     hipLaunchKernelGGL(k_gather_j<6>, dim3(grid_for(n)), dim3(256), 0, stream, src, n, addr, id, m, t, x, v, a,
                        jerk, snap, crackle);
+  return hipGetLastError();
+}
+
+hipError_t launch_selfmap(const SourceArrays &src, int nj, int ni, const int64_t *ext_id, int32_t *self,
+                          hipStream_t stream) {
+  if (ni <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_selfmap, dim3(grid_for(ni)), dim3(kThreads), 0, stream, src, nj, ni, ext_id, self);
   return hipGetLastError();
 }
 

@@ -46,6 +46,7 @@ struct nbx_ctx {
   double *d_h2 = nullptr;
   int64_t *d_ext_id = nullptr;
   double *d_ext_x = nullptr, *d_ext_v = nullptr, *d_ext_a = nullptr;
+  int32_t *d_ext_self = nullptr;
   double *d_acc = nullptr, *d_jrk = nullptr, *d_snp = nullptr, *d_pot = nullptr, *d_nnr2 = nullptr;
   int64_t *d_nnid = nullptr;
   int32_t *d_nbr_cnt = nullptr;
@@ -147,15 +148,13 @@ int check_ctx(nbx_ctx *c) {
 }
 
 // Shared by the host and device force paths.
-int enqueue_force(nbx_ctx *c, hipStream_t stream, int ni, const int32_t *d_iaddr, const int64_t *ext_id,
-                  const double *ext_x, const double *ext_v, const double *ext_a, double eps2,
-                  const double *d_h2, double *acc, double *jrk, double *snp, double *pot, int64_t *nn_id,
-                  double *nn_r2, int32_t *nbr_cnt, int64_t *nbr_ids) {
+int enqueue_force(nbx_ctx *c, hipStream_t stream, int ni, const int32_t *d_iaddr, const int32_t *ext_self,
+                  const int64_t *ext_id, const double *ext_x, const double *ext_v, const double *ext_a,
+                  double eps2, const double *d_h2, double *acc, double *jrk, double *snp, double *pot,
+                  int64_t *nn_id, double *nn_r2, int32_t *nbr_cnt, int64_t *nbr_ids) {
   if (!c->predicted) return fail(c, NBX_ERR_STATE, "nbx_force before nbx_predict");
   if (!(eps2 >= 0.0)) return fail(c, NBX_ERR_ARG, "eps2 must be >= 0 (got %g)", eps2);
   if (ni == 0) return NBX_OK;
-  if (ext_x) return fail(c, NBX_ERR_STATE, "explicit sinks are not supported by this build");
-  if (d_h2) return fail(c, NBX_ERR_STATE, "neighbour lists are not supported by this build");
   const int nj_pad = (c->nj + kTile - 1) / kTile * kTile;
   const LaunchShape ls = choose_shape(ni, nj_pad);
   int rc = ensure_scratch(c, ni, ls);
@@ -168,6 +167,7 @@ int enqueue_force(nbx_ctx *c, hipStream_t stream, int ni, const int32_t *d_iaddr
   fp.eps2 = eps2;
   fp.ni = ni;
   fp.i_addr = d_iaddr;
+  fp.ext_self = ext_self;
   fp.ext_id = ext_id;
   fp.ext_x = ext_x;
   fp.ext_v = ext_v;
@@ -267,6 +267,11 @@ int nbx_open(nbx_ctx **out, const nbx_config *cfg) {
   rc = rc ? rc : alloc_n(c, &c->d_pot, ni);
   rc = rc ? rc : alloc_n(c, &c->d_nnid, ni);
   rc = rc ? rc : alloc_n(c, &c->d_nnr2, ni);
+  if (cfg->nbr_max > 0) {
+    rc = rc ? rc : alloc_n(c, &c->d_h2, ni);
+    rc = rc ? rc : alloc_n(c, &c->d_nbr_cnt, ni);
+    rc = rc ? rc : alloc_n(c, &c->d_nbr_ids, ni * (size_t)cfg->nbr_max);
+  }
   rc = rc ? rc : alloc_n(c, &c->d_err, 4);
   if (rc) return bail(rc);
   hipError_t e = launch_pad(cfg->order, c->src, 0, cfg->nj_max, c->stream);
@@ -372,8 +377,10 @@ int nbx_force(nbx_ctx *c, int ni, const int32_t *i_addr, double eps2, const doub
       return fail(c, NBX_ERR_ARG, "i_addr[%d]=%d outside [0, nj=%d)", k, i_addr[k], c->nj);
   if (h2 && c->cfg.nbr_max == 0) return fail(c, NBX_ERR_ARG, "neighbour lists need nbr_max > 0");
   if (ni > 0) HIP_TRY(c, hipMemcpyAsync(c->d_iaddr, i_addr, (size_t)ni * 4, hipMemcpyHostToDevice, c->stream));
-  int rc = enqueue_force(c, c->stream, ni, c->d_iaddr, nullptr, nullptr, nullptr, nullptr, eps2, nullptr, c->d_acc,
-                         c->d_jrk, c->d_snp, c->d_pot, c->d_nnid, c->d_nnr2, nullptr, nullptr);
+  if (ni > 0 && h2) HIP_TRY(c, hipMemcpyAsync(c->d_h2, h2, (size_t)ni * 8, hipMemcpyHostToDevice, c->stream));
+  int rc = enqueue_force(c, c->stream, ni, c->d_iaddr, nullptr, nullptr, nullptr, nullptr, nullptr, eps2,
+                         h2 ? c->d_h2 : nullptr, c->d_acc, c->d_jrk, c->d_snp, c->d_pot, c->d_nnid, c->d_nnr2,
+                         c->d_nbr_cnt, c->d_nbr_ids);
   if (rc < 0) return rc;
   c->last_ni = ni;
   c->last_nbr = h2 != nullptr;
@@ -383,8 +390,37 @@ int nbx_force(nbx_ctx *c, int ni, const int32_t *i_addr, double eps2, const doub
 int nbx_force_ext(nbx_ctx *c, int ni, const int64_t *id, const double *x, const double *v, const double *a,
                   double eps2, const double *h2) {
   if (int rc = check_ctx(c)) return rc;
-  (void)ni; (void)id; (void)x; (void)v; (void)a; (void)eps2; (void)h2;
-  return fail(c, NBX_ERR_STATE, "explicit sinks are not supported by this build");
+  if (ni < 0) return fail(c, NBX_ERR_ARG, "ni < 0");
+  if (ni > c->cfg.ni_max) return fail(c, NBX_ERR_CAPACITY, "ni=%d > ni_max=%d", ni, c->cfg.ni_max);
+  if (ni > 0 && (!id || !x || !v)) return fail(c, NBX_ERR_ARG, "NULL sink array");
+  if (ni > 0 && c->cfg.order == 6 && !a) return fail(c, NBX_ERR_ARG, "order 6 needs the sink accelerations");
+  if (h2 && c->cfg.nbr_max == 0) return fail(c, NBX_ERR_ARG, "neighbour lists need nbr_max > 0");
+  if (!c->d_ext_id) {  // explicit-sink buffers, allocated on first use
+    const size_t n = (size_t)c->cfg.ni_max;
+    int rc = alloc_n(c, &c->d_ext_id, n);
+    rc = rc ? rc : alloc_n(c, &c->d_ext_x, 3 * n);
+    rc = rc ? rc : alloc_n(c, &c->d_ext_v, 3 * n);
+    if (c->cfg.order == 6) rc = rc ? rc : alloc_n(c, &c->d_ext_a, 3 * n);
+    rc = rc ? rc : alloc_n(c, &c->d_ext_self, n);
+    if (rc) return rc;
+  }
+  const size_t n = (size_t)ni;
+  hipStream_t s = c->stream;
+  if (ni > 0) {
+    HIP_TRY(c, hipMemcpyAsync(c->d_ext_id, id, n * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(c->d_ext_x, x, n * 24, hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(c->d_ext_v, v, n * 24, hipMemcpyHostToDevice, s));
+    if (c->cfg.order == 6) HIP_TRY(c, hipMemcpyAsync(c->d_ext_a, a, n * 24, hipMemcpyHostToDevice, s));
+    if (h2) HIP_TRY(c, hipMemcpyAsync(c->d_h2, h2, n * 8, hipMemcpyHostToDevice, s));
+    if (c->predicted) HIP_TRY(c, launch_selfmap(c->src, c->nj, ni, c->d_ext_id, c->d_ext_self, s));
+  }
+  int rc = enqueue_force(c, s, ni, nullptr, c->d_ext_self, c->d_ext_id, c->d_ext_x, c->d_ext_v,
+                         c->cfg.order == 6 ? c->d_ext_a : nullptr, eps2, h2 ? c->d_h2 : nullptr, c->d_acc,
+                         c->d_jrk, c->d_snp, c->d_pot, c->d_nnid, c->d_nnr2, c->d_nbr_cnt, c->d_nbr_ids);
+  if (rc < 0) return rc;
+  c->last_ni = ni;
+  c->last_nbr = h2 != nullptr;
+  return rc;
 }
 
 int nbx_get_force(nbx_ctx *c, double *acc, double *jerk, double *snap, double *pot, int64_t *nn_id,
@@ -407,8 +443,19 @@ int nbx_get_force(nbx_ctx *c, double *acc, double *jerk, double *snap, double *p
 
 int nbx_get_nbr(nbx_ctx *c, int32_t *count, int64_t *ids) {
   if (int rc = check_ctx(c)) return rc;
-  (void)count; (void)ids;
-  return fail(c, NBX_ERR_STATE, "neighbour lists are not supported by this build");
+  if (c->last_ni < 0 || !c->last_nbr) return fail(c, NBX_ERR_STATE, "the last force call computed no neighbour lists");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const size_t n = (size_t)c->last_ni;
+  if (n == 0) return NBX_OK;
+  std::vector<int32_t> cnt(n);
+  HIP_TRY(c, hipMemcpy(cnt.data(), c->d_nbr_cnt, n * 4, hipMemcpyDeviceToHost));
+  if (count) std::memcpy(count, cnt.data(), n * 4);
+  if (ids) HIP_TRY(c, hipMemcpy(ids, c->d_nbr_ids, n * (size_t)c->cfg.nbr_max * 8, hipMemcpyDeviceToHost));
+  const int rc = collect_errors(c);
+  if (rc < 0) return rc;
+  for (size_t k = 0; k < n; ++k)
+    if (cnt[k] > c->cfg.nbr_max) return NBX_WARN_NBR_OVERFLOW;
+  return rc;
 }
 
 int nbx_get_predicted(nbx_ctx *c, int n, const int32_t *addr, double *xp, double *vp, double *ap) {
@@ -505,8 +552,8 @@ int nbx_force_dev(nbx_ctx *c, void *stream, int ni, const int32_t *d_i_addr, dou
   if (d_h2 && (c->cfg.nbr_max == 0 || !d_nbr_count || !d_nbr_ids))
     return fail(c, NBX_ERR_ARG, "neighbour lists need nbr_max > 0 and count/id arrays");
   if (c->nj < 1) return fail(c, NBX_ERR_STATE, "no sources in use (nbx_set_nj)");
-  return enqueue_force(c, static_cast<hipStream_t>(stream), ni, d_i_addr, nullptr, nullptr, nullptr, nullptr, eps2,
-                       d_h2, d_acc, d_jerk, d_snap, d_pot, d_nn_id, d_nn_r2, d_nbr_count, d_nbr_ids);
+  return enqueue_force(c, static_cast<hipStream_t>(stream), ni, d_i_addr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                       eps2, d_h2, d_acc, d_jerk, d_snap, d_pot, d_nn_id, d_nn_r2, d_nbr_count, d_nbr_ids);
 }
 
 int nbx_sync(nbx_ctx *c, void *stream) {

@@ -221,7 +221,8 @@ def nbx_force_ext(ctx, id, x, v, a, eps2, h2=None):
     x = _f64(x)
     n = x.shape[0]
     id = np.ascontiguousarray(id, dtype=np.int64)
-    v, a = _f64(v, n), _f64(a, n)
+    v = _f64(v, n)
+    a = None if a is None else _f64(a, n)
     h2 = None if h2 is None else _f64(np.broadcast_to(np.asarray(h2, dtype=np.float64), (n,)), n, 0)
     return _check(ctx, load().nbx_force_ext(ctx, n, _ptr(id), _ptr(x), _ptr(v), _ptr(a), float(eps2), _ptr(h2)))
 
@@ -342,8 +343,16 @@ class Context:
         self._ni = len(i_addr)
         return nbx_force(self.ctx, i_addr, eps2, h2)
 
+    def force_ext(self, ids, x, v, a, eps2, h2=None):
+        self._ni = len(ids)
+        return nbx_force_ext(self.ctx, ids, x, v, a, eps2, h2)
+
     def get_force(self):
         return nbx_get_force(self.ctx, self._ni, self.order)
+
+    def get_nbr(self):
+        """(count[ni], ids[ni][nbr_max], status) of the last force call."""
+        return nbx_get_nbr(self.ctx, self._ni, self.nbr_max)
 
     def get_predicted(self, addr):
         return nbx_get_predicted(self.ctx, addr, self.order)

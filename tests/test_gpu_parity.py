@@ -258,3 +258,111 @@ def test_full_size_sampled(prec):
             ref = oracle_all(src, 4, eps2, t, addr=sel[pick])
             got = {k: (v[pick] if v is not None else None) for k, v in out.items() if k != "status"}
             _compare(got, ref, prec, 4, sel[pick], src.ids, "  ni=%d" % ni)
+
+
+def _pair_r2(xp, sink_x):
+    d = xp[None, :, :] - sink_x[:, None, :]
+    return np.sum(d * d, axis=2)
+
+
+@pytest.mark.parametrize("prec", [nbx.NBX_FP64, nbx.NBX_MIXED])
+@pytest.mark.parametrize("order", [4, 6])
+def test_neighbour_lists(order, prec):
+    """Neighbour sets equal the oracle's; in mixed precision pairs within 2e-6 relative of the
+    radius may fall either way."""
+    n, t, nbr_max = 3000, 0.0, 64
+    eps2 = 1e-4 if order == 4 else 1e-6
+    say("neighbour lists order=%d prec=%s" % (order, PREC_NAME[prec]))
+    src = nbody_ics.make_sources(n, seed=40, order=order, masses="salpeter" if order == 6 else "equal")
+    sel = nbody_ics.active_set(n, 1500, seed=41)
+    rng = np.random.default_rng(42)
+    h2 = rng.uniform(0.002, 0.01, size=len(sel))
+    ref = oracle_all(src, order, eps2, t, addr=sel, h2=h2, nbr_max=n)
+    with nbx.Context(order=order, precision=prec, nj_max=n, ni_max=n, nbr_max=nbr_max) as ctx:
+        ctx.set_sources(src)
+        ctx.predict(t)
+        ctx.force(sel, eps2, h2)
+        out = ctx.get_force()
+        cnt, ids, status = ctx.get_nbr()
+    _compare(out, ref, prec, order, sel, src.ids, "  with lists")
+    r2 = _pair_r2(ref["xp"], ref["xp"][sel])
+    total = 0
+    for i in range(len(sel)):
+        want = set(ref["nbr_ids"][i, : ref["nbr_count"][i]])
+        got = set(ids[i, : min(cnt[i], nbr_max)])
+        if prec == nbx.NBX_FP64:
+            assert cnt[i] == ref["nbr_count"][i], i
+        else:
+            border = set(src.ids[np.nonzero(np.abs(r2[i] - h2[i]) <= 2e-6 * h2[i])[0]])
+            assert want - border <= got | border and got - border <= want | border, i
+            assert abs(int(cnt[i]) - int(ref["nbr_count"][i])) <= len(border), i
+        if cnt[i] <= nbr_max:
+            assert got <= want | (set() if prec == nbx.NBX_FP64 else border)
+        total += cnt[i]
+    assert status in (nbx.NBX_OK, nbx.NBX_WARN_NBR_OVERFLOW)
+    assert (status == nbx.NBX_WARN_NBR_OVERFLOW) == bool(np.any(cnt > nbr_max))
+    say("  mean neighbours %.1f, max %d" % (total / len(sel), cnt.max()))
+
+
+def test_neighbour_overflow():
+    """A dense clump: counts stay exact, stored ids are a subset, the call warns."""
+    n, nbr_max = 600, 16
+    say("neighbour overflow")
+    src = nbody_ics.make_sources(n, seed=43)
+    src.x[:300] = src.x[:300] * 1e-3  # 300 sources within ~1e-3 of the centre
+    sel = np.arange(0, 300, 7, dtype=np.int32)
+    h2 = np.full(len(sel), 1e-2)
+    ref = oracle_all(src, 4, 1e-6, 0.0, addr=sel, h2=h2, nbr_max=n)
+    with nbx.Context(order=4, precision=nbx.NBX_FP64, nj_max=n, ni_max=n, nbr_max=nbr_max) as ctx:
+        ctx.set_sources(src)
+        ctx.predict(0.0)
+        ctx.force(sel, 1e-6, h2)
+        out = ctx.get_force()
+        cnt, ids, status = ctx.get_nbr()
+    assert out["status"] == nbx.NBX_WARN_NBR_OVERFLOW
+    assert status == nbx.NBX_WARN_NBR_OVERFLOW
+    np.testing.assert_array_equal(cnt, ref["nbr_count"])
+    for i in range(len(sel)):
+        want = set(ref["nbr_ids"][i, : ref["nbr_count"][i]])
+        got = list(ids[i, : min(cnt[i], nbr_max)])
+        assert len(set(got)) == len(got) and set(got) <= want
+
+
+@pytest.mark.parametrize("prec", [nbx.NBX_FP64, nbx.NBX_MIXED])
+@pytest.mark.parametrize("order", [4, 6])
+def test_explicit_sinks(order, prec):
+    """Sinks given explicitly: foreign ids feel every source; sinks carrying a source's id (at a
+    shifted position) exclude exactly that source."""
+    n, t = 2500, 0.0
+    eps2 = 1e-4
+    say("explicit sinks order=%d prec=%s" % (order, PREC_NAME[prec]))
+    src = nbody_ics.make_sources(n, seed=44, order=order)
+    xp, vp, ap = oracle.predict(order, t, src.t, src.x, src.v, src.a, src.jerk, src.snap, src.crackle)
+    rng = np.random.default_rng(45)
+    ni = 700
+    own = rng.choice(n, size=ni // 2, replace=False)
+    ids = np.concatenate([src.ids[own], np.arange(10**6, 10**6 + ni - ni // 2)]).astype(np.int64)
+    x = np.concatenate([xp[own] + rng.normal(0, 1e-3, (ni // 2, 3)), rng.normal(0, 0.5, (ni - ni // 2, 3))])
+    v = rng.normal(0, 0.5, (ni, 3))
+    a = rng.normal(0, 0.5, (ni, 3)) if order == 6 else None
+    h2 = np.full(ni, 4e-3)
+    ref = oracle.force(order, eps2, src.ids, src.m, xp, vp, ids, x, v, aj=ap if order == 6 else None, ai=a,
+                       h2=h2, nbr_max=n)
+    ref["xp"] = xp
+    with nbx.Context(order=order, precision=prec, nj_max=n, ni_max=ni, nbr_max=32) as ctx:
+        ctx.set_sources(src)
+        ctx.predict(t)
+        ctx.force_ext(ids, x, v, a, eps2, h2)
+        out = ctx.get_force()
+        cnt, nb, _ = ctx.get_nbr()
+    e_acc = rel_err_vec(out["acc"], ref["acc"])
+    e_pot = np.abs(out["pot"] - ref["pot"]) / np.abs(ref["pot"])
+    say("  ext: max rel acc %.2e pot %.2e" % (e_acc.max(), e_pot.max()))
+    assert e_acc.max() <= TOL[prec]["acc"] and e_pot.max() <= TOL[prec]["pot"]
+    assert not np.any(out["nn_id"] == ids)  # never the sink's own source
+    d = xp[out["nn_id"]] - x
+    np.testing.assert_allclose(out["nn_r2"], np.sum(d * d, axis=1), rtol=1e-13)
+    slack = 1e-14 if prec == nbx.NBX_FP64 else 4e-7
+    assert np.all(out["nn_r2"] <= ref["nn_r2"] * (1 + slack))
+    if prec == nbx.NBX_FP64:
+        np.testing.assert_array_equal(cnt, ref["nbr_count"])
