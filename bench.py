@@ -65,6 +65,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     ap.add_argument("--sweep-reps", type=int, default=5)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="run one plain device-to-device copy kernel of MIB MiB first (HBM counter calibration)")
+    ap.add_argument("--order6", action="store_true",
+                    help="also time 6th-order forces with neighbour lists on a 1048576-body Plummer/Salpeter "
+                         "cluster (eps2=1e-8, h2=1e-4, at most 256 neighbours), N_i in {1024, 65536, 1048576}")
     return ap.parse_args()
 
 
@@ -156,6 +161,60 @@ def cpu_baseline(src, seconds):
                       "against all %d sources (%.2e interactions, %.1f s)" % (N, ns, N, ns * float(N), dt)}
 
 
+def order6(torch, nbx, ics, dev, steps):
+    """Config-3 points: 6th order, Salpeter masses, neighbour lists; kernel time per precision."""
+    import numpy as np
+
+    n, eps2, h2, nbr_max = 1 << 20, 1e-8, 1e-4, 256
+    src = ics.make_sources(n, seed=3, order=6, masses="salpeter")
+    stream = torch.cuda.current_stream()
+    T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    f64, i64, i32 = torch.float64, torch.int64, torch.int32
+    ctx = nbx.Context(order=6, precision=nbx.NBX_MIXED, nj_max=n, ni_max=n, nbr_max=nbr_max)
+    nbx.nbx_set_j_dev(ctx.ctx, stream, n, T(np.arange(n), i32), T(src.ids, i64), T(src.m, f64), T(src.t, f64),
+                      T(src.x, f64), T(src.v, f64), T(src.a, f64), T(src.jerk, f64), T(src.snap, f64),
+                      T(src.crackle, f64))
+    nbx.nbx_set_nj(ctx.ctx, n)
+    nbx.nbx_predict(ctx.ctx, 0.0)
+    out = [torch.empty((n, 3), dtype=f64, device=dev) for _ in range(3)]
+    pot, nnr2 = torch.empty(n, dtype=f64, device=dev), torch.empty(n, dtype=f64, device=dev)
+    nnid, cnt = torch.empty(n, dtype=i64, device=dev), torch.empty(n, dtype=i32, device=dev)
+    ids = torch.empty((n, nbr_max), dtype=i64, device=dev)
+    d_h2 = torch.full((n,), h2, dtype=f64, device=dev)
+    rows = []
+    for ni in (1024, 65536, n):
+        sel = T(ics.active_set(n, ni, seed=1003), i32)
+        row = {"ni": ni}
+        for prec, name in ((nbx.NBX_FP64, "fp64"), (nbx.NBX_MIXED, "mixed")):
+            ctx.set_precision(prec)
+            reps = 1 if ni == n else steps
+
+            def go():
+                nbx.nbx_force_dev(ctx.ctx, stream, ni, sel, eps2, d_h2, out[0], out[1], out[2], pot, nnid, nnr2,
+                                  cnt, ids)
+
+            go()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                go()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            row[name + "_kernel_ms"] = round(ms, 4)
+            row[name + "_int_s"] = float("%.4g" % (ni * float(n) / (ms * 1e-3)))
+        row["speedup"] = round(row["fp64_kernel_ms"] / row["mixed_kernel_ms"], 3)
+        row["mean_neighbours"] = round(float(cnt[:ni].double().mean().item()), 3)
+        rows.append(row)
+        print("bench: order6 %s" % json.dumps(row), file=sys.stderr, flush=True)
+    status = nbx.nbx_sync(ctx.ctx, stream)
+    ctx.close()
+    return {"workload": "Plummer N=1048576, Salpeter masses (slope -2.35, 0.1-100, total 1), eps2=1e-8, "
+                        "6th-order acc+jerk+snap+pot+NN+neighbour lists (h2=1e-4, max 256)",
+            "flops_per_interaction": 79, "rows": rows, "list_status": status}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -172,6 +231,17 @@ def main():
         sys.exit(3)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
+    if args.copy_calibration > 0:
+        nbytes = args.copy_calibration << 20
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        evict = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB: pushes a out of the 256 MB MALL
+        del evict
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print("bench: copy calibration read %d B, wrote %d B" % (nbytes, nbytes), file=sys.stderr, flush=True)
+        del a, b
     w = Workload(torch, nbx, nbody_ics, dev)
     ctx = nbx.Context(order=4, precision=nbx.NBX_MIXED, nj_max=N, ni_max=N)
     d = w.d
@@ -212,6 +282,8 @@ def main():
             print("bench: sweep %s" % json.dumps(row), file=sys.stderr, flush=True)
     nbx.nbx_sync(ctx.ctx, stream)
     ctx.close()
+
+    o6 = order6(torch, nbx, nbody_ics, dev, max(2, args.steps // 10)) if args.order6 else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -260,6 +332,8 @@ def main():
         "cpu_baseline": cpu,
         "sweep": sweep,
     }
+    if o6 is not None:
+        line["order6"] = o6
     print(json.dumps(line), flush=True)
 
 

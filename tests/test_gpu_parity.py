@@ -366,3 +366,38 @@ def test_explicit_sinks(order, prec):
     assert np.all(out["nn_r2"] <= ref["nn_r2"] * (1 + slack))
     if prec == nbx.NBX_FP64:
         np.testing.assert_array_equal(cnt, ref["nbr_count"])
+
+
+@pytest.mark.parametrize("prec", [nbx.NBX_FP64, nbx.NBX_MIXED])
+def test_order6_million_sampled(prec):
+    """1048576-body Plummer cluster with Salpeter masses, eps2 = 1e-8, 6th order with neighbour
+    lists (h2 = 1e-4, at most 256): the launch shapes of N_i = 1024, 65536 and N, checked on
+    sampled sinks against the oracle (forces, nearest neighbour and neighbour sets)."""
+    n, eps2, h2v, nbr_max = 1 << 20, 1e-8, 1e-4, 256
+    say("order6 1M prec=%s" % PREC_NAME[prec])
+    src = nbody_ics.make_sources(n, seed=3, order=6, masses="salpeter")
+    rng = np.random.default_rng(78)
+    with nbx.Context(order=6, precision=prec, nj_max=n, ni_max=n, nbr_max=nbr_max) as ctx:
+        ctx.set_sources(src)
+        ctx.predict(0.0)
+        for ni in (1024, 65536, n):
+            sel = nbody_ics.active_set(n, ni, seed=1003)
+            say("  ni=%d shape=%s" % (ni, ctx.launch_shape(ni)))
+            ctx.force(sel, eps2, np.full(ni, h2v))
+            out = ctx.get_force()
+            cnt, ids, status = ctx.get_nbr()
+            pick = np.sort(rng.choice(ni, size=96, replace=False))
+            ref = oracle_all(src, 6, eps2, 0.0, addr=sel[pick], h2=np.full(96, h2v), nbr_max=n)
+            got = {k: (v[pick] if v is not None else None) for k, v in out.items() if k != "status"}
+            _compare(got, ref, prec, 6, sel[pick], src.ids, "  ni=%d" % ni)
+            r2 = _pair_r2(ref["xp"], ref["xp"][sel[pick]])
+            for a, i in enumerate(pick):
+                want = set(ref["nbr_ids"][a, : ref["nbr_count"][a]])
+                have = set(ids[i, : min(cnt[i], nbr_max)])
+                if prec == nbx.NBX_FP64:
+                    assert cnt[i] == ref["nbr_count"][a]
+                    assert have == want or cnt[i] > nbr_max
+                else:
+                    border = set(src.ids[np.nonzero(np.abs(r2[a] - h2v) <= 2e-6 * h2v)[0]])
+                    assert want - border <= have | border
+            say("  ni=%d mean neighbours %.2f max %d status %d" % (ni, cnt.mean(), cnt.max(), status))
