@@ -67,6 +67,9 @@ def parse():
     ap.add_argument("--sweep-reps", type=int, default=5)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run one plain device-to-device copy kernel of MIB MiB first (HBM counter calibration)")
+    ap.add_argument("--batch", action="store_true",
+                    help="also time 4096 independent few-body Plummer systems (3..96 particles, eps2=0, 4th order) "
+                         "in one persistent launch, default and autotuned lane mappings")
     ap.add_argument("--order6", action="store_true",
                     help="also time 6th-order forces with neighbour lists on a 1048576-body Plummer/Salpeter "
                          "cluster (eps2=1e-8, h2=1e-4, at most 256 neighbours), N_i in {1024, 65536, 1048576}")
@@ -215,6 +218,49 @@ def order6(torch, nbx, ics, dev, steps):
             "flops_per_interaction": 79, "rows": rows, "list_status": status}
 
 
+def batch(torch, nbx, ics, dev, steps):
+    """Batched few-body systems: one persistent launch; FP64 and mixed; default and tuned L."""
+    import numpy as np
+
+    n_sys, eps2 = 4096, 0.0
+    sizes = ics.few_body_sizes(n_sys, 4)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    parts = [ics.plummer(int(n), seed=10000 + s) for s, n in enumerate(sizes)]
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    m = T(np.concatenate([p[0] for p in parts]))
+    x, v = T(np.concatenate([p[1] for p in parts])), T(np.concatenate([p[2] for p in parts]))
+    n = int(off[-1])
+    acc, jrk = torch.empty((n, 3), dtype=torch.float64, device=dev), torch.empty((n, 3), dtype=torch.float64, device=dev)
+    pot = torch.empty(n, dtype=torch.float64, device=dev)
+    inter = float(np.sum(sizes.astype(np.float64) ** 2))
+    stream = torch.cuda.current_stream()
+    res = {"workload": "4096 Plummer systems, N uniform in [3,96] (seed 4), eps2=0, 4th-order acc+jerk+pot, one "
+                       "persistent launch", "interactions": inter, "particles": n}
+    for prec, name in ((nbx.NBX_FP64, "fp64"), (nbx.NBX_MIXED, "mixed")):
+        ctx = nbx.Context(order=4, precision=prec, nj_max=1, ni_max=1)
+        nbx.nbx_batch_setup(ctx.ctx, off)
+        for tuned in (False, True):
+            if tuned:
+                lanes = nbx.nbx_batch_tune(ctx.ctx, stream, m, x, v, eps2, acc, jrk, pot)
+                res[name + "_lanes_per_class"] = [int(l) for l in lanes]
+            for _ in range(3):
+                nbx.nbx_batch_force_dev(ctx.ctx, stream, m, x, v, eps2, acc, jrk, pot)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                nbx.nbx_batch_force_dev(ctx.ctx, stream, m, x, v, eps2, acc, jrk, pot)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) / steps * 1e3
+            key = name + ("_tuned" if tuned else "_default")
+            res[key + "_us"] = round(us, 3)
+            res[key + "_int_s"] = float("%.4g" % (inter / (us * 1e-6)))
+        ctx.close()
+    print("bench: batch %s" % json.dumps(res), file=sys.stderr, flush=True)
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -284,6 +330,7 @@ def main():
     ctx.close()
 
     o6 = order6(torch, nbx, nbody_ics, dev, max(2, args.steps // 10)) if args.order6 else None
+    bt = batch(torch, nbx, nbody_ics, dev, max(20, args.steps)) if args.batch else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -334,6 +381,8 @@ def main():
     }
     if o6 is not None:
         line["order6"] = o6
+    if bt is not None:
+        line["batch"] = bt
     print(json.dumps(line), flush=True)
 
 

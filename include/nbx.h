@@ -34,8 +34,9 @@
  * the other source with the smallest |r|^2, returned as (id, |r|^2 in FP64);
  * none: id -1, r2 +inf.  In NBX_FP64 the choice is made on the exact FP64
  * |r|^2 (ties to the lower source address); in NBX_MIXED it is made on the
- * FP32 value of R^2, so sources whose R^2 agree to FP32 rounding may be
- * returned in either order.  Neighbour list (Background; Results, perturber
+ * FP32 value of |r|^2, so sources whose |r|^2 agree to FP32 rounding may be
+ * returned in either order.  A distinct source at exactly r = 0 is never
+ * reported (its key equals the sink's own).  Neighbour list (Background; Results, perturber
  * lists): every other source with |r|^2 < h2_i, at most nbr_max per sink;
  * the count is exact, and when it exceeds nbr_max the stored ids are an
  * unspecified subset and the call returns NBX_WARN_NBR_OVERFLOW.
@@ -187,6 +188,33 @@ int nbx_force_dev(nbx_ctx *ctx, void *stream, int ni, const int32_t *d_i_addr, d
                   const double *d_h2, double *d_acc, double *d_jerk, double *d_snap,
                   double *d_pot, int64_t *d_nn_id, double *d_nn_r2, int32_t *d_nbr_count,
                   int64_t *d_nbr_ids);
+
+/* ---- batched few-body systems (4th order: acc, jerk, pot) -------------------------------------
+ * Many independent small systems in one persistent launch.  System s holds the particles
+ * [offsets[s], offsets[s+1]) of flat device arrays; every particle is a sink and a source of its
+ * own system only, its own term excluded; the state is used as given (no prediction).  eps2 >= 0
+ * (0 is allowed: coincident distinct particles give inf/NaN).  Precision follows the context.
+ * This extends the paper's aim of keeping the GPU busy when only a few particles are integrated
+ * (Abstract; Discussion > CPU: small N favours the CPU). */
+#define NBX_BATCH_NMAX 128 /* largest system of a batch */
+
+/* Describe the batch: n_sys >= 1 systems, host offsets[n_sys + 1] with offsets[0] = 0 and every
+ * size offsets[s+1] - offsets[s] in [1, NBX_BATCH_NMAX] (else NBX_ERR_ARG).  Builds the wave
+ * schedule on the host (largest systems first) and uploads it.  Synchronous. */
+int nbx_batch_setup(nbx_ctx *ctx, int n_sys, const int32_t *offsets);
+
+/* Autotuner: for every size class present (n in (2^(c-1), 2^c], c = 0..7) time each
+ * lanes-per-sink option L = 1..64 on the given device data with HIP events, keep the fastest in
+ * the context and rebuild the schedule.  Writes the outputs as a side effect.  Synchronous.
+ * lanes_per_class[8] (may be NULL) receives the chosen L per class (0: class absent). */
+int nbx_batch_tune(nbx_ctx *ctx, void *stream, const double *d_m, const double *d_x, const double *d_v,
+                   double eps2, double *d_acc, double *d_jerk, double *d_pot, int32_t *lanes_per_class);
+
+/* Forces within every system: d_m [n], d_x, d_v [n][3] in, d_acc, d_jerk [n][3] and d_pot [n]
+ * out (n = offsets[n_sys]).  Enqueue only.  Without nbx_batch_tune a default L per class is used
+ * (L = 64 / next power of two of the class's largest size, at least 1). */
+int nbx_batch_force_dev(nbx_ctx *ctx, void *stream, const double *d_m, const double *d_x, const double *d_v,
+                        double eps2, double *d_acc, double *d_jerk, double *d_pot);
 
 /* Wait for all work this context enqueued (on its own stream and on stream) and report
  * device-side argument errors (NBX_ERR_ARG) or neighbour-list overflow (NBX_WARN_NBR_OVERFLOW)

@@ -70,6 +70,22 @@ struct ForceParams {
   int *err;            // device-side error counters: [0] bad sink address, [1] bad source address
 };
 
+// Batched few-body systems: particles of system s are [offset[s], offset[s+1]); items[k] =
+// (system, lanes_log2), one wave per item, in schedule order.
+constexpr int kBatchMax = 128;  // largest system of a batch
+struct BatchParams {
+  int n_items;
+  const int2 *items;
+  const int32_t *offset;
+  const double *m;
+  const double *x;
+  const double *v;
+  double eps2;
+  double *acc;
+  double *jrk;
+  double *pot;
+};
+
 struct LaunchShape {
   int lanes_log2;
   int sinks_per_lane;
@@ -92,6 +108,7 @@ hipError_t launch_gather_j(int order, const SourceArrays &src, int n, const int3
                            int64_t *id, double *m, double *t, double *x, double *v, double *a,
                            double *jerk, double *snap, double *crackle, hipStream_t stream);
 hipError_t launch_fill_i32(int32_t *p, int n, int value, hipStream_t stream);
+hipError_t launch_batch(int precision, const BatchParams &bp, int grid, hipStream_t stream);
 hipError_t launch_selfmap(const SourceArrays &src, int nj, int ni, const int64_t *ext_id, int32_t *self,
                           hipStream_t stream);
 

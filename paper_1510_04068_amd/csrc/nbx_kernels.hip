@@ -178,6 +178,21 @@ struct Mixed {
     float xh[3], m, xl[3], v[3], a[3];
   };
 
+  // A sink whose state is exactly a staged source record (batched systems).
+  __device__ static __forceinline__ Sink sink_from_j(const J &j) {
+    Sink s;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      s.xh[k] = j.xh[k];
+      s.xl[k] = j.xl[k];
+      s.v[k] = j.v[k];
+      s.a[k] = j.a[k];
+    }
+    s.m = j.m;
+    s.id = -1;
+    return s;
+  }
+
   __device__ static __forceinline__ Sink make_sink(const double xp[3], const double vp[3],
                                                    const double ap[3], double m) {
     Sink s;
@@ -356,6 +371,19 @@ struct F64 {
   struct J {
     double x[3], m, v[3], a[3];
   };
+
+  __device__ static __forceinline__ Sink sink_from_j(const J &j) {
+    Sink s;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      s.x[k] = j.x[k];
+      s.v[k] = j.v[k];
+      s.a[k] = j.a[k];
+    }
+    s.m = j.m;
+    s.id = -1;
+    return s;
+  }
 
   __device__ static __forceinline__ Sink make_sink(const double xp[3], const double vp[3],
                                                    const double ap[3], double m) {
@@ -875,6 +903,78 @@ __global__ __launch_bounds__(kThreads) void k_combine(const ForceParams fp, int 
 }
 
 // ---------------------------------------------------------------------------------------------
+// Batched few-body systems (4th order: acc, jerk, pot).  One persistent launch; each wave takes
+// the work items w, w + W, w + 2W, ... of a cost-sorted schedule (W = waves in the grid).  An
+// item is one system of n <= kBatchMax particles: the wave stages the system in its own LDS
+// slice, then covers the sinks 64/L at a time with L lanes per sink, each lane summing every L-th
+// source (self excluded by index), and a butterfly over the L lanes.  L comes per item from the
+// schedule (chosen per size class by nbx_batch_tune).
+// ---------------------------------------------------------------------------------------------
+template <int Prec>
+__global__ __launch_bounds__(kThreads) void k_batch(const BatchParams bp) {
+  using Tr = typename TraitsSel<4, Prec>::type;
+  using T = typename Tr::Real;
+  constexpr int K = kValues<4>;
+  __shared__ typename Tr::J lds_all[kThreads / 64][kBatchMax];
+  __shared__ RedLds<1, K> red_unused;
+  const int lane = threadIdx.x & 63;
+  const int wslot = threadIdx.x >> 6;
+  typename Tr::J *lds = lds_all[wslot];
+  const int nwaves = gridDim.x * (kThreads / 64);
+  const T eps2 = (T)bp.eps2;
+  for (int it = blockIdx.x * (kThreads / 64) + wslot; it < bp.n_items; it += nwaves) {
+    const int2 item = bp.items[it];  // (system, lanes_log2)
+    const int b = bp.offset[item.x];
+    const int n = bp.offset[item.x + 1] - b;
+    const double zero[3] = {0.0, 0.0, 0.0};
+    for (int k = lane; k < n; k += 64) {
+      double x[3], v[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        x[c] = bp.x[3 * (size_t)(b + k) + c];
+        v[c] = bp.v[3 * (size_t)(b + k) + c];
+      }
+      lds[k] = Tr::make_j(x, v, zero, bp.m[b + k]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const int lg = item.y;
+    const int L = 1 << lg;
+    for (int base = 0; base < n; base += 64 >> lg) {
+      const int i = base + (lane >> lg);
+      const int slot = lane & (L - 1);
+      const bool live = i < n;
+      const typename Tr::Sink si = Tr::sink_from_j(lds[live ? i : 0]);
+      Comp<T, K> acc;
+      acc.init();
+      typename Tr::Key dummy = ~typename Tr::Key(0);
+      for (int j0 = slot; j0 < n; j0 += kChunkAcc << lg) {
+        const int je = n < j0 + (kChunkAcc << lg) ? n : j0 + (kChunkAcc << lg);
+        for (int j = j0; j < je; j += L) Tr::template interact<true>(lds[j], si, eps2, j, i, acc, dummy);
+        acc.template fold<0, K>();
+      }
+      double w[1][K];
+      uint64_t wk[1] = {0};
+      int wi[1] = {0};
+#pragma unroll
+      for (int k = 0; k < K; ++k) w[0][k] = (double)acc.hi[k] + (double)acc.lo[k];
+      group_reduce<1, K>(L, w, wk, wi, red_unused);  // L <= 64: shuffles only
+      if (slot == 0 && live) {
+        const size_t q = (size_t)(b + i);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          bp.acc[3 * q + k] = w[0][k];
+          bp.jrk[3 * q + k] = w[0][3 + k];
+        }
+        bp.pot[q] = w[0][6];
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
 // Explicit sinks: address of the source carrying each sink's id (first match), or -1.  Sources
 // are scanned in LDS tiles of 256 ids.
 // ---------------------------------------------------------------------------------------------
@@ -1157,6 +1257,15 @@ hipError_t launch_gather_j(int order, const SourceArrays &src, int n, const int3
   else
     hipLaunchKernelGGL(k_gather_j<6>, dim3(grid_for(n)), dim3(256), 0, stream, src, n, addr, id, m, t, x, v, a,
                        jerk, snap, crackle);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch(int precision, const BatchParams &bp, int grid, hipStream_t stream) {
+  if (bp.n_items <= 0) return hipSuccess;
+  if (precision == NBX_MIXED)
+    hipLaunchKernelGGL(k_batch<NBX_MIXED>, dim3(grid), dim3(kThreads), 0, stream, bp);
+  else
+    hipLaunchKernelGGL(k_batch<NBX_FP64>, dim3(grid), dim3(kThreads), 0, stream, bp);
   return hipGetLastError();
 }
 

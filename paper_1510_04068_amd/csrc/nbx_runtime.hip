@@ -57,6 +57,12 @@ struct nbx_ctx {
   // set_j staging (host path), grown on demand
   DevBuf up;
   int up_cap = 0;
+  // batched few-body systems
+  std::vector<int32_t> batch_sizes;
+  int32_t *d_batch_offset = nullptr;
+  DevBuf batch_items;
+  int batch_n_items = 0;
+  int batch_lg[8] = {-1, -1, -1, -1, -1, -1, -1, -1};  // lanes_log2 per size class (-1: default)
   // state of the last force call (host path)
   int last_ni = -1;
   bool last_nbr = false;
@@ -190,6 +196,65 @@ int enqueue_force(nbx_ctx *c, hipStream_t stream, int ni, const int32_t *d_iaddr
   fp.err = c->d_err;
   hipError_t e = launch_force(c->cfg.order, c->precision, fp, ls, stream);
   if (e != hipSuccess) return hip_fail(c, e, "force kernel launch");
+  return NBX_OK;
+}
+
+// Size class of a batched system of n particles: smallest c with n <= 2^c.
+int batch_class(int n) {
+  int c = 0;
+  while ((1 << c) < n) ++c;
+  return c;
+}
+
+int batch_default_lg(int c) {  // L = 64 / 2^c, at least 1
+  return c >= 6 ? 0 : 6 - c;
+}
+
+// Build and upload the schedule: items (system, lanes_log2) of the selected classes (mask), the
+// largest systems first (ties by system index), one wave each.
+int batch_upload(nbx_ctx *c, unsigned class_mask, const int *lg_override, hipStream_t stream) {
+  const int n_sys = (int)c->batch_sizes.size();
+  std::vector<int> order;
+  order.reserve(n_sys);
+  for (int k = 0; k < n_sys; ++k)
+    if (class_mask & (1u << batch_class(c->batch_sizes[k]))) order.push_back(k);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return c->batch_sizes[a] > c->batch_sizes[b]; });
+  std::vector<int2> items(order.size());
+  for (size_t k = 0; k < order.size(); ++k) {
+    const int cl = batch_class(c->batch_sizes[order[k]]);
+    int lg = lg_override ? lg_override[cl] : c->batch_lg[cl];
+    if (lg < 0) lg = batch_default_lg(cl);
+    items[k] = make_int2(order[k], lg);
+  }
+  if (int rc = grow(c, c->batch_items, std::max<size_t>(1, items.size()) * sizeof(int2))) return rc;
+  if (!items.empty())
+    HIP_TRY(c, hipMemcpyAsync(c->batch_items.p, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice,
+                              stream));
+  HIP_TRY(c, hipStreamSynchronize(stream));
+  c->batch_n_items = (int)items.size();
+  return NBX_OK;
+}
+
+int batch_enqueue(nbx_ctx *c, hipStream_t stream, const double *d_m, const double *d_x, const double *d_v,
+                  double eps2, double *d_acc, double *d_jerk, double *d_pot) {
+  BatchParams bp{};
+  bp.n_items = c->batch_n_items;
+  bp.items = static_cast<const int2 *>(c->batch_items.p);
+  bp.offset = c->d_batch_offset;
+  bp.m = d_m;
+  bp.x = d_x;
+  bp.v = d_v;
+  bp.eps2 = eps2;
+  bp.acc = d_acc;
+  bp.jrk = d_jerk;
+  bp.pot = d_pot;
+  const int waves_per_wg = kThreads / 64;
+  int grid = (bp.n_items + waves_per_wg - 1) / waves_per_wg;
+  if (grid > 8 * 256) grid = 8 * 256;  // persistent: at most 8 workgroups per CU, waves loop over items
+  if (grid < 1) grid = 1;
+  hipError_t e = launch_batch(c->precision, bp, grid, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "batch kernel launch");
   return NBX_OK;
 }
 
@@ -554,6 +619,91 @@ int nbx_force_dev(nbx_ctx *c, void *stream, int ni, const int32_t *d_i_addr, dou
   if (c->nj < 1) return fail(c, NBX_ERR_STATE, "no sources in use (nbx_set_nj)");
   return enqueue_force(c, static_cast<hipStream_t>(stream), ni, d_i_addr, nullptr, nullptr, nullptr, nullptr, nullptr,
                        eps2, d_h2, d_acc, d_jerk, d_snap, d_pot, d_nn_id, d_nn_r2, d_nbr_count, d_nbr_ids);
+}
+
+int nbx_batch_setup(nbx_ctx *c, int n_sys, const int32_t *offsets) {
+  if (int rc = check_ctx(c)) return rc;
+  if (n_sys < 1 || !offsets) return fail(c, NBX_ERR_ARG, "need n_sys >= 1 and offsets");
+  if (offsets[0] != 0) return fail(c, NBX_ERR_ARG, "offsets[0] must be 0");
+  std::vector<int32_t> sizes(n_sys);
+  for (int k = 0; k < n_sys; ++k) {
+    sizes[k] = offsets[k + 1] - offsets[k];
+    if (sizes[k] < 1 || sizes[k] > NBX_BATCH_NMAX)
+      return fail(c, NBX_ERR_ARG, "system %d has %d particles (allowed 1..%d)", k, sizes[k], NBX_BATCH_NMAX);
+  }
+  if (c->d_batch_offset) {
+    auto it = std::find(c->owned.begin(), c->owned.end(), (void *)c->d_batch_offset);
+    if (it != c->owned.end()) c->owned.erase(it);
+    HIP_TRY(c, hipFree(c->d_batch_offset));
+    c->d_batch_offset = nullptr;
+  }
+  if (int rc = alloc_n(c, &c->d_batch_offset, (size_t)n_sys + 1)) return rc;
+  HIP_TRY(c, hipMemcpyAsync(c->d_batch_offset, offsets, ((size_t)n_sys + 1) * 4, hipMemcpyHostToDevice, c->stream));
+  c->batch_sizes = sizes;
+  for (int k = 0; k < 8; ++k) c->batch_lg[k] = -1;
+  return batch_upload(c, 0xffu, nullptr, c->stream);
+}
+
+int nbx_batch_force_dev(nbx_ctx *c, void *stream, const double *d_m, const double *d_x, const double *d_v,
+                        double eps2, double *d_acc, double *d_jerk, double *d_pot) {
+  if (int rc = check_ctx(c)) return rc;
+  if (c->batch_sizes.empty()) return fail(c, NBX_ERR_STATE, "nbx_batch_force_dev before nbx_batch_setup");
+  if (!d_m || !d_x || !d_v || !d_acc || !d_jerk || !d_pot) return fail(c, NBX_ERR_ARG, "NULL device array");
+  if (!(eps2 >= 0.0)) return fail(c, NBX_ERR_ARG, "eps2 must be >= 0");
+  return batch_enqueue(c, static_cast<hipStream_t>(stream), d_m, d_x, d_v, eps2, d_acc, d_jerk, d_pot);
+}
+
+int nbx_batch_tune(nbx_ctx *c, void *stream, const double *d_m, const double *d_x, const double *d_v, double eps2,
+                   double *d_acc, double *d_jerk, double *d_pot, int32_t *lanes_per_class) {
+  if (int rc = check_ctx(c)) return rc;
+  if (c->batch_sizes.empty()) return fail(c, NBX_ERR_STATE, "nbx_batch_tune before nbx_batch_setup");
+  if (!d_m || !d_x || !d_v || !d_acc || !d_jerk || !d_pot) return fail(c, NBX_ERR_ARG, "NULL device array");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned present = 0;
+  for (int32_t n : c->batch_sizes) present |= 1u << batch_class(n);
+  hipEvent_t e0, e1;
+  HIP_TRY(c, hipEventCreate(&e0));
+  HIP_TRY(c, hipEventCreate(&e1));
+  int best[8];
+  for (int cl = 0; cl < 8; ++cl) {
+    best[cl] = -1;
+    if (!(present & (1u << cl))) continue;
+    float best_ms = 1e30f;
+    for (int lg = 0; lg <= 6; ++lg) {
+      int lgs[8];
+      for (int k = 0; k < 8; ++k) lgs[k] = lg;
+      int rc = batch_upload(c, 1u << cl, lgs, s);
+      for (int rep = 0; rc == NBX_OK && rep < 2; ++rep)
+        rc = batch_enqueue(c, s, d_m, d_x, d_v, eps2, d_acc, d_jerk, d_pot);
+      if (rc) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return rc;
+      }
+      constexpr int reps = 10;
+      HIP_TRY(c, hipEventRecord(e0, s));
+      for (int rep = 0; rc == NBX_OK && rep < reps; ++rep)
+        rc = batch_enqueue(c, s, d_m, d_x, d_v, eps2, d_acc, d_jerk, d_pot);
+      HIP_TRY(c, hipEventRecord(e1, s));
+      HIP_TRY(c, hipEventSynchronize(e1));
+      if (rc) return rc;
+      float ms = 0.f;
+      HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_ms) {
+        best_ms = ms;
+        best[cl] = lg;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  for (int cl = 0; cl < 8; ++cl) {
+    c->batch_lg[cl] = best[cl];
+    if (lanes_per_class) lanes_per_class[cl] = best[cl] < 0 ? 0 : 1 << best[cl];
+  }
+  int rc = batch_upload(c, 0xffu, nullptr, s);
+  if (rc) return rc;
+  return batch_enqueue(c, s, d_m, d_x, d_v, eps2, d_acc, d_jerk, d_pot);
 }
 
 int nbx_sync(nbx_ctx *c, void *stream) {

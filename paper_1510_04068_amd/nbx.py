@@ -43,7 +43,9 @@ EXPORTS = (
     "nbx_version", "nbx_device_count", "nbx_open", "nbx_close", "nbx_last_error", "nbx_set_precision",
     "nbx_set_nj", "nbx_set_j", "nbx_predict", "nbx_force", "nbx_force_ext", "nbx_get_force", "nbx_get_nbr",
     "nbx_get_predicted", "nbx_get_j", "nbx_set_j_dev", "nbx_force_dev", "nbx_sync", "nbx_launch_shape",
+    "nbx_batch_setup", "nbx_batch_tune", "nbx_batch_force_dev",
 )
+NBX_BATCH_NMAX = 128
 
 
 class nbx_config(ctypes.Structure):
@@ -104,6 +106,9 @@ def load(path: str = LIB_PATH):
         "nbx_force_dev": ([_P, _P, _I, _P, _D] + [_P] * 9, _I),
         "nbx_sync": ([_P, _P], _I),
         "nbx_launch_shape": ([_P, _I, _P, _P, _P, _P], _I),
+        "nbx_batch_setup": ([_P, _I, _P], _I),
+        "nbx_batch_tune": ([_P, _P, _P, _P, _P, _D, _P, _P, _P, _P], _I),
+        "nbx_batch_force_dev": ([_P, _P, _P, _P, _P, _D, _P, _P, _P], _I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -296,6 +301,26 @@ def nbx_launch_shape(ctx, ni):
         raise NbxError(rc, "bad arguments")
     return {"lanes_per_sink": vals[0].value, "sinks_per_lane": vals[1].value, "splits": vals[2].value,
             "workgroups": vals[3].value}
+
+
+def nbx_batch_setup(ctx, offsets):
+    offsets = np.ascontiguousarray(offsets, dtype=np.int32)
+    return _check(ctx, load().nbx_batch_setup(ctx, int(offsets.shape[0] - 1), _ptr(offsets)))
+
+
+def nbx_batch_tune(ctx, stream, d_m, d_x, d_v, eps2, d_acc, d_jerk, d_pot):
+    """Returns the lanes-per-sink chosen for each of the 8 size classes (0: class absent)."""
+    lanes = np.zeros(8, dtype=np.int32)
+    rc = load().nbx_batch_tune(ctx, _stream(stream), _dptr(d_m), _dptr(d_x), _dptr(d_v), float(eps2),
+                               _dptr(d_acc), _dptr(d_jerk), _dptr(d_pot), _ptr(lanes))
+    _check(ctx, rc)
+    return lanes
+
+
+def nbx_batch_force_dev(ctx, stream, d_m, d_x, d_v, eps2, d_acc, d_jerk, d_pot):
+    rc = load().nbx_batch_force_dev(ctx, _stream(stream), _dptr(d_m), _dptr(d_x), _dptr(d_v), float(eps2),
+                                    _dptr(d_acc), _dptr(d_jerk), _dptr(d_pot))
+    return _check(ctx, rc)
 
 
 class Context:
