@@ -70,6 +70,9 @@ def parse():
     ap.add_argument("--batch", action="store_true",
                     help="also time 4096 independent few-body Plummer systems (3..96 particles, eps2=0, 4th order) "
                          "in one persistent launch, default and autotuned lane mappings")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="also time the adjoint on a 65536-body Plummer sphere (eps2=1e-6): forward forces, the "
+                         "vector-Jacobian product, and the gradient through 16 checkpointed Hermite steps (dt=1/512)")
     ap.add_argument("--order6", action="store_true",
                     help="also time 6th-order forces with neighbour lists on a 1048576-body Plummer/Salpeter "
                          "cluster (eps2=1e-8, h2=1e-4, at most 256 neighbours), N_i in {1024, 65536, 1048576}")
@@ -261,6 +264,53 @@ def batch(torch, nbx, ics, dev, steps):
     return res
 
 
+def adjoint(torch, nbx, ics, dev, steps):
+    """Config-5 timings: forward, adjoint kernel, and a 16-step checkpointed Hermite gradient."""
+    import numpy as np
+
+    from paper_1510_04068_amd.autograd import ForceContext, forces, hermite4
+
+    n, eps2 = 65536, 1e-6
+    src = ics.make_sources(n, seed=5)
+    rng = np.random.default_rng(5005)
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    wa, wj = T(rng.normal(size=(n, 3))), T(rng.normal(size=(n, 3)))
+    stream = torch.cuda.current_stream()
+    res = {"workload": "Plummer N=65536, eps2=1e-6, loss = seeded weights . (acc, jerk) + total potential energy; "
+                       "16 checkpointed 4th-order Hermite steps, dt=1/512", "n": n}
+    for prec, name in ((nbx.NBX_FP64, "fp64"), (nbx.NBX_MIXED, "mixed")):
+        fc = ForceContext(n, precision=prec)
+        x, v, m = T(src.x), T(src.v), T(src.m)
+
+        def ev_time(fn, reps):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps
+
+        g = [torch.empty((n, 3), dtype=torch.float64, device=dev) for _ in range(2)] + [torch.empty(n, dtype=torch.float64, device=dev)]
+        gp = 0.5 * m
+        res[name + "_forward_ms"] = round(ev_time(lambda: forces(x, v, m, eps2, fc), steps), 4)
+        res[name + "_vjp_ms"] = round(ev_time(lambda: nbx.nbx_force_vjp_dev(fc.ctx.ctx, stream, n, m, x, v, eps2, wa, wj, gp,
+                                                                           g[0], g[1], g[2]), steps), 4)
+
+        def traj():
+            xx, vv, mm = x.clone().requires_grad_(), v.clone().requires_grad_(), m.clone().requires_grad_()
+            x1, v1 = hermite4(xx, vv, mm, eps2, 1.0 / 512, 16, fc, checkpoint=True)
+            ((wa * x1).sum() + (wj * v1).sum()).backward()
+
+        res[name + "_hermite16_grad_ms"] = round(ev_time(traj, 1), 3)
+        res[name + "_vjp_pairs_s"] = float("%.4g" % (float(n) * n / (res[name + "_vjp_ms"] * 1e-3)))
+        fc.close()
+    print("bench: adjoint %s" % json.dumps(res), file=sys.stderr, flush=True)
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -331,6 +381,7 @@ def main():
 
     o6 = order6(torch, nbx, nbody_ics, dev, max(2, args.steps // 10)) if args.order6 else None
     bt = batch(torch, nbx, nbody_ics, dev, max(20, args.steps)) if args.batch else None
+    adj = adjoint(torch, nbx, nbody_ics, dev, max(3, args.steps // 5)) if args.adjoint else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -383,6 +434,8 @@ def main():
         line["order6"] = o6
     if bt is not None:
         line["batch"] = bt
+    if adj is not None:
+        line["adjoint"] = adj
     print(json.dumps(line), flush=True)
 
 

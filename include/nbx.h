@@ -189,6 +189,19 @@ int nbx_force_dev(nbx_ctx *ctx, void *stream, int ni, const int32_t *d_i_addr, d
                   double *d_pot, int64_t *d_nn_id, double *d_nn_r2, int32_t *d_nbr_count,
                   int64_t *d_nbr_ids);
 
+/* ---- adjoint -----------------------------------------------------------------------------------
+ * Gradients of L = sum_i (g_acc_i . acc_i + g_jerk_i . jerk_i + g_pot_i pot_i) with respect to the
+ * positions, velocities and masses of a closed system of n particles, where acc, jerk, pot are the
+ * 4th-order outputs of nbx_force with every particle a sink and a source (state used as given, no
+ * prediction, self excluded).  This is the vector-Jacobian product of that force evaluation, for
+ * reverse-mode differentiation through an integrator.  d_m [n], d_x, d_v [n][3], upstream
+ * d_g_acc, d_g_jerk [n][3], d_g_pot [n] in; d_grad_x, d_grad_v [n][3], d_grad_m [n] out.  eps2 >= 0.
+ * Precision follows the context (NBX_MIXED needs every softened distance above ~1e-5 so that R^-7
+ * stays finite in FP32).  Uses the context's split scratch.  Enqueue only. */
+int nbx_force_vjp_dev(nbx_ctx *ctx, void *stream, int n, const double *d_m, const double *d_x,
+                      const double *d_v, double eps2, const double *d_g_acc, const double *d_g_jerk,
+                      const double *d_g_pot, double *d_grad_x, double *d_grad_v, double *d_grad_m);
+
 /* ---- batched few-body systems (4th order: acc, jerk, pot) -------------------------------------
  * Many independent small systems in one persistent launch.  System s holds the particles
  * [offsets[s], offsets[s+1]) of flat device arrays; every particle is a sink and a source of its

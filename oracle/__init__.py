@@ -18,6 +18,7 @@ from .oracle import (  # noqa: F401
     max_threads,
     predict,
     force,
+    force_vjp,
     hermite4_correct,
     total_energy,
 )

@@ -190,3 +190,69 @@ int oracle_max_threads(void) {
   return 1;
 #endif
 }
+
+/* Vector-Jacobian product of the 4th-order outputs (acc, jerk, pot) of a closed system (every
+ * particle is a sink and a source, self excluded) with respect to the inputs (x, v, m).
+ * Upstream gradients g_acc, g_jerk [n][3] and g_pot [n].  For one pair with
+ * r = x_j - x_i, v = v_j - v_i, q = 1/R, s = r.v and the sink's gradients (g_a, g_j, g_p), the
+ * contribution f = g_a.A0 + g_j.A1 + g_p.P (A0 = m_j r q^3, A1 = m_j (v q^3 - 3 s r q^5),
+ * P = -m_j q) has, writing Ga = g_a.r, G1 = g_j.v, G2 = g_j.r:
+ *   df/dr = m_j [q^3 g_a - 3 q^5 s g_j - 3 q^5 G2 v + (-3 q^5 (Ga + G1) + 15 q^7 s G2 + g_p q^3) r]
+ *   df/dv = m_j [q^3 g_j - 3 q^5 G2 r]
+ *   df/dm_j = q^3 (Ga + G1) - 3 q^5 s G2 - g_p q
+ * and r, v enter x_j, v_j with + and x_i, v_i with -.  Outputs grad_x, grad_v [nsel][3] and
+ * grad_m [nsel] for the particles sel[nsel] (all if sel is NULL and nsel == n). */
+int oracle_force_vjp(double eps2, int n, const double *m, const double *x, const double *v,
+                     const double *g_acc, const double *g_jerk, const double *g_pot, int nsel,
+                     const int32_t *sel, double *grad_x, double *grad_v, double *grad_m, int nthreads) {
+  if (n < 0 || nsel < 0 || !m || !x || !v || !g_acc || !g_jerk || !g_pot || !grad_x || !grad_v || !grad_m)
+    return ORACLE_ERR_ARG;
+  if (!sel && nsel != n) return ORACLE_ERR_ARG;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+#pragma omp parallel for schedule(static)
+  for (int a = 0; a < nsel; ++a) {
+    const int p = sel ? sel[a] : a;
+    long double gx[3] = {0, 0, 0}, gv[3] = {0, 0, 0}, gm = 0;
+    for (int o = 0; o < n; ++o) {
+      if (o == p) continue;
+      /* p as the sink of source o: r = x_o - x_p; d/dx_p = -df/dr, d/dv_p = -df/dv */
+      /* p as the source of sink o: r = x_p - x_o; d/dx_p = +df/dr, d/dv_p = +df/dv, d/dm_p = df/dm */
+      for (int role = 0; role < 2; ++role) {
+        const int sink = role == 0 ? p : o, src = role == 0 ? o : p;
+        double r[3], w[3];
+        for (int k = 0; k < 3; ++k) {
+          r[k] = x[3 * (size_t)src + k] - x[3 * (size_t)sink + k];
+          w[k] = v[3 * (size_t)src + k] - v[3 * (size_t)sink + k];
+        }
+        const double *ga = g_acc + 3 * (size_t)sink, *gj = g_jerk + 3 * (size_t)sink;
+        const double gp = g_pot[sink], mj = m[src];
+        const double R2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + eps2;
+        const double q = 1.0 / sqrt(R2);
+        const double q3 = q * q * q, q5 = q3 * q * q, q7 = q5 * q * q;
+        const double s = r[0] * w[0] + r[1] * w[1] + r[2] * w[2];
+        const double Ga = ga[0] * r[0] + ga[1] * r[1] + ga[2] * r[2];
+        const double G1 = gj[0] * w[0] + gj[1] * w[1] + gj[2] * w[2];
+        const double G2 = gj[0] * r[0] + gj[1] * r[1] + gj[2] * r[2];
+        const double cr = -3.0 * q5 * (Ga + G1) + 15.0 * q7 * s * G2 + gp * q3;
+        const double sign = role == 0 ? -1.0 : 1.0;
+        for (int k = 0; k < 3; ++k) {
+          const double dr = mj * (q3 * ga[k] - 3.0 * q5 * s * gj[k] - 3.0 * q5 * G2 * w[k] + cr * r[k]);
+          const double dv = mj * (q3 * gj[k] - 3.0 * q5 * G2 * r[k]);
+          gx[k] += sign * dr;
+          gv[k] += sign * dv;
+        }
+        if (role == 1) gm += q3 * (Ga + G1) - 3.0 * q5 * s * G2 - gp * q;
+      }
+    }
+    for (int k = 0; k < 3; ++k) {
+      grad_x[3 * (size_t)a + k] = (double)gx[k];
+      grad_v[3 * (size_t)a + k] = (double)gv[k];
+    }
+    grad_m[a] = (double)gm;
+  }
+  return ORACLE_OK;
+}

@@ -54,6 +54,9 @@ def _load():
             [ctypes.c_int, ctypes.c_double, ctypes.c_int, lp, dp, dp, dp, dp, ctypes.c_int, lp, dp, dp, dp, dp,
              ctypes.c_int, dp, dp, dp, dp, lp, dp, ip, lp, dp, ctypes.c_int]
         )
+        lib.oracle_force_vjp.restype = ctypes.c_int
+        lib.oracle_force_vjp.argtypes = [ctypes.c_double, ctypes.c_int, dp, dp, dp, dp, dp, dp, ctypes.c_int, ip, dp,
+                                         dp, dp, ctypes.c_int]
         lib.oracle_max_threads.restype = ctypes.c_int
         lib.oracle_max_threads.argtypes = []
         _lib = lib
@@ -167,3 +170,25 @@ def total_energy(m, v, pot):
     """Kinetic plus potential energy: sum m v^2 / 2 + sum m pot / 2 (each pair once)."""
     m = np.asarray(m, dtype=np.float64)
     return float(0.5 * np.sum(m * np.sum(np.asarray(v) ** 2, axis=1)) + 0.5 * np.sum(m * np.asarray(pot)))
+
+
+def force_vjp(eps2, m, x, v, g_acc, g_jerk, g_pot, sel=None, nthreads=0):
+    """Gradients (grad_x, grad_v, grad_m) of sum(g_acc.acc + g_jerk.jerk + g_pot.pot) for a closed
+    4th-order system (every particle a sink and a source), for the particles sel (all if None)."""
+    lib = _load()
+    x = _f64(x)
+    n = x.shape[0]
+    m, v = _f64(m, (n,)), _f64(v, (n, 3))
+    g_acc, g_jerk, g_pot = _f64(g_acc, (n, 3)), _f64(g_jerk, (n, 3)), _f64(g_pot, (n,))
+    if sel is None:
+        nsel, selp = n, None
+    else:
+        sel = np.ascontiguousarray(sel, dtype=np.int32)
+        nsel, selp = sel.shape[0], sel
+    gx, gv, gm = np.zeros((nsel, 3)), np.zeros((nsel, 3)), np.zeros(nsel)
+    d, I = ctypes.c_double, ctypes.c_int32
+    rc = lib.oracle_force_vjp(float(eps2), n, _ptr(m, d), _ptr(x, d), _ptr(v, d), _ptr(g_acc, d), _ptr(g_jerk, d),
+                              _ptr(g_pot, d), nsel, _ptr(selp, I), _ptr(gx, d), _ptr(gv, d), _ptr(gm, d), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_force_vjp rejected its arguments")
+    return gx, gv, gm

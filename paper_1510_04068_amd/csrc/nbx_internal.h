@@ -86,6 +86,24 @@ struct BatchParams {
   double *pot;
 };
 
+// Adjoint of the 4th-order forces of a closed system (every particle a sink and a source).
+struct VjpParams {
+  int n;
+  int n_pad;   // n rounded up to kTile
+  int splits;  // source splits S; partials part[(s*7 + k)*n + p] when S > 1
+  double eps2;
+  const double *m;
+  const double *x;
+  const double *v;
+  const double *g_acc;
+  const double *g_jerk;
+  const double *g_pot;
+  double *grad_x;
+  double *grad_v;
+  double *grad_m;
+  double *part;
+};
+
 struct LaunchShape {
   int lanes_log2;
   int sinks_per_lane;
@@ -108,6 +126,7 @@ hipError_t launch_gather_j(int order, const SourceArrays &src, int n, const int3
                            int64_t *id, double *m, double *t, double *x, double *v, double *a,
                            double *jerk, double *snap, double *crackle, hipStream_t stream);
 hipError_t launch_fill_i32(int32_t *p, int n, int value, hipStream_t stream);
+hipError_t launch_vjp(int precision, const VjpParams &vp, hipStream_t stream);
 hipError_t launch_batch(int precision, const BatchParams &bp, int grid, hipStream_t stream);
 hipError_t launch_selfmap(const SourceArrays &src, int nj, int ni, const int64_t *ext_id, int32_t *self,
                           hipStream_t stream);

@@ -35,6 +35,7 @@
 
 #include <cstdio>
 #include <cstdlib>
+#include <type_traits>
 
 #include "nbx_internal.h"
 
@@ -975,6 +976,172 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchParams bp) {
 }
 
 // ---------------------------------------------------------------------------------------------
+// Adjoint (vector-Jacobian product) of the 4th-order outputs of a closed system.  For a pair
+// with r = x_q - x_p, w = v_q - v_p, q = 1/R, s = r.w and the sink's upstream gradients
+// (g_a, g_j, g_p), the pair term f = g_a.A0 + g_j.A1 + g_p.P has (Ga = g_a.r, G1 = g_j.w,
+// G2 = g_j.r)
+//   df/dr = m_src [q^3 g_a - 3 q^5 s g_j - 3 q^5 G2 w + (-3 q^5 (Ga + G1) + 15 q^7 s G2 + g_p q^3) r]
+//   df/dw = m_src [q^3 g_j - 3 q^5 G2 r],   df/dm_src = q^3 (Ga + G1) - 3 q^5 s G2 - g_p q.
+// Particle p gathers, over every other particle o, the pair (p sink, o source) with -df/dr,
+// -df/dw and the pair (o sink, p source) with +df/dr, +df/dw, +df/dm at r -> -r, w -> -w.  One
+// particle per lane, LDS tiles of the other particles, source splits combined in fixed order.
+// ---------------------------------------------------------------------------------------------
+template <int Prec>
+struct VjpRec;
+template <>
+struct alignas(16) VjpRec<NBX_MIXED> {
+  float xh[3], m, xl[3], gp, v[3], pad0, ga[3], pad1, gj[3], pad2;
+};
+template <>
+struct alignas(16) VjpRec<NBX_FP64> {
+  double x[3], m, v[3], gp, ga[3], pad0, gj[3], pad1;
+};
+
+template <int Prec>
+__device__ __forceinline__ VjpRec<Prec> vjp_rec(const VjpParams &vp, int o) {
+  VjpRec<Prec> r{};
+  const bool live = o < vp.n;
+  const size_t b = 3 * (size_t)(live ? o : 0);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double x = live ? vp.x[b + k] : kPadPos;
+    if constexpr (Prec == NBX_MIXED) {
+      ds_split(x, r.xh[k], r.xl[k]);
+      r.v[k] = live ? (float)vp.v[b + k] : 0.0f;
+      r.ga[k] = live ? (float)vp.g_acc[b + k] : 0.0f;
+      r.gj[k] = live ? (float)vp.g_jerk[b + k] : 0.0f;
+    } else {
+      r.x[k] = x;
+      r.v[k] = live ? vp.v[b + k] : 0.0;
+      r.ga[k] = live ? vp.g_acc[b + k] : 0.0;
+      r.gj[k] = live ? vp.g_jerk[b + k] : 0.0;
+    }
+  }
+  r.m = live ? vp.m[o] : 0.0;
+  r.gp = live ? vp.g_pot[o] : 0.0;
+  return r;
+}
+
+// One pair (p, o), o != p guarded; A[0..2] += d/dx_p, A[3..5] += d/dv_p, A[6] += d/dm_p, with the
+// source part accumulated without the factor m_p (applied once at the end): values 7..12.
+template <int Prec, typename T>
+__device__ __forceinline__ void vjp_pair(const VjpRec<Prec> &P, const VjpRec<Prec> &O, T eps2, bool self,
+                                         T (&acc)[13]) {
+  T r[3], w[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if constexpr (Prec == NBX_MIXED) {
+      r[k] = (O.xh[k] - P.xh[k]) + (O.xl[k] - P.xl[k]);
+    } else {
+      r[k] = O.x[k] - P.x[k];
+    }
+    w[k] = O.v[k] - P.v[k];
+  }
+  const T R2 = r[2] * r[2] + (r[1] * r[1] + (r[0] * r[0] + eps2));
+  T q;
+  if constexpr (Prec == NBX_MIXED) {
+    q = __builtin_amdgcn_rsqf(R2);
+    q = q * __builtin_fmaf(-0.5f * R2, q * q, 1.5f);
+  } else {
+    q = rsqrt64(R2);
+  }
+  q = self ? T(0) : q;
+  const T q2 = q * q, q3 = q * q2, q5 = q3 * q2, q7 = q5 * q2;
+  const T s = r[0] * w[0] + r[1] * w[1] + r[2] * w[2];
+  // p as the sink of o (gradients of p, mass of o): subtract df/dr, df/dw
+  {
+    const T Ga = P.ga[0] * r[0] + P.ga[1] * r[1] + P.ga[2] * r[2];
+    const T G1 = P.gj[0] * w[0] + P.gj[1] * w[1] + P.gj[2] * w[2];
+    const T G2 = P.gj[0] * r[0] + P.gj[1] * r[1] + P.gj[2] * r[2];
+    const T cr = T(-3) * q5 * (Ga + G1) + T(15) * q7 * s * G2 + P.gp * q3;
+    const T mo = O.m;
+    const T t1 = mo * q3, t2 = mo * T(3) * q5 * s, t3 = mo * T(3) * q5 * G2, t4 = mo * cr;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      acc[k] -= t1 * P.ga[k] - t2 * P.gj[k] - t3 * w[k] + t4 * r[k];
+      acc[3 + k] -= t1 * P.gj[k] - t3 * r[k];
+    }
+  }
+  // p as the source of o (gradients of o, mass of p), r -> -r, w -> -w
+  {
+    const T Ha = O.ga[0] * r[0] + O.ga[1] * r[1] + O.ga[2] * r[2];
+    const T H1 = O.gj[0] * w[0] + O.gj[1] * w[1] + O.gj[2] * w[2];
+    const T H2 = O.gj[0] * r[0] + O.gj[1] * r[1] + O.gj[2] * r[2];
+    const T crp = T(3) * q5 * (Ha + H1) - T(15) * q7 * s * H2 + O.gp * q3;
+    const T u2 = T(3) * q5 * s, u3 = T(3) * q5 * H2;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      acc[7 + k] += q3 * O.ga[k] - u2 * O.gj[k] - u3 * w[k] - crp * r[k];
+      acc[10 + k] += q3 * O.gj[k] - u3 * r[k];
+    }
+    acc[6] += -q3 * (Ha + H1) + u2 * H2 - O.gp * q;
+  }
+}
+
+template <int Prec>
+__global__ __launch_bounds__(kThreads) void k_vjp(const VjpParams vp) {
+  using T = typename std::conditional<Prec == NBX_MIXED, float, double>::type;
+  __shared__ VjpRec<Prec> tile[kTile];
+  const int S = vp.splits;
+  const int split = blockIdx.x % S;
+  const int ib = blockIdx.x / S;
+  const int p = ib * kThreads + threadIdx.x;
+  const int ntiles = vp.n_pad / kTile;
+  const int t0 = (int)(((int64_t)split * ntiles) / S);
+  const int t1 = (int)(((int64_t)(split + 1) * ntiles) / S);
+  const VjpRec<Prec> P = vjp_rec<Prec>(vp, p);
+  const T eps2 = (T)vp.eps2;
+  Comp<T, 13> acc;
+  acc.init();
+  for (int tl = t0; tl < t1; ++tl) {
+    __syncthreads();
+    tile[threadIdx.x] = vjp_rec<Prec>(vp, tl * kTile + threadIdx.x);
+    __syncthreads();
+    for (int c = 0; c < kTile; c += kChunkAcc) {
+#pragma unroll 2
+      for (int e = c; e < c + kChunkAcc; ++e) {
+        const int o = tl * kTile + e;
+        vjp_pair<Prec, T>(P, tile[e], eps2, o == p || o >= vp.n, acc.part);
+      }
+      acc.template fold<0, 13>();
+    }
+  }
+  double g[7];
+  const double mp = P.m;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) g[k] = (double)acc.hi[k] + (double)acc.lo[k] + mp * ((double)acc.hi[7 + k] + (double)acc.lo[7 + k]);
+  g[6] = (double)acc.hi[6] + (double)acc.lo[6];
+  if (p >= vp.n) return;
+  if (S == 1) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      vp.grad_x[3 * (size_t)p + k] = g[k];
+      vp.grad_v[3 * (size_t)p + k] = g[3 + k];
+    }
+    vp.grad_m[p] = g[6];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 7; ++k) vp.part[((size_t)split * 7 + k) * vp.n + p] = g[k];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_vjp_combine(const VjpParams vp) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= vp.n) return;
+  double g[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int s = 0; s < vp.splits; ++s) {
+#pragma unroll
+    for (int k = 0; k < 7; ++k) g[k] += vp.part[((size_t)s * 7 + k) * vp.n + p];
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    vp.grad_x[3 * (size_t)p + k] = g[k];
+    vp.grad_v[3 * (size_t)p + k] = g[3 + k];
+  }
+  vp.grad_m[p] = g[6];
+}
+
+// ---------------------------------------------------------------------------------------------
 // Explicit sinks: address of the source carrying each sink's id (first match), or -1.  Sources
 // are scanned in LDS tiles of 256 ids.
 // ---------------------------------------------------------------------------------------------
@@ -1257,6 +1424,20 @@ hipError_t launch_gather_j(int order, const SourceArrays &src, int n, const int3
   else
     hipLaunchKernelGGL(k_gather_j<6>, dim3(grid_for(n)), dim3(256), 0, stream, src, n, addr, id, m, t, x, v, a,
                        jerk, snap, crackle);
+  return hipGetLastError();
+}
+
+hipError_t launch_vjp(int precision, const VjpParams &vp, hipStream_t stream) {
+  if (vp.n <= 0) return hipSuccess;
+  const int blocks = (vp.n + kThreads - 1) / kThreads;
+  const dim3 grid(blocks * vp.splits), block(kThreads);
+  if (precision == NBX_MIXED)
+    hipLaunchKernelGGL(k_vjp<NBX_MIXED>, grid, block, 0, stream, vp);
+  else
+    hipLaunchKernelGGL(k_vjp<NBX_FP64>, grid, block, 0, stream, vp);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || vp.splits <= 1) return e;
+  hipLaunchKernelGGL(k_vjp_combine, dim3(grid_for(vp.n)), dim3(256), 0, stream, vp);
   return hipGetLastError();
 }
 

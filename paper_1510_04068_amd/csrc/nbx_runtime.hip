@@ -621,6 +621,42 @@ int nbx_force_dev(nbx_ctx *c, void *stream, int ni, const int32_t *d_i_addr, dou
                        eps2, d_h2, d_acc, d_jerk, d_snap, d_pot, d_nn_id, d_nn_r2, d_nbr_count, d_nbr_ids);
 }
 
+int nbx_force_vjp_dev(nbx_ctx *c, void *stream, int n, const double *d_m, const double *d_x, const double *d_v,
+                      double eps2, const double *d_g_acc, const double *d_g_jerk, const double *d_g_pot,
+                      double *d_grad_x, double *d_grad_v, double *d_grad_m) {
+  if (int rc = check_ctx(c)) return rc;
+  if (n < 0) return fail(c, NBX_ERR_ARG, "n < 0");
+  if (n == 0) return NBX_OK;
+  if (!d_m || !d_x || !d_v || !d_g_acc || !d_g_jerk || !d_g_pot || !d_grad_x || !d_grad_v || !d_grad_m)
+    return fail(c, NBX_ERR_ARG, "NULL device array");
+  if (!(eps2 >= 0.0)) return fail(c, NBX_ERR_ARG, "eps2 must be >= 0");
+  VjpParams vp{};
+  vp.n = n;
+  vp.n_pad = (n + kTile - 1) / kTile * kTile;
+  const int blocks = (n + kThreads - 1) / kThreads;
+  const int ntiles = vp.n_pad / kTile;
+  int S = (2048 + blocks - 1) / blocks;
+  const int scap = (int)std::max<int64_t>(1, ((int64_t)1 << 21) / n);
+  S = std::min(std::min(S, ntiles), scap);
+  vp.splits = std::max(S, 1);
+  if (vp.splits > 1)
+    if (int rc = grow(c, c->part, (size_t)vp.splits * 7 * (size_t)n * sizeof(double))) return rc;
+  vp.eps2 = eps2;
+  vp.m = d_m;
+  vp.x = d_x;
+  vp.v = d_v;
+  vp.g_acc = d_g_acc;
+  vp.g_jerk = d_g_jerk;
+  vp.g_pot = d_g_pot;
+  vp.grad_x = d_grad_x;
+  vp.grad_v = d_grad_v;
+  vp.grad_m = d_grad_m;
+  vp.part = static_cast<double *>(c->part.p);
+  hipError_t e = launch_vjp(c->precision, vp, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(c, e, "adjoint kernel launch");
+  return NBX_OK;
+}
+
 int nbx_batch_setup(nbx_ctx *c, int n_sys, const int32_t *offsets) {
   if (int rc = check_ctx(c)) return rc;
   if (n_sys < 1 || !offsets) return fail(c, NBX_ERR_ARG, "need n_sys >= 1 and offsets");

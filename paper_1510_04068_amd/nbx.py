@@ -43,7 +43,7 @@ EXPORTS = (
     "nbx_version", "nbx_device_count", "nbx_open", "nbx_close", "nbx_last_error", "nbx_set_precision",
     "nbx_set_nj", "nbx_set_j", "nbx_predict", "nbx_force", "nbx_force_ext", "nbx_get_force", "nbx_get_nbr",
     "nbx_get_predicted", "nbx_get_j", "nbx_set_j_dev", "nbx_force_dev", "nbx_sync", "nbx_launch_shape",
-    "nbx_batch_setup", "nbx_batch_tune", "nbx_batch_force_dev",
+    "nbx_batch_setup", "nbx_batch_tune", "nbx_batch_force_dev", "nbx_force_vjp_dev",
 )
 NBX_BATCH_NMAX = 128
 
@@ -109,6 +109,7 @@ def load(path: str = LIB_PATH):
         "nbx_batch_setup": ([_P, _I, _P], _I),
         "nbx_batch_tune": ([_P, _P, _P, _P, _P, _D, _P, _P, _P, _P], _I),
         "nbx_batch_force_dev": ([_P, _P, _P, _P, _P, _D, _P, _P, _P], _I),
+        "nbx_force_vjp_dev": ([_P, _P, _I, _P, _P, _P, _D, _P, _P, _P, _P, _P, _P], _I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -320,6 +321,13 @@ def nbx_batch_tune(ctx, stream, d_m, d_x, d_v, eps2, d_acc, d_jerk, d_pot):
 def nbx_batch_force_dev(ctx, stream, d_m, d_x, d_v, eps2, d_acc, d_jerk, d_pot):
     rc = load().nbx_batch_force_dev(ctx, _stream(stream), _dptr(d_m), _dptr(d_x), _dptr(d_v), float(eps2),
                                     _dptr(d_acc), _dptr(d_jerk), _dptr(d_pot))
+    return _check(ctx, rc)
+
+
+def nbx_force_vjp_dev(ctx, stream, n, d_m, d_x, d_v, eps2, d_g_acc, d_g_jerk, d_g_pot, d_grad_x, d_grad_v, d_grad_m):
+    rc = load().nbx_force_vjp_dev(ctx, _stream(stream), int(n), _dptr(d_m), _dptr(d_x), _dptr(d_v), float(eps2),
+                                  _dptr(d_g_acc), _dptr(d_g_jerk), _dptr(d_g_pot), _dptr(d_grad_x), _dptr(d_grad_v),
+                                  _dptr(d_grad_m))
     return _check(ctx, rc)
 
 
