@@ -13,13 +13,16 @@
  *    differences: copy, predict and gravity kernels).  The paper does not
  *    print the predictor; it is the Taylor polynomial of the particle's orbit
  *    about its own time t_j, truncated at the integrator's order: position and
- *    velocity for 4th order, position, velocity and acceleration for 6th.
+ *    velocity through the acceleration for the 2nd-order (GRAPE-5, leapfrog)
+ *    mode, through the jerk for 4th order, and position, velocity and
+ *    acceleration through the crackle for 6th.
  *
  *  - oracle_force: direct summation of the forces exerted by the sources on
  *    the sinks ("i-particles") (Methods > Parallelisation method), with the
  *    quantities the Results section lists: acceleration, its time derivative
  *    (jerk) for 4th-order Hermite, the second derivative (snap) for 6th order
- *    (Results > Sixth order performance), the potential, the nearest
+ *    (Results > Sixth order performance), the potential (the 2nd-order mode
+ *    of the Background section returns acceleration and potential only), the nearest
  *    neighbour (particle id and distance, Discussion > CPU) and the list of
  *    particles within a radius (Background; Results, NBODY4/Kira perturber
  *    lists).  The paper prints no force law; the reading used is Newtonian
@@ -60,22 +63,31 @@
 #define ORACLE_ERR_ARG -1
 
 /* Taylor predictor: for each particle, dt = t - t_j and
- *   x_p = x + v dt + a dt^2/2 + jerk dt^3/6 [+ snap dt^4/24 + crackle dt^5/120]
- *   v_p = v + a dt + jerk dt^2/2 [+ snap dt^3/6 + crackle dt^4/24]
- *   a_p = a + jerk dt + snap dt^2/2 + crackle dt^3/6          (6th order)
- * Arrays are [n][3] row-major; tj is [n].  ap may be NULL for order 4. */
+ *   order 2:  x_p = x + v dt + a dt^2/2,  v_p = v + a dt,  a_p = a
+ *   order 4:  x_p = x + v dt + a dt^2/2 + jerk dt^3/6
+ *             v_p = v + a dt + jerk dt^2/2,  a_p = a + jerk dt
+ *   order 6:  x_p = x + v dt + a dt^2/2 + jerk dt^3/6 + snap dt^4/24 + crackle dt^5/120
+ *             v_p = v + a dt + jerk dt^2/2 + snap dt^3/6 + crackle dt^4/24
+ *             a_p = a + jerk dt + snap dt^2/2 + crackle dt^3/6
+ * Arrays are [n][3] row-major; tj is [n].  ap may be NULL for orders 2 and 4; jerk may be NULL
+ * for order 2 (it is not used). */
 int oracle_predict(int n, int order, double t, const double *tj, const double *x, const double *v,
                    const double *a, const double *jerk, const double *snap, const double *crackle,
                    double *xp, double *vp, double *ap) {
-  if (n < 0 || (order != 4 && order != 6) || !tj || !x || !v || !a || !jerk || !xp || !vp)
+  if (n < 0 || (order != 2 && order != 4 && order != 6) || !tj || !x || !v || !a || !xp || !vp)
     return ORACLE_ERR_ARG;
+  if (order != 2 && !jerk) return ORACLE_ERR_ARG;
   if (order == 6 && (!snap || !crackle || !ap)) return ORACLE_ERR_ARG;
   for (int p = 0; p < n; ++p) {
     const double dt = t - tj[p];
     const double dt2 = dt * dt, dt3 = dt2 * dt, dt4 = dt3 * dt, dt5 = dt4 * dt;
     for (int k = 0; k < 3; ++k) {
       const int q = 3 * p + k;
-      if (order == 4) {
+      if (order == 2) {
+        xp[q] = x[q] + v[q] * dt + a[q] * dt2 / 2.0;
+        vp[q] = v[q] + a[q] * dt;
+        if (ap) ap[q] = a[q];
+      } else if (order == 4) {
         xp[q] = x[q] + v[q] * dt + a[q] * dt2 / 2.0 + jerk[q] * dt3 / 6.0;
         vp[q] = v[q] + a[q] * dt + jerk[q] * dt2 / 2.0;
         if (ap) ap[q] = a[q] + jerk[q] * dt;
@@ -95,15 +107,18 @@ int oracle_predict(int n, int order, double t, const double *tj, const double *x
  * h2[ni] (NULL: no neighbour lists).  Outputs (any may be NULL except acc):
  * acc/jerk/snap[ni][3], pot[ni], nn_id[ni], nn_r2[ni], nbr_count[ni],
  * nbr_ids[ni][nbr_max], cond[ni][3] = (sum |A0|, sum |A1|, sum |A2|) for
- * condition-normalised error measures.  nthreads <= 0: OpenMP default. */
+ * condition-normalised error measures.  Order 2: acceleration and potential
+ * only; vj and vi may be NULL and jerk is not written.  nthreads <= 0: OpenMP
+ * default. */
 int oracle_force(int order, double eps2, int nj, const int64_t *idj, const double *mj, const double *xj,
                  const double *vj, const double *aj, int ni, const int64_t *idi, const double *xi,
                  const double *vi, const double *ai, const double *h2, int nbr_max, double *acc,
                  double *jerk, double *snap, double *pot, int64_t *nn_id, double *nn_r2,
                  int32_t *nbr_count, int64_t *nbr_ids, double *cond, int nthreads) {
-  if ((order != 4 && order != 6) || nj < 0 || ni < 0 || !idj || !mj || !xj || !vj || !idi || !xi ||
-      !vi || !acc)
+  if ((order != 2 && order != 4 && order != 6) || nj < 0 || ni < 0 || !idj || !mj || !xj || !idi ||
+      !xi || !acc)
     return ORACLE_ERR_ARG;
+  if (order != 2 && (!vj || !vi)) return ORACLE_ERR_ARG;
   if (order == 6 && (!aj || !ai)) return ORACLE_ERR_ARG;
   if (h2 && (nbr_max < 0 || !nbr_count || (nbr_max > 0 && !nbr_ids))) return ORACLE_ERR_ARG;
 #ifdef _OPENMP
@@ -119,14 +134,14 @@ int oracle_force(int order, double eps2, int nj, const int64_t *idj, const doubl
     double best_r2 = INFINITY;
     int64_t best_id = -1;
     int32_t count = 0;
-    const double *x0 = xi + 3 * (size_t)i, *v0 = vi + 3 * (size_t)i;
+    const double *x0 = xi + 3 * (size_t)i, *v0 = (order == 2) ? NULL : vi + 3 * (size_t)i;
     const double *a0 = (order == 6) ? ai + 3 * (size_t)i : NULL;
     for (int j = 0; j < nj; ++j) {
       if (idj[j] == idi[i]) continue;
-      double r[3], v[3], a[3] = {0, 0, 0};
+      double r[3], v[3] = {0, 0, 0}, a[3] = {0, 0, 0};
       for (int k = 0; k < 3; ++k) {
         r[k] = xj[3 * (size_t)j + k] - x0[k];
-        v[k] = vj[3 * (size_t)j + k] - v0[k];
+        if (order != 2) v[k] = vj[3 * (size_t)j + k] - v0[k];
         if (order == 6) a[k] = aj[3 * (size_t)j + k] - a0[k];
       }
       const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
@@ -166,7 +181,7 @@ int oracle_force(int order, double eps2, int nj, const int64_t *idj, const doubl
     }
     for (int k = 0; k < 3; ++k) {
       acc[3 * (size_t)i + k] = (double)s_acc[k];
-      if (jerk) jerk[3 * (size_t)i + k] = (double)s_jerk[k];
+      if (jerk && order != 2) jerk[3 * (size_t)i + k] = (double)s_jerk[k];
       if (snap && order == 6) snap[3 * (size_t)i + k] = (double)s_snap[k];
     }
     if (pot) pot[i] = (double)s_pot;
@@ -175,7 +190,7 @@ int oracle_force(int order, double eps2, int nj, const int64_t *idj, const doubl
     if (h2) nbr_count[i] = count;
     if (cond) {
       cond[3 * (size_t)i + 0] = (double)s_c0;
-      cond[3 * (size_t)i + 1] = (double)s_c1;
+      cond[3 * (size_t)i + 1] = (order == 2) ? 0.0 : (double)s_c1;
       cond[3 * (size_t)i + 2] = (double)s_c2;
     }
   }

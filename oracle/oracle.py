@@ -86,14 +86,16 @@ def predict(order, t, tj, x, v, a, jerk, snap=None, crackle=None):
     """Taylor-predict every particle from its own time tj to t.
 
     Returns (xp, vp, ap); ap is the predicted acceleration (6th order), for
-    order 4 it is a + jerk*dt (returned for convenience, unused by 4th-order
-    forces).
+    order 4 it is a + jerk*dt and for order 2 it is a (returned for
+    convenience, unused by 2nd- and 4th-order forces).  jerk may be None for
+    order 2.
     """
     lib = _load()
     x = _f64(x)
     n = x.shape[0]
     tj = _f64(tj, (n,))
-    v, a, jerk = _f64(v, (n, 3)), _f64(a, (n, 3)), _f64(jerk, (n, 3))
+    v, a = _f64(v, (n, 3)), _f64(a, (n, 3))
+    jerk = _f64(jerk, (n, 3)) if order != 2 else None
     snap = _f64(snap, (n, 3)) if order == 6 else None
     crackle = _f64(crackle, (n, 3)) if order == 6 else None
     xp, vp, ap = np.empty((n, 3)), np.empty((n, 3)), np.empty((n, 3))
@@ -108,9 +110,10 @@ def predict(order, t, tj, x, v, a, jerk, snap=None, crackle=None):
 def force(order, eps2, idj, mj, xj, vj, idi, xi, vi, aj=None, ai=None, h2=None, nbr_max=0, nthreads=0):
     """Direct-summation forces of the sources (j) on the sinks (i).
 
-    Returns a dict with acc, jerk, snap (6th order), pot, nn_id, nn_r2,
-    cond (sum of |term| per sink for acc/jerk/snap) and, when h2 is given,
-    nbr_count and nbr_ids (first nbr_max ids in source order, -1 padded).
+    Returns a dict with acc, jerk (orders 4, 6), snap (6th order), pot, nn_id,
+    nn_r2, cond (sum of |term| per sink for acc/jerk/snap) and, when h2 is
+    given, nbr_count and nbr_ids (first nbr_max ids in source order, -1
+    padded).  Order 2 (GRAPE-5 mode) needs no velocities (vj, vi may be None).
     """
     lib = _load()
     xj = _f64(xj)
@@ -119,7 +122,9 @@ def force(order, eps2, idj, mj, xj, vj, idi, xi, vi, aj=None, ai=None, h2=None, 
     ni = xi.shape[0]
     idj = np.ascontiguousarray(idj, dtype=np.int64)
     idi = np.ascontiguousarray(idi, dtype=np.int64)
-    mj, vj, vi = _f64(mj, (nj,)), _f64(vj, (nj, 3)), _f64(vi, (ni, 3))
+    mj = _f64(mj, (nj,))
+    vj = _f64(vj, (nj, 3)) if order != 2 else None
+    vi = _f64(vi, (ni, 3)) if order != 2 else None
     if idj.shape != (nj,) or idi.shape != (ni,):
         raise ValueError("id arrays have the wrong length")
     aj = _f64(aj, (nj, 3)) if order == 6 else None
@@ -128,7 +133,7 @@ def force(order, eps2, idj, mj, xj, vj, idi, xi, vi, aj=None, ai=None, h2=None, 
         h2 = _f64(np.broadcast_to(np.asarray(h2, dtype=np.float64), (ni,)).copy(), (ni,))
     out = {
         "acc": np.zeros((ni, 3)),
-        "jerk": np.zeros((ni, 3)),
+        "jerk": np.zeros((ni, 3)) if order != 2 else None,
         "snap": np.zeros((ni, 3)) if order == 6 else None,
         "pot": np.zeros(ni),
         "nn_id": np.zeros(ni, dtype=np.int64),

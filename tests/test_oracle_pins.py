@@ -324,3 +324,106 @@ def test_oracle_independent_of_thread_count():
     r4 = _all_pairs(6, 1e-4, src.m, src.x, src.v, a=src.a, nthreads=4)
     for k in ("acc", "jerk", "snap", "pot", "nn_r2"):
         np.testing.assert_array_equal(r1[k], r4[k])
+
+
+# --------------------------------------------------------------------------------------------
+# 2nd-order (GRAPE-5, leapfrog) mode: acceleration and potential only, positions and masses are
+# all the force needs (Background: the library supports the 2nd-order leapfrog).  Pinned by the
+# exact circular orbit, Newton's third law, -grad of the potential, the 40-digit evaluation, the
+# predictor's exactness on quadratics and the 2nd-order convergence of a leapfrog built on it.
+# --------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("eps2", [0.0, 1e-2])
+def test_order2_circular_binary_without_velocities(eps2):
+    d, m1, m2 = 0.7, 0.9, 0.1
+    M = m1 + m2
+    R = math.sqrt(d * d + eps2)
+    w2 = M / R**3
+    th = 1.1
+    r = d * np.array([math.cos(th), math.sin(th), 0.0])
+    x = np.array([-(m2 / M) * r, (m1 / M) * r])
+    acc_true = -w2 * x  # centripetal, towards the centre of mass at the origin
+    ids = np.arange(2, dtype=np.int64)
+    out = oracle.force(2, eps2, ids, np.array([m1, m2]), x, None, ids, x, None)
+    assert out["jerk"] is None
+    np.testing.assert_allclose(out["acc"], acc_true, rtol=0, atol=1e-14 * np.abs(acc_true).max())
+    np.testing.assert_allclose(out["pot"], [-m2 / R, -m1 / R], rtol=1e-15)
+    assert list(out["nn_id"]) == [1, 0]
+
+
+def test_order2_newton_third_law_and_minus_grad_potential():
+    src = nbody_ics.make_sources(96, seed=21, masses="salpeter")
+    out = oracle.force(2, 1e-4, src.ids, src.m, src.x, None, src.ids, src.x, None)
+    total = np.sum(src.m[:, None] * out["acc"], axis=0)
+    assert np.all(np.abs(total) <= 1e-14 * np.sum(src.m[:, None] * np.abs(out["acc"])))
+    rng = np.random.default_rng(22)
+    y = rng.normal(0, 0.4, size=(4, 3))
+    ids = np.arange(5000, 5004, dtype=np.int64)
+    base = oracle.force(2, 0.02, src.ids, src.m, src.x, None, ids, y, None)
+    grad = np.zeros_like(y)
+    for k in range(3):
+        def pot_at(s):
+            yy = y.copy()
+            yy[:, k] += s
+            return oracle.force(2, 0.02, src.ids, src.m, src.x, None, ids, yy, None)["pot"]
+        grad[:, k] = _fd(pot_at, 1e-3)
+    np.testing.assert_allclose(base["acc"], -grad, rtol=0, atol=2e-8 * np.abs(base["acc"]).max())
+
+
+def test_order2_rounding_against_high_precision():
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 40
+    src = nbody_ics.make_sources(24, seed=23, masses="salpeter")
+    eps2 = 1e-5
+    out = oracle.force(2, eps2, src.ids, src.m, src.x, None, src.ids, src.x, None)
+    for i in (0, 11, 23):
+        acc = [mpmath.mpf(0)] * 3
+        pot = mpmath.mpf(0)
+        for j in range(24):
+            if j == i:
+                continue
+            r = [mpmath.mpf(src.x[j, k]) - mpmath.mpf(src.x[i, k]) for k in range(3)]
+            R2 = sum(c * c for c in r) + mpmath.mpf(eps2)
+            acc = [acc[k] + mpmath.mpf(src.m[j]) * r[k] / R2**1.5 for k in range(3)]
+            pot -= mpmath.mpf(src.m[j]) / mpmath.sqrt(R2)
+        ref = np.array([float(c) for c in acc])
+        assert np.abs(out["acc"][i] - ref).max() <= 1.6e-15 * np.abs(ref).max()
+        assert abs(out["pot"][i] - float(pot)) <= 4e-16 * abs(float(pot))
+
+
+def test_order2_predictor_exact_on_quadratics_ignores_jerk():
+    rng = np.random.default_rng(24)
+    n = 40
+    x0, v0, a0 = rng.normal(size=(3, n, 3))
+    jerk = rng.normal(size=(n, 3))  # not part of the 2nd-order polynomial
+    tj = rng.uniform(-1, 0, size=n)
+    t = 0.3
+    dt = (t - tj)[:, None]
+    xp, vp, ap = oracle.predict(2, t, tj, x0, v0, a0, jerk)
+    np.testing.assert_allclose(xp, x0 + v0 * dt + 0.5 * a0 * dt**2, rtol=1e-14, atol=1e-14)
+    np.testing.assert_allclose(vp, v0 + a0 * dt, rtol=1e-14, atol=1e-14)
+    np.testing.assert_array_equal(ap, a0)
+    xq, vq, _ = oracle.predict(2, t, tj, x0, v0, a0, None)
+    np.testing.assert_array_equal(xq, xp)
+    np.testing.assert_array_equal(vq, vp)
+
+
+def test_order2_leapfrog_circular_orbit_second_order():
+    # kick-drift-kick leapfrog driven by the 2nd-order forces: error falls as dt^2
+    m = np.array([0.5, 0.5])
+    ids = np.arange(2, dtype=np.int64)
+    x0 = np.array([[-0.5, 0, 0], [0.5, 0, 0]])
+    v0 = np.array([[0, -0.5, 0], [0, 0.5, 0]])
+    errs = []
+    for nsteps in (32, 64, 128):
+        dt = 1.0 / nsteps
+        x, v = x0.copy(), v0.copy()
+        a = oracle.force(2, 0.0, ids, m, x, None, ids, x, None)["acc"]
+        for _ in range(nsteps):
+            v = v + 0.5 * dt * a
+            x = x + dt * v
+            a = oracle.force(2, 0.0, ids, m, x, None, ids, x, None)["acc"]
+            v = v + 0.5 * dt * a
+        exact = 0.5 * np.array([math.cos(1.0), math.sin(1.0), 0.0])
+        errs.append(np.abs(x[1] - exact).max())
+    for e1, e2 in zip(errs, errs[1:]):
+        assert 3.0 < e1 / e2 < 5.0, errs  # 2^2 = 4
