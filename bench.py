@@ -27,7 +27,9 @@ sys.path.insert(0, ROOT)
 
 N = 131072
 EPS2 = 1e-6
+BS_EPS2 = 1e-6  # softening of the block time-step runs
 FLOPS_4TH = 42  # algorithmic flops per 4th-order acc+jerk+pot interaction (FMA = 2, rsqrt = 1)
+FLOPS_2ND = 20  # algorithmic flops per 2nd-order acc+pot interaction (3 dx, 6 R^2, 1 rsqrt, 3 powers, 6 acc, 1 pot)
 PEAK_FP32 = 157.3  # TFLOP/s, MI355X FP32 vector
 PEAK_FP64 = 78.6  # TFLOP/s, MI355X FP64 vector
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_force_mixed_plummer131072_traffic.json")
@@ -73,6 +75,12 @@ def parse():
     ap.add_argument("--adjoint", action="store_true",
                     help="also time the adjoint on a 65536-body Plummer sphere (eps2=1e-6): forward forces, the "
                          "vector-Jacobian product, and the gradient through 16 checkpointed Hermite steps (dt=1/512)")
+    ap.add_argument("--order2", action="store_true",
+                    help="also time the 2nd-order (GRAPE-5) mode, acc+pot+NN, on the same N=131072 sources, "
+                         "N_i in {1024, 16384, 131072}")
+    ap.add_argument("--blockstep", type=str, default="", metavar="N,N,...",
+                    help="also run the 6th-order block time-step Hermite integrator for one N-body time unit "
+                         "(eta4=0.01, eta6=0.1, eps2=1e-6) on Plummer spheres of these sizes, FP64 and mixed")
     ap.add_argument("--order6", action="store_true",
                     help="also time 6th-order forces with neighbour lists on a 1048576-body Plummer/Salpeter "
                          "cluster (eps2=1e-8, h2=1e-4, at most 256 neighbours), N_i in {1024, 65536, 1048576}")
@@ -219,6 +227,93 @@ def order6(torch, nbx, ics, dev, steps):
     return {"workload": "Plummer N=1048576, Salpeter masses (slope -2.35, 0.1-100, total 1), eps2=1e-8, "
                         "6th-order acc+jerk+snap+pot+NN+neighbour lists (h2=1e-4, max 256)",
             "flops_per_interaction": 79, "rows": rows, "list_status": status}
+
+
+def order2(torch, nbx, ics, dev, steps):
+    """2nd-order (GRAPE-5) mode on the headline sources: acc + pot + NN; kernel time per precision."""
+    import numpy as np
+
+    src = ics.make_sources(N, seed=2)
+    stream = torch.cuda.current_stream()
+    T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    f64, i64, i32 = torch.float64, torch.int64, torch.int32
+    ctx = nbx.Context(order=2, precision=nbx.NBX_MIXED, nj_max=N, ni_max=N)
+    nbx.nbx_set_j_dev(ctx.ctx, stream, N, T(np.arange(N), i32), T(src.ids, i64), T(src.m, f64), T(src.t, f64),
+                      T(src.x, f64), T(src.v, f64), T(src.a, f64), None)
+    nbx.nbx_set_nj(ctx.ctx, N)
+    nbx.nbx_predict(ctx.ctx, 0.0)
+    acc = torch.empty((N, 3), dtype=f64, device=dev)
+    pot, nnr2 = torch.empty(N, dtype=f64, device=dev), torch.empty(N, dtype=f64, device=dev)
+    nnid = torch.empty(N, dtype=i64, device=dev)
+    rows = []
+    for ni in (1024, 16384, N):
+        sel = T(ics.active_set(N, ni, seed=1002), i32)
+        sh = ctx.launch_shape(ni)
+        row = {"ni": ni, "shape": "L%d P%d S%d wg%d" % (sh["lanes_per_sink"], sh["sinks_per_lane"], sh["splits"],
+                                                      sh["workgroups"])}
+        for prec, name in ((nbx.NBX_FP64, "fp64"), (nbx.NBX_MIXED, "mixed")):
+            ctx.set_precision(prec)
+
+            def go():
+                nbx.nbx_force_dev(ctx.ctx, stream, ni, sel, EPS2, None, acc, None, None, pot, nnid, nnr2)
+
+            go()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                go()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            row[name + "_kernel_ms"] = round(ms, 4)
+            row[name + "_int_s"] = float("%.4g" % (ni * float(N) / (ms * 1e-3)))
+            peak = PEAK_FP32 if prec == nbx.NBX_MIXED else PEAK_FP64
+            row[name + "_roofline_frac"] = round(FLOPS_2ND * ni * float(N) / (ms * 1e-3) / 1e12 / peak, 4)
+        row["speedup"] = round(row["fp64_kernel_ms"] / row["mixed_kernel_ms"], 3)
+        rows.append(row)
+        print("bench: order2 %s" % json.dumps(row), file=sys.stderr, flush=True)
+    nbx.nbx_sync(ctx.ctx, stream)
+    ctx.close()
+    return {"workload": "Plummer N=131072 (seed 2), eps2=1e-6, per-source times, 2nd-order (GRAPE-5) acc+pot+NN",
+            "flops_per_interaction": FLOPS_2ND, "rows": rows}
+
+
+def blockstep(torch, nbx, ics, sizes):
+    """6th-order block time-step runs, one N-body time unit, FP64 (DP) and mixed (DS): wall time from
+    the start to the end of the integration, energy error, block steps and mean N_active."""
+    import numpy as np
+
+    rows = []
+    for n in sizes:
+        m, x, v = ics.plummer(n, seed=7)
+        for prec, name in ((nbx.NBX_FP64, "fp64"), (nbx.NBX_MIXED, "mixed")):
+            ctx = nbx.Context(order=6, precision=prec, nj_max=n, ni_max=n)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            nbx.nbx_bs_init(ctx.ctx, np.arange(n), m, x, v, BS_EPS2)
+            e0 = sum(nbx.nbx_bs_energy(ctx.ctx))
+            t1 = time.perf_counter()
+            for k in range(1, 9):  # one time unit in eighths, with a progress line each
+                st = nbx.nbx_bs_run(ctx.ctx, k / 8.0)
+                print("bench: blockstep n=%d %s t=%g blocks=%d status=%d" % (n, name, st["t"], st["block_steps"],
+                                                                            st["status"]), file=sys.stderr,
+                      flush=True)
+                if st["status"] != nbx.NBX_OK:
+                    break
+            t2 = time.perf_counter()
+            e1 = sum(nbx.nbx_bs_energy(ctx.ctx))
+            ctx.close()
+            row = {"n": n, "precision": name, "init_s": round(t1 - t0, 4), "run_s": round(t2 - t1, 4),
+                   "block_steps": st["block_steps"], "particle_steps": st["particle_steps"],
+                   "mean_n_active": round(st["particle_steps"] / max(st["block_steps"], 1), 2),
+                   "energy_error": float("%.3e" % abs((e1 - e0) / e0)), "status": st["status"],
+                   "interactions_per_s": float("%.4g" % (st["particle_steps"] * float(n) / (t2 - t1)))}
+            rows.append(row)
+            print("bench: blockstep %s" % json.dumps(row), file=sys.stderr, flush=True)
+    return {"workload": "Plummer spheres (seed 7), 6th-order Hermite block time steps, averaged Aarseth/6th-order "
+                        "criterion eta4=0.01 eta6=0.1, eps2=%g, dt_max=1/8, one N-body time unit" % BS_EPS2,
+            "rows": rows}
 
 
 def batch(torch, nbx, ics, dev, steps):
@@ -379,6 +474,8 @@ def main():
     nbx.nbx_sync(ctx.ctx, stream)
     ctx.close()
 
+    o2 = order2(torch, nbx, nbody_ics, dev, max(3, args.steps // 2)) if args.order2 else None
+    bsr = blockstep(torch, nbx, nbody_ics, [int(k) for k in args.blockstep.split(",")]) if args.blockstep else None
     o6 = order6(torch, nbx, nbody_ics, dev, max(2, args.steps // 10)) if args.order6 else None
     bt = batch(torch, nbx, nbody_ics, dev, max(20, args.steps)) if args.batch else None
     adj = adjoint(torch, nbx, nbody_ics, dev, max(3, args.steps // 5)) if args.adjoint else None
@@ -430,6 +527,10 @@ def main():
         "cpu_baseline": cpu,
         "sweep": sweep,
     }
+    if o2 is not None:
+        line["order2"] = o2
+    if bsr is not None:
+        line["blockstep"] = bsr
     if o6 is not None:
         line["order6"] = o6
     if bt is not None:

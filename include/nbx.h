@@ -28,7 +28,9 @@
  * Sources with the sink's own id are excluded from every output.  Jerk and
  * snap are the time derivatives of the softened acceleration along the
  * predicted motion, as a 4th/6th-order Hermite integrator needs them
- * (Results; Results > Sixth order performance).
+ * (Results; Results > Sixth order performance).  Order 2 is the GRAPE-5 mode
+ * for a 2nd-order leapfrog (Background; Conclusions): acc and pot only, from
+ * positions and masses; its predictor stops at the acceleration term.
  *
  * Nearest neighbour (Results; Discussion > CPU: particle id and distance):
  * the other source with the smallest |r|^2, returned as (id, |r|^2 in FP64);
@@ -76,6 +78,7 @@ extern "C" {
 
 #define NBX_OK 0
 #define NBX_WARN_NBR_OVERFLOW 1 /* a neighbour list was truncated to nbr_max (counts stay exact) */
+#define NBX_WARN_DT_MIN 2       /* a block time-step was clamped at dt_min (or its criterion was not a number) */
 #define NBX_ERR_ARG (-1)        /* NULL pointer, negative size, bad order/precision, address out of range */
 #define NBX_ERR_CAPACITY (-2)   /* n > nj_max or ni > ni_max */
 #define NBX_ERR_STATE (-3)      /* call out of order (force before predict, get before force, ...) */
@@ -90,7 +93,8 @@ typedef struct nbx_ctx nbx_ctx; /* opaque; owns every device buffer it allocates
 
 typedef struct nbx_config {
   int device;    /* HIP device ordinal */
-  int order;     /* 4: acc, jerk, pot;  6: also snap (needs snap and crackle of the sources) */
+  int order;     /* 2: acc, pot (GRAPE-5 mode);  4: acc, jerk, pot;  6: also snap (needs snap and
+                    crackle of the sources) */
   int precision; /* NBX_FP64 or NBX_MIXED; can be changed later with nbx_set_precision */
   int nj_max;    /* source capacity (addresses 0 .. nj_max-1) */
   int ni_max;    /* largest number of sinks in one nbx_force call */
@@ -104,7 +108,7 @@ int nbx_version(void);
 int nbx_device_count(int *count);
 
 /* Create a context on cfg->device and allocate its source/sink buffers.
- * Errors: NBX_ERR_ARG (NULL, order not 4/6, bad precision, nj_max < 1,
+ * Errors: NBX_ERR_ARG (NULL, order not 2/4/6, bad precision, nj_max < 1,
  * ni_max < 1, nbr_max < 0), NBX_ERR_NO_DEVICE, NBX_ERR_OOM, NBX_ERR_DEVICE.
  * On error *out is NULL. */
 int nbx_open(nbx_ctx **out, const nbx_config *cfg);
@@ -125,8 +129,10 @@ int nbx_set_nj(nbx_ctx *ctx, int nj);
 
 /* Copy n sources from host arrays into addresses addr[k] (the copy step).  id[n], m[n], t[n]
  * (the time the Taylor data refers to), x, v, a, jerk [n][3]; snap and crackle [n][3] for order 6
- * (NULL for order 4).  Every addr must be in [0, nj_max) (else NBX_ERR_ARG, nothing copied); the
- * number of sources in use grows to cover the highest address written.  Synchronous. */
+ * (NULL for order 4).  Order 2: v and a may be NULL (taken as zero) and jerk is ignored (may be
+ * NULL); the predictor uses x + v dt + a dt^2/2.  Every addr must be in [0, nj_max) (else
+ * NBX_ERR_ARG, nothing copied); the number of sources in use grows to cover the highest address
+ * written.  Synchronous. */
 int nbx_set_j(nbx_ctx *ctx, int n, const int32_t *addr, const int64_t *id, const double *m,
               const double *t, const double *x, const double *v, const double *a,
               const double *jerk, const double *snap, const double *crackle);
@@ -143,15 +149,15 @@ int nbx_predict(nbx_ctx *ctx, double t);
  * context's stream; returns without waiting for the GPU. */
 int nbx_force(nbx_ctx *ctx, int ni, const int32_t *i_addr, double eps2, const double *h2);
 
-/* Forces on ni sinks given explicitly (they need not be sources): id[ni], x, v [ni][3], a [ni][3]
- * for order 6 (else NULL).  A source with the sink's id is excluded.  The sink state is used as
+/* Forces on ni sinks given explicitly (they need not be sources): id[ni], x, v [ni][3] (v may be
+ * NULL for order 2), a [ni][3] for order 6 (else NULL).  A source with the sink's id is excluded.  The sink state is used as
  * given (no prediction).  Otherwise as nbx_force. */
 int nbx_force_ext(nbx_ctx *ctx, int ni, const int64_t *id, const double *x, const double *v,
                   const double *a, double eps2, const double *h2);
 
 /* Wait for the last nbx_force / nbx_force_ext and copy its results to caller-owned host arrays:
- * acc, jerk [ni][3], snap [ni][3] (order 6), pot [ni], nn_id [ni], nn_r2 [ni].  Any pointer may be
- * NULL to skip that output.  Returns NBX_WARN_NBR_OVERFLOW if a neighbour list overflowed. */
+ * acc, jerk [ni][3] (orders 4, 6; never written for order 2), snap [ni][3] (order 6), pot [ni],
+ * nn_id [ni], nn_r2 [ni].  Any pointer may be NULL to skip that output.  Returns NBX_WARN_NBR_OVERFLOW if a neighbour list overflowed. */
 int nbx_get_force(nbx_ctx *ctx, double *acc, double *jerk, double *snap, double *pot,
                   int64_t *nn_id, double *nn_r2);
 
@@ -171,7 +177,8 @@ int nbx_get_j(nbx_ctx *ctx, int n, const int32_t *addr, int64_t *id, double *m, 
 
 /* ---- device-pointer variants (caller-owned device memory and stream; enqueue only) ---------- */
 
-/* As nbx_set_j, from device arrays.  Out-of-range addresses are skipped and counted; the next
+/* As nbx_set_j, from device arrays (order 2: d_v, d_a, d_jerk may be NULL, as there).  Out-of-range
+ * addresses are skipped and counted; the next
  * nbx_sync reports them as NBX_ERR_ARG.  The number of sources in use is not changed: call
  * nbx_set_nj. */
 int nbx_set_j_dev(nbx_ctx *ctx, void *stream, int n, const int32_t *d_addr, const int64_t *d_id,
@@ -180,7 +187,8 @@ int nbx_set_j_dev(nbx_ctx *ctx, void *stream, int n, const int32_t *d_addr, cons
                   const double *d_crackle);
 
 /* As nbx_force, with the sink addresses and every output in caller device memory:
- * d_acc, d_jerk [ni][3] (required), d_snap [ni][3] (order 6, else may be NULL), d_pot [ni],
+ * d_acc, d_jerk [ni][3] (required; d_jerk may be NULL for order 2 and is not written there),
+ * d_snap [ni][3] (order 6, else may be NULL), d_pot [ni],
  * d_nn_id [ni], d_nn_r2 [ni] (required); d_nbr_count [ni] and d_nbr_ids [ni][nbr_max] when d_h2
  * is given.  Sink addresses outside [0, nj) make the kernel skip that sink (its outputs are left
  * untouched) and are counted for nbx_sync. */
@@ -228,6 +236,68 @@ int nbx_batch_tune(nbx_ctx *ctx, void *stream, const double *d_m, const double *
  * (L = 64 / next power of two of the class's largest size, at least 1). */
 int nbx_batch_force_dev(nbx_ctx *ctx, void *stream, const double *d_m, const double *d_x, const double *d_v,
                         double eps2, double *d_acc, double *d_jerk, double *d_pot);
+
+/* ---- block time-step Hermite integrator ---------------------------------------------------------
+ * The integrator the paper runs on top of the library (Results > Block time-step simulations):
+ * 4th- or 6th-order Hermite (the context's order) with individual power-of-two time steps, kept
+ * resident on the device.  The particles are the context's sources 0..n-1 (nbx_bs_init loads
+ * them; any later nbx_set_j / nbx_set_j_dev ends the integration), every block step predicts all
+ * of them to the block time, computes the forces on the particles due at that time (the gravity
+ * kernel at the context's precision), corrects them and picks their next steps, all on the GPU;
+ * only the block time and N_active return to the host.  Corrector (h = dt/2):
+ *   order 4: v1 = v0 + h (a0 + a1) - h^2/3 (j1 - j0),  x1 = x0 + h (v0 + v1) - h^2/3 (a1 - a0)
+ *   order 6: v1 = v0 + h (a0 + a1) - 2h^2/5 (j1 - j0) + h^3/15 (s0 + s1),
+ *            x1 = x0 + h (v0 + v1) - 2h^2/5 (a1 - a0) + h^3/15 (j0 + j1)
+ * (the integrals of the Hermite interpolants).  Higher derivatives a2..a5 at the end of a step come
+ * from the interpolant of the acceleration (cubic through a, j; quintic through a, j, s).
+ * Step criteria: Aarseth dt4 = sqrt(eta4 (|a||a2| + |a1|^2) / (|a1||a3| + |a2|^2)); order 6 takes
+ * the average of dt4 and dt6 = eta6 ((|a||a2| + |a1|^2) / (|a3||a5| + |a4|^2))^(1/6), as the paper
+ * does for its DS and DP runs (the 6th-order criterion alone can collapse when jerk and snap carry
+ * rounding noise).  A step halves until it is at most the criterion and doubles, at most once per
+ * step and up to dt_max, when the criterion allows it and the new time is a multiple of the doubled
+ * step.  The first step is eta_start |a|/|j| (order 6: at most eta_start sqrt(|a|/|s|)) rounded
+ * down to a power of two; the crackle starts at zero. */
+typedef struct nbx_bs_params {
+  double eps2;      /* softening */
+  double eta4;      /* Aarseth accuracy parameter (the paper: 0.01) */
+  double eta6;      /* 6th-order accuracy parameter (the paper: 0.1; order 6 only) */
+  double eta_start; /* first-step parameter (e.g. 0.01) */
+  double dt_max;    /* largest step, a power of two <= 1 */
+  double dt_min;    /* smallest step, a power of two <= dt_max (smaller requests are clamped) */
+} nbx_bs_params;
+
+typedef struct nbx_bs_stats {
+  double t;               /* current block time */
+  int64_t block_steps;    /* block steps since nbx_bs_init */
+  int64_t particle_steps; /* sum of N_active over those steps (interactions = particle_steps * n) */
+} nbx_bs_stats;
+
+/* Start an integration at t = 0 from host arrays id[n], m[n], x, v [n][3] (1 <= n <= nj_max and
+ * <= ni_max; order 4 or 6).  Computes the starting forces (order 6: two passes, the snap needs the
+ * accelerations) and first steps.  Synchronous.  NBX_WARN_DT_MIN if a first step was clamped. */
+int nbx_bs_init(nbx_ctx *ctx, int n, const int64_t *id, const double *m, const double *x,
+                const double *v, const nbx_bs_params *p);
+
+/* One block step, if the next block time is <= t_end; *n_active (may be NULL) receives N_active
+ * (0: no step taken).  Returns after enqueueing the corrector (waits only for the schedule).  Once
+ * any step has been clamped at dt_min it takes no further step and returns NBX_WARN_DT_MIN: the
+ * step criterion has collapsed (the paper sees this for the 6th-order criterion when the forces
+ * are not accurate enough); the state stays valid and readable. */
+int nbx_bs_step(nbx_ctx *ctx, double t_end, int *n_active);
+
+/* Block steps until the next block time would pass t_end; stats (may be NULL) as after the run.
+ * Stops early with NBX_WARN_DT_MIN as soon as a step has been clamped at dt_min (stats.t then
+ * shows how far it got). */
+int nbx_bs_run(nbx_ctx *ctx, double t_end, nbx_bs_stats *stats);
+
+/* State at the current block time: x, v [n][3] (predicted for particles between their steps), dt
+ * [n] current steps, t_i [n] the particles' own times, stats; every output may be NULL. */
+int nbx_bs_get_state(nbx_ctx *ctx, double *t, double *x, double *v, double *dt, double *t_i,
+                     nbx_bs_stats *stats);
+
+/* Kinetic and potential energy at the current block time (positions and velocities predicted;
+ * the potential from a force evaluation on all particles; sums in long double).  Synchronous. */
+int nbx_bs_energy(nbx_ctx *ctx, double *ekin, double *epot);
 
 /* Wait for all work this context enqueued (on its own stream and on stream) and report
  * device-side argument errors (NBX_ERR_ARG) or neighbour-list overflow (NBX_WARN_NBR_OVERFLOW)

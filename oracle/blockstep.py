@@ -23,6 +23,9 @@ paper prints none of the formulas; this module writes the method out from its de
     eta_start sqrt(|a|/|s|)) rounded down to a power of two, crackle zero.
   * Each block step advances the particles whose t_i + dt_i is the smallest; every particle is
     predicted to that time (the oracle's Taylor predictor) and the active ones feel all of them.
+  * Once a step has been clamped at dt_min the integration stops: the criterion has collapsed,
+    which the paper reports for the 6th-order criterion when the forces carry too much rounding
+    noise (Results > Block time-step simulations).
 """
 
 from __future__ import annotations
@@ -178,7 +181,9 @@ class BlockStep:
         self.dt = first_step(order, self.a, self.j, self.s, eta_start, dt_max, dt_min)
 
     def step(self, t_end):
-        """One block step if due by t_end; returns N_active (0: none)."""
+        """One block step if due by t_end; returns N_active (0: none, or stopped after a clamp)."""
+        if self.clamped:
+            return 0
         tn_all = self.t_i + self.dt
         tn = tn_all.min()
         if not tn <= t_end:

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnbx.so")
-SOURCES = ["nbx_kernels.hip", "nbx_runtime.hip"]
+SOURCES = ["nbx_kernels.hip", "nbx_blockstep.hip", "nbx_runtime.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 (v_pk_*_f32) generation is switched off: every FP32 op is a plain VALU op.

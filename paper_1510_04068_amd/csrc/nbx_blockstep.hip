@@ -1,0 +1,392 @@
+// nbx_blockstep.hip -- device-resident block time-step Hermite integrator (4th and 6th order).
+//
+// The paper's library leaves the integrator to the host code (Results > Block time-step
+// simulations: the host does the corrections, the time-step computation and the particle copies,
+// the GPU the prediction and the gravity).  Here those host steps run as kernels on the same
+// stream, so a block step moves no particle data over PCIe: the particle state lives in the
+// library's FP64 source arrays, and only (t_next, N_active) comes back to the host each block step
+// (the force launch shape depends on N_active).
+//
+// One block step:
+//   1. schedule: t_next = min_i (t_i + dt_i) and the ordered list of the particles with
+//      t_i + dt_i == t_next (k_bs_min, k_bs_count, k_bs_list; no atomics, so the list is in
+//      address order and the step is deterministic);
+//   2. forces on the active particles at t_next: the gravity kernel (fused predictor);
+//   3. correct, choose the next step and write the new state back into the source arrays
+//      (k_bs_correct).
+//
+// Hermite corrector (Makino & Aarseth 1992 for 4th order; Nitadori & Makino 2008 for 6th), with
+// h = dt/2.  Each line is the integral over the step of the Hermite interpolant of the integrand
+// through its values and derivatives at both ends:
+//   4th: v1 = v0 + h (a0 + a1) - h^2/3 (j1 - j0)
+//        x1 = x0 + h (v0 + v1) - h^2/3 (a1 - a0)
+//   6th: v1 = v0 + h (a0 + a1) - 2h^2/5 (j1 - j0) + h^3/15 (s0 + s1)
+//        x1 = x0 + h (v0 + v1) - 2h^2/5 (a1 - a0) + h^3/15 (j0 + j1)
+// The higher derivatives at t1 come from the same interpolant of the acceleration (cubic through
+// a, j; quintic through a, j, s) written about the mid-point, tau in [-h, h]:
+//   cubic:   c2 = (j1 - j0) / (4h),                 c3 h^3 = (h (j0 + j1) - (a1 - a0)) / 4
+//   quintic: c4 h^4 = (h^2 (s0 + s1) - h (j1 - j0)) / 16
+//            c5 h^5 = (h^2 (s1 - s0) - 3h (j0 + j1) + 3 (a1 - a0)) / 16
+//            c3 h^3 = (5h (j0 + j1) - 5 (a1 - a0) - h^2 (s1 - s0)) / 8
+// and a^(k)(h) follows by differentiating sum c_m tau^m.
+//
+// Time-step criteria (Results > Block time-step simulations; the paper prints no formula):
+//   Aarseth:      dt4 = sqrt(eta4 (|a||a2| + |a1|^2) / (|a1||a3| + |a2|^2))
+//   6th order:    dt6 = eta6 ((|a||a2| + |a1|^2) / (|a3||a5| + |a4|^2))^(1/6)
+//   order 4 uses dt4; order 6 uses the average (dt4 + dt6) / 2, the choice the paper makes for
+//   both its DS and DP runs because dt6 alone can collapse when jerk and snap carry rounding noise.
+// Block quantisation: steps are powers of two; a particle halves its step until it is at most the
+// criterion, and doubles it (once per step, up to dt_max) only when the criterion allows twice the
+// step and the new time is a multiple of twice the step, so that blocks stay synchronised.  A step
+// that would fall below dt_min is clamped there and counted; the host stops integrating once the
+// count is non-zero (the interpolated derivatives are dominated by force rounding noise, which the
+// paper observed for the 6th-order criterion with double-single forces).
+
+#include "nbx.h"
+#include "nbx_internal.h"
+#include "nbx_predict.h"
+
+namespace nbx {
+
+constexpr int kBsPer = kBsChunk / kThreads;  // particles per thread in the scheduling kernels
+
+__device__ __forceinline__ double wave_min(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
+  return v;
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Minimum over the workgroup, returned to every thread.
+__device__ double block_min(double v, double *red) {
+  v = wave_min(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double m = red[0];
+#pragma unroll
+  for (int w = 1; w < kThreads / 64; ++w) m = fmin(m, red[w]);
+  __syncthreads();
+  return m;
+}
+
+// Sum over the workgroup, returned to every thread.
+__device__ int block_sum(int v, int *red) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int s = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+
+// Exclusive prefix sum over the workgroup in thread order; *total receives the sum.
+__device__ int block_exclusive_scan(int v, int *red, int *total) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  int inc = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int o = __shfl_up(inc, off);
+    if (lane >= off) inc += o;
+  }
+  if (lane == 63) red[wave] = inc;
+  __syncthreads();
+  int before = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) {
+    if (w < wave) before += red[w];
+    all += red[w];
+  }
+  __syncthreads();
+  *total = all;
+  return before + inc - v;
+}
+
+// 1. per-workgroup minimum of t_i + dt_i over its chunk of kBsChunk particles
+__global__ __launch_bounds__(kThreads) void k_bs_min(BlockStepParams bp) {
+  __shared__ double red[kThreads / 64];
+  const int b0 = blockIdx.x * kBsChunk;
+  double m = __builtin_huge_val();
+#pragma unroll
+  for (int r = 0; r < kBsPer; ++r) {
+    const int i = b0 + r * kThreads + threadIdx.x;
+    if (i < bp.n) m = fmin(m, bp.tnext[i]);
+  }
+  m = block_min(m, red);
+  if (threadIdx.x == 0) bp.wg_min[blockIdx.x] = m;
+}
+
+// 2. every workgroup reduces all partial minima to t_next, counts its active particles;
+//    workgroup 0 publishes t_next
+__global__ __launch_bounds__(kThreads) void k_bs_count(BlockStepParams bp) {
+  __shared__ double red[kThreads / 64];
+  __shared__ int redi[kThreads / 64];
+  const int nwg = gridDim.x;
+  double m = __builtin_huge_val();
+  for (int k = threadIdx.x; k < nwg; k += kThreads) m = fmin(m, bp.wg_min[k]);
+  const double tn = block_min(m, red);
+  const int b0 = blockIdx.x * kBsChunk;
+  int c = 0;
+#pragma unroll
+  for (int r = 0; r < kBsPer; ++r) {
+    const int i = b0 + r * kThreads + threadIdx.x;
+    if (i < bp.n && bp.tnext[i] == tn) ++c;
+  }
+  c = block_sum(c, redi);
+  if (threadIdx.x == 0) {
+    bp.wg_cnt[blockIdx.x] = c;
+    if (blockIdx.x == 0) bp.sched->t_next = tn;
+  }
+}
+
+// 3. ordered compaction: workgroup b writes its active particles, in address order, after those
+//    of workgroups 0..b-1; the last workgroup publishes the count
+__global__ __launch_bounds__(kThreads) void k_bs_list(BlockStepParams bp) {
+  __shared__ int redi[kThreads / 64];
+  const int b = blockIdx.x;
+  int before = 0;
+  for (int k = threadIdx.x; k < b; k += kThreads) before += bp.wg_cnt[k];
+  const int offset = block_sum(before, redi);
+  const double tn = bp.sched->t_next;
+  // thread t owns the kBsPer consecutive particles b0 + t*kBsPer ... (address order = thread order)
+  const int i0 = b * kBsChunk + threadIdx.x * kBsPer;
+  bool act[kBsPer];
+  int mine = 0;
+#pragma unroll
+  for (int r = 0; r < kBsPer; ++r) {
+    const int i = i0 + r;
+    act[r] = i < bp.n && bp.tnext[i] == tn;
+    mine += act[r] ? 1 : 0;
+  }
+  int total = 0;
+  int pos = offset + block_exclusive_scan(mine, redi, &total);
+#pragma unroll
+  for (int r = 0; r < kBsPer; ++r)
+    if (act[r]) bp.list[pos++] = i0 + r;
+  if (b == gridDim.x - 1 && threadIdx.x == 0) bp.sched->count = offset + total;
+}
+
+__device__ __forceinline__ double norm3(const double v[3]) { return sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); }
+
+// Power-of-two step for the criterion `crit`, from the current step dt_old ending at t1.
+__device__ void report_clamp(const BlockStepParams &bp) {
+  atomicAdd(&bp.err[3], 1);
+  atomicAdd(&bp.sched->clamped, 1);
+}
+
+__device__ double quantise(double crit, double dt_old, double t1, const BlockStepParams &bp) {
+  if (!(crit >= 0.0)) {  // NaN or negative: keep the step and report it
+    report_clamp(bp);
+    return dt_old;
+  }
+  double dn = dt_old;
+  if (crit < dt_old) {
+    while (dn > crit && dn > bp.dt_min) dn *= 0.5;
+    if (dn > crit) report_clamp(bp);  // clamped at dt_min
+  } else if (crit >= 2.0 * dt_old && 2.0 * dt_old <= bp.dt_max && fmod(t1, 2.0 * dt_old) == 0.0) {
+    dn = 2.0 * dt_old;
+  }
+  return dn;
+}
+
+// Ratio guard: a zero denominator (e.g. a particle far from everything) allows the largest step.
+__device__ __forceinline__ double safe_ratio(double num, double den, double big) {
+  return den > 0.0 ? num / den : big;
+}
+
+template <int Order>
+__global__ __launch_bounds__(kThreads) void k_bs_correct(BlockStepParams bp, int ni, double t1) {
+  const int k = blockIdx.x * kThreads + threadIdx.x;
+  if (k >= ni) return;
+  const int i = bp.list[k];
+  Raw r;
+  load_raw<Order>(bp.src, i, r);
+  const double dt = bp.dt[i];
+  const double h = 0.5 * dt;
+  const double h2 = h * h;
+  double a1[3], j1[3], s1[3] = {0.0, 0.0, 0.0}, x1[3], v1[3];
+  double d2[3], d3[3], d4[3] = {0.0, 0.0, 0.0}, d5[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    a1[c] = bp.acc[3 * (size_t)k + c];
+    j1[c] = bp.jrk[3 * (size_t)k + c];
+    if constexpr (Order == 6) s1[c] = bp.snp[3 * (size_t)k + c];
+    const double am = a1[c] - r.a[c], ap = a1[c] + r.a[c];
+    const double jm = j1[c] - r.j[c], jp = j1[c] + r.j[c];
+    if constexpr (Order == 4) {
+      v1[c] = r.v[c] + h * ap - (h2 / 3.0) * jm;
+      x1[c] = r.x[c] + h * (r.v[c] + v1[c]) - (h2 / 3.0) * am;
+      const double c2 = jm / (4.0 * h);
+      const double c3 = (h * jp - am) / (4.0 * h2 * h);
+      d2[c] = 2.0 * c2 + 6.0 * c3 * h;
+      d3[c] = 6.0 * c3;
+    } else {
+      const double sm = s1[c] - r.s[c], sp = s1[c] + r.s[c];
+      v1[c] = r.v[c] + h * ap - (0.4 * h2) * jm + (h2 * h / 15.0) * sp;
+      x1[c] = r.x[c] + h * (r.v[c] + v1[c]) - (0.4 * h2) * am + (h2 * h / 15.0) * jp;
+      const double w4 = (h2 * sp - h * jm) / 16.0;               // c4 h^4
+      const double w5 = (h2 * sm - 3.0 * h * jp + 3.0 * am) / 16.0;  // c5 h^5
+      const double w3 = (5.0 * h * jp - 5.0 * am - h2 * sm) / 8.0;   // c3 h^3
+      const double h3 = h2 * h, h4 = h2 * h2, h5 = h4 * h;
+      d2[c] = s1[c];
+      d3[c] = (6.0 * w3 + 24.0 * w4 + 60.0 * w5) / h3;
+      d4[c] = (24.0 * w4 + 120.0 * w5) / h4;
+      d5[c] = 120.0 * w5 / h5;
+    }
+  }
+  const double na = norm3(a1), nj = norm3(j1), n2 = norm3(d2), n3 = norm3(d3);
+  const double big = bp.dt_max * bp.dt_max * 4.0;
+  const double num = na * n2 + nj * nj;
+  double crit = sqrt(bp.eta4 * safe_ratio(num, nj * n3 + n2 * n2, big / bp.eta4));
+  if constexpr (Order == 6) {
+    const double n4 = norm3(d4), n5 = norm3(d5);
+    const double q = safe_ratio(num, n3 * n5 + n4 * n4, -1.0);
+    const double dt6 = q < 0.0 ? 2.0 * bp.dt_max : bp.eta6 * pow(q, 1.0 / 6.0);
+    crit = 0.5 * (crit + dt6);
+  }
+  const double dn = quantise(crit, dt, t1, bp);
+  bp.src.pos_mass[i] = make_double4(x1[0], x1[1], x1[2], r.m);
+  bp.src.vel_time[i] = make_double4(v1[0], v1[1], v1[2], t1);
+  double *aj = bp.src.acc_jrk + 6 * (size_t)i;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    aj[c] = a1[c];
+    aj[3 + c] = j1[c];
+  }
+  if constexpr (Order == 6) {
+    double *sc = bp.src.snp_crk + 6 * (size_t)i;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      sc[c] = s1[c];
+      sc[3 + c] = d3[c];  // crackle at t1 for the next prediction
+    }
+  }
+  bp.dt[i] = dn;
+  bp.tnext[i] = t1 + dn;
+}
+
+// Start: particles at t = 0 with no derivatives yet; list = 0..n-1.
+template <int Order>
+__global__ __launch_bounds__(kThreads) void k_bs_load(BlockStepParams bp, const int64_t *id, const double *m,
+                                                      const double *x, const double *v) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= bp.n) return;
+  const size_t b = 3 * (size_t)i;
+  bp.src.pos_mass[i] = make_double4(x[b], x[b + 1], x[b + 2], m[i]);
+  bp.src.vel_time[i] = make_double4(v[b], v[b + 1], v[b + 2], 0.0);
+  double *aj = bp.src.acc_jrk + 6 * (size_t)i;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) aj[c] = 0.0;
+  if constexpr (Order == 6) {
+    double *sc = bp.src.snp_crk + 6 * (size_t)i;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) sc[c] = 0.0;
+  }
+  bp.src.id[i] = id[i];
+  bp.list[i] = i;
+  if (i == 0) bp.sched->clamped = 0;
+}
+
+// Start, after a force pass on every particle (row i = particle i): store a and j (the 6th-order
+// snap needs the sources' accelerations, so order 6 runs a second pass after this).
+__global__ __launch_bounds__(kThreads) void k_bs_seed(BlockStepParams bp) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= bp.n) return;
+  double *aj = bp.src.acc_jrk + 6 * (size_t)i;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    aj[c] = bp.acc[3 * (size_t)i + c];
+    aj[3 + c] = bp.jrk[3 * (size_t)i + c];
+  }
+}
+
+// Start: first step dt0 = eta_start |a|/|j| (order 6: the smaller of that and
+// eta_start sqrt(|a|/|s|)), rounded down to a power of two <= dt_max; crackle starts at zero.
+template <int Order>
+__global__ __launch_bounds__(kThreads) void k_bs_start(BlockStepParams bp) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= bp.n) return;
+  double a[3], j[3], s[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    a[c] = bp.acc[3 * (size_t)i + c];
+    j[c] = bp.jrk[3 * (size_t)i + c];
+    s[c] = Order == 6 ? bp.snp[3 * (size_t)i + c] : 0.0;
+  }
+  const double na = norm3(a), nj = norm3(j), ns = norm3(s);
+  double d0 = nj > 0.0 ? bp.eta_start * na / nj : bp.dt_max;
+  if (Order == 6 && ns > 0.0) d0 = fmin(d0, bp.eta_start * sqrt(na / ns));
+  double dn = bp.dt_max;
+  while (dn > d0 && dn > bp.dt_min) dn *= 0.5;
+  if (!(dn <= d0) && !(d0 >= bp.dt_max)) report_clamp(bp);  // clamped at dt_min (or NaN)
+  if constexpr (Order == 6) {
+    double *sc = bp.src.snp_crk + 6 * (size_t)i;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      sc[c] = s[c];
+      sc[3 + c] = 0.0;
+    }
+  }
+  bp.dt[i] = dn;
+  bp.tnext[i] = dn;
+}
+
+__global__ __launch_bounds__(kThreads) void k_iota(int32_t *p, int n) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i < n) p[i] = i;
+}
+
+static inline int grid_for(int n) { return (n + kThreads - 1) / kThreads; }
+
+hipError_t launch_iota(int32_t *p, int n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_iota, dim3(grid_for(n)), dim3(kThreads), 0, stream, p, n);
+  return hipGetLastError();
+}
+
+int bs_groups(int n) { return (n + kBsChunk - 1) / kBsChunk; }
+
+hipError_t launch_bs_schedule(const BlockStepParams &bp, hipStream_t stream) {
+  const int g = bs_groups(bp.n);
+  hipLaunchKernelGGL(k_bs_min, dim3(g), dim3(kThreads), 0, stream, bp);
+  hipLaunchKernelGGL(k_bs_count, dim3(g), dim3(kThreads), 0, stream, bp);
+  hipLaunchKernelGGL(k_bs_list, dim3(g), dim3(kThreads), 0, stream, bp);
+  return hipGetLastError();
+}
+
+hipError_t launch_bs_correct(int order, const BlockStepParams &bp, int ni, double t1, hipStream_t stream) {
+  if (ni <= 0) return hipSuccess;
+  if (order == 6)
+    hipLaunchKernelGGL(k_bs_correct<6>, dim3(grid_for(ni)), dim3(kThreads), 0, stream, bp, ni, t1);
+  else
+    hipLaunchKernelGGL(k_bs_correct<4>, dim3(grid_for(ni)), dim3(kThreads), 0, stream, bp, ni, t1);
+  return hipGetLastError();
+}
+
+hipError_t launch_bs_load(int order, const BlockStepParams &bp, const int64_t *id, const double *m, const double *x,
+                          const double *v, hipStream_t stream) {
+  if (order == 6)
+    hipLaunchKernelGGL(k_bs_load<6>, dim3(grid_for(bp.n)), dim3(kThreads), 0, stream, bp, id, m, x, v);
+  else
+    hipLaunchKernelGGL(k_bs_load<4>, dim3(grid_for(bp.n)), dim3(kThreads), 0, stream, bp, id, m, x, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_bs_seed(const BlockStepParams &bp, hipStream_t stream) {
+  hipLaunchKernelGGL(k_bs_seed, dim3(grid_for(bp.n)), dim3(kThreads), 0, stream, bp);
+  return hipGetLastError();
+}
+
+hipError_t launch_bs_start(int order, const BlockStepParams &bp, hipStream_t stream) {
+  if (order == 6)
+    hipLaunchKernelGGL(k_bs_start<6>, dim3(grid_for(bp.n)), dim3(kThreads), 0, stream, bp);
+  else
+    hipLaunchKernelGGL(k_bs_start<4>, dim3(grid_for(bp.n)), dim3(kThreads), 0, stream, bp);
+  return hipGetLastError();
+}
+
+}  // namespace nbx

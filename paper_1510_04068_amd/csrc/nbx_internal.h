@@ -67,7 +67,7 @@ struct ForceParams {
   double *part;
   uint64_t *part_key;
   int32_t *part_idx;
-  int *err;            // device-side error counters: [0] bad sink address, [1] bad source address
+  int *err;  // device-side error counters: [0] bad sink address, [1] bad source address, [2] list overflow
 };
 
 // Batched few-body systems: particles of system s are [offset[s], offset[s+1]); items[k] =
@@ -104,6 +104,28 @@ struct VjpParams {
   double *part;
 };
 
+// Block time-step integrator (device resident).  The particle state is the source arrays; the
+// force rows acc/jrk/snp are those of the active list (row k = particle list[k]).
+constexpr int kBsChunk = 4 * kThreads;  // particles per workgroup in the scheduling kernels
+struct BsSched {
+  double t_next;  // next block time
+  int count;      // active particles at t_next
+  int clamped;    // steps clamped at dt_min (or with a criterion that is not a number) since the start
+};
+struct BlockStepParams {
+  SourceArrays src;
+  int n;
+  double eta4, eta6, eta_start, dt_max, dt_min;
+  double *dt;       // [n] current step of each particle (power of two)
+  double *tnext;    // [n] t_i + dt_i
+  int32_t *list;    // [n] active particles of the current block step, address order
+  double *wg_min;   // [groups] partial minima of tnext
+  int32_t *wg_cnt;  // [groups] active particles per group
+  BsSched *sched;
+  const double *acc, *jrk, *snp;  // forces of the active list at the block time
+  int *err;                       // [3]: steps clamped at dt_min or criteria that were not numbers
+};
+
 struct LaunchShape {
   int lanes_log2;
   int sinks_per_lane;
@@ -130,6 +152,16 @@ hipError_t launch_vjp(int precision, const VjpParams &vp, hipStream_t stream);
 hipError_t launch_batch(int precision, const BatchParams &bp, int grid, hipStream_t stream);
 hipError_t launch_selfmap(const SourceArrays &src, int nj, int ni, const int64_t *ext_id, int32_t *self,
                           hipStream_t stream);
+
+// Block time-step kernels (defined in nbx_blockstep.hip).
+int bs_groups(int n);
+hipError_t launch_bs_schedule(const BlockStepParams &bp, hipStream_t stream);
+hipError_t launch_bs_correct(int order, const BlockStepParams &bp, int ni, double t1, hipStream_t stream);
+hipError_t launch_bs_load(int order, const BlockStepParams &bp, const int64_t *id, const double *m, const double *x,
+                          const double *v, hipStream_t stream);
+hipError_t launch_bs_seed(const BlockStepParams &bp, hipStream_t stream);
+hipError_t launch_bs_start(int order, const BlockStepParams &bp, hipStream_t stream);
+hipError_t launch_iota(int32_t *p, int n, hipStream_t stream);
 
 // Launch-shape rule (defined in nbx_kernels.hip).
 LaunchShape choose_shape(int ni, int nj_pad);

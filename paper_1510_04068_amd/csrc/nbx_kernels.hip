@@ -19,6 +19,10 @@
 //     the subsets with atomics inside the gravity kernel, Methods > Other differences; on
 //     gfx950 the device-scope fence that would need per workgroup is the expensive part).
 //
+// Orders: 2 (the GRAPE-5 / leapfrog mode of the Background section: acceleration and potential
+// from positions and masses), 4 (adds the jerk) and 6 (adds the snap, from predicted
+// accelerations).  All three share the staging, the loop, the reductions and the combine.
+//
 // Arithmetic per interaction (the pair terms of nbx.h):
 //   MIXED: dx = (xh_j - xh_i) + (xl_j - xl_i) in FP32 from double-single positions, FP32
 //          velocities/masses, v_rsq_f32 with one Newton step, FP32 chunk sums folded into
@@ -38,6 +42,7 @@
 #include <type_traits>
 
 #include "nbx_internal.h"
+#include "nbx_predict.h"
 
 #include "nbx.h"
 
@@ -45,68 +50,6 @@ namespace nbx {
 
 constexpr int kChunkAcc = 16;  // acceleration terms summed in plain FP32/FP64 before a TwoSum fold
 constexpr int kChunk = 64;     // same for jerk, pot and snap (a multiple of kChunkAcc)
-
-// ---------------------------------------------------------------------------------------------
-// Source state and the FP64 Taylor predictor
-// ---------------------------------------------------------------------------------------------
-struct Raw {
-  double x[3], m, v[3], tj, a[3], j[3], s[3], c[3];
-};
-
-template <int Order>
-__device__ __forceinline__ void load_raw(const SourceArrays &src, int addr, Raw &r) {
-  const double4 pm = src.pos_mass[addr];
-  const double4 vt = src.vel_time[addr];
-  r.x[0] = pm.x; r.x[1] = pm.y; r.x[2] = pm.z; r.m = pm.w;
-  r.v[0] = vt.x; r.v[1] = vt.y; r.v[2] = vt.z; r.tj = vt.w;
-  const double2 *aj = reinterpret_cast<const double2 *>(src.acc_jrk + 6 * (size_t)addr);
-  const double2 q0 = aj[0], q1 = aj[1], q2 = aj[2];
-  r.a[0] = q0.x; r.a[1] = q0.y; r.a[2] = q1.x;
-  r.j[0] = q1.y; r.j[1] = q2.x; r.j[2] = q2.y;
-  if constexpr (Order == 6) {
-    const double2 *sc = reinterpret_cast<const double2 *>(src.snp_crk + 6 * (size_t)addr);
-    const double2 s0 = sc[0], s1 = sc[1], s2 = sc[2];
-    r.s[0] = s0.x; r.s[1] = s0.y; r.s[2] = s1.x;
-    r.c[0] = s1.y; r.c[1] = s2.x; r.c[2] = s2.y;
-  }
-}
-
-// Taylor polynomial about t_j in Horner form with explicit FMAs and contraction disabled, so
-// that every call site computes the same bits for the same source.
-template <int Order>
-__device__ __forceinline__ void predict_raw(const Raw &r, double t, double xp[3], double vp[3],
-                                            double ap[3]) {
-#pragma clang fp contract(off)
-  const double dt = t - r.tj;
-  const double h2 = dt * 0.5;
-  const double h3 = dt * (1.0 / 3.0);
-  if constexpr (Order == 4) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      xp[k] = fma(dt, fma(h2, fma(h3, r.j[k], r.a[k]), r.v[k]), r.x[k]);
-      vp[k] = fma(dt, fma(h2, r.j[k], r.a[k]), r.v[k]);
-      ap[k] = fma(dt, r.j[k], r.a[k]);
-    }
-  } else {
-    const double h4 = dt * 0.25;
-    const double h5 = dt * 0.2;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      xp[k] = fma(dt, fma(h2, fma(h3, fma(h4, fma(h5, r.c[k], r.s[k]), r.j[k]), r.a[k]), r.v[k]), r.x[k]);
-      vp[k] = fma(dt, fma(h2, fma(h3, fma(h4, r.c[k], r.s[k]), r.j[k]), r.a[k]), r.v[k]);
-      ap[k] = fma(dt, fma(h2, fma(h3, r.c[k], r.s[k]), r.j[k]), r.a[k]);
-    }
-  }
-}
-
-template <int Order>
-__device__ __forceinline__ void predict_addr(const SourceArrays &src, int addr, double t,
-                                             double xp[3], double vp[3], double ap[3], double &m) {
-  Raw r;
-  load_raw<Order>(src, addr, r);
-  predict_raw<Order>(r, t, xp, vp, ap);
-  m = r.m;
-}
 
 // ---------------------------------------------------------------------------------------------
 // Compensated accumulation: K running values, each a plain chunk sum plus a (hi, lo) pair that
@@ -136,15 +79,22 @@ struct Comp {
   }
 };
 
-// value slots: 0..2 acc, 3..5 jerk, 6 pot, 7..9 snap
+// value slots: 0..2 acc, 3..5 jerk, 6 pot, 7..9 snap (order 2: 0..2 acc, 3 pot)
 template <int Order>
-constexpr int kValues = Order == 6 ? 10 : 7;
+constexpr int kValues = Order == 6 ? 10 : (Order == 4 ? 7 : 4);
+template <int Order>
+constexpr int kPotSlot = Order == 2 ? 3 : 6;
 
 // ---------------------------------------------------------------------------------------------
 // Precision traits: LDS tile layout, sink representation and the pair interaction
 // ---------------------------------------------------------------------------------------------
 template <int Order>
 struct MixedTile;
+template <>
+struct MixedTile<2> {  // 32 B per source
+  float4 t0[kTile];    // xh.x xh.y xh.z m
+  float4 t1[kTile];    // xl.x xl.y xl.z (unused)
+};
 template <>
 struct MixedTile<4> {  // 40 B per source
   float4 t0[kTile];    // xh.x xh.y xh.z m
@@ -214,10 +164,13 @@ struct Mixed {
 #pragma unroll
     for (int k = 0; k < 3; ++k) ds_split(xp[k], xh[k], xl[k]);
     tl.t0[e] = make_float4(xh[0], xh[1], xh[2], (float)m);
-    tl.t1[e] = make_float4(xl[0], xl[1], xl[2], (float)vp[0]);
-    if constexpr (Order == 4) {
+    if constexpr (Order == 2) {
+      tl.t1[e] = make_float4(xl[0], xl[1], xl[2], 0.0f);
+    } else if constexpr (Order == 4) {
+      tl.t1[e] = make_float4(xl[0], xl[1], xl[2], (float)vp[0]);
       tl.t2[e] = make_float2((float)vp[1], (float)vp[2]);
     } else {
+      tl.t1[e] = make_float4(xl[0], xl[1], xl[2], (float)vp[0]);
       tl.t2[e] = make_float4((float)vp[1], (float)vp[2], (float)ap[0], (float)ap[1]);
       tl.t3[e] = (float)ap[2];
     }
@@ -228,12 +181,15 @@ struct Mixed {
     const float4 a = tl.t0[e];
     const float4 b = tl.t1[e];
     j.xh[0] = a.x; j.xh[1] = a.y; j.xh[2] = a.z; j.m = a.w;
-    j.xl[0] = b.x; j.xl[1] = b.y; j.xl[2] = b.z; j.v[0] = b.w;
-    if constexpr (Order == 4) {
+    j.xl[0] = b.x; j.xl[1] = b.y; j.xl[2] = b.z;
+    if constexpr (Order == 2) {
+      // positions and mass are all the 2nd-order terms use
+    } else if constexpr (Order == 4) {
       const float2 c = tl.t2[e];
-      j.v[1] = c.x; j.v[2] = c.y;
+      j.v[0] = b.w; j.v[1] = c.x; j.v[2] = c.y;
     } else {
       const float4 c = tl.t2[e];
+      j.v[0] = b.w;
       j.v[1] = c.x; j.v[2] = c.y; j.a[0] = c.z; j.a[1] = c.w;
       j.a[2] = tl.t3[e];
     }
@@ -277,11 +233,7 @@ struct Mixed {
                                                   Comp<float, kValues<Order>> &A, Key &gmin) {
     float dx, dy, dz;
     const float r2 = diff_r2(j, s, dx, dy, dz);
-    const float dvx = j.v[0] - s.v[0];
-    const float dvy = j.v[1] - s.v[1];
-    const float dvz = j.v[2] - s.v[2];
     const float R2 = r2 + eps2;
-    const float rv = __builtin_fmaf(dz, dvz, __builtin_fmaf(dy, dvy, dx * dvx));
     // v_rsq_f32 estimate plus one Newton step: y (3 - R2 y^2) / 2
     float rinv = __builtin_amdgcn_rsqf(R2);
     rinv = rinv * __builtin_fmaf(-0.5f * R2, rinv * rinv, 1.5f);
@@ -289,40 +241,51 @@ struct Mixed {
     const float rinv2 = rinv * rinv;
     const float mr = j.m * rinv;
     const float mr3 = mr * rinv2;
-    const float al = rv * rinv2;
-    if constexpr (Order == 4) {
-      const float am3 = al * -3.0f;
-      const float wx = __builtin_fmaf(am3, dx, dvx);
-      const float wy = __builtin_fmaf(am3, dy, dvy);
-      const float wz = __builtin_fmaf(am3, dz, dvz);
+    if constexpr (Order == 2) {
       A.part[0] = __builtin_fmaf(mr3, dx, A.part[0]);
       A.part[1] = __builtin_fmaf(mr3, dy, A.part[1]);
       A.part[2] = __builtin_fmaf(mr3, dz, A.part[2]);
-      A.part[3] = __builtin_fmaf(mr3, wx, A.part[3]);
-      A.part[4] = __builtin_fmaf(mr3, wy, A.part[4]);
-      A.part[5] = __builtin_fmaf(mr3, wz, A.part[5]);
-      A.part[6] -= mr;
+      A.part[3] -= mr;
     } else {
-      const float dax = j.a[0] - s.a[0];
-      const float day = j.a[1] - s.a[1];
-      const float daz = j.a[2] - s.a[2];
-      const float vv = __builtin_fmaf(dvz, dvz, __builtin_fmaf(dvy, dvy, dvx * dvx));
-      const float ra = __builtin_fmaf(dz, daz, __builtin_fmaf(dy, day, dx * dax));
-      const float be = __builtin_fmaf(al, al, (vv + ra) * rinv2);
-      const float am3 = al * -3.0f;
-      const float am6 = al * -6.0f;
-      const float bm3 = be * -3.0f;
-      const float a0x = mr3 * dx, a0y = mr3 * dy, a0z = mr3 * dz;
-      const float a1x = __builtin_fmaf(am3, a0x, mr3 * dvx);
-      const float a1y = __builtin_fmaf(am3, a0y, mr3 * dvy);
-      const float a1z = __builtin_fmaf(am3, a0z, mr3 * dvz);
-      const float a2x = __builtin_fmaf(am6, a1x, __builtin_fmaf(bm3, a0x, mr3 * dax));
-      const float a2y = __builtin_fmaf(am6, a1y, __builtin_fmaf(bm3, a0y, mr3 * day));
-      const float a2z = __builtin_fmaf(am6, a1z, __builtin_fmaf(bm3, a0z, mr3 * daz));
-      A.part[0] += a0x; A.part[1] += a0y; A.part[2] += a0z;
-      A.part[3] += a1x; A.part[4] += a1y; A.part[5] += a1z;
-      A.part[6] -= mr;
-      A.part[7] += a2x; A.part[8] += a2y; A.part[9] += a2z;
+      const float dvx = j.v[0] - s.v[0];
+      const float dvy = j.v[1] - s.v[1];
+      const float dvz = j.v[2] - s.v[2];
+      const float rv = __builtin_fmaf(dz, dvz, __builtin_fmaf(dy, dvy, dx * dvx));
+      const float al = rv * rinv2;
+      if constexpr (Order == 4) {
+        const float am3 = al * -3.0f;
+        const float wx = __builtin_fmaf(am3, dx, dvx);
+        const float wy = __builtin_fmaf(am3, dy, dvy);
+        const float wz = __builtin_fmaf(am3, dz, dvz);
+        A.part[0] = __builtin_fmaf(mr3, dx, A.part[0]);
+        A.part[1] = __builtin_fmaf(mr3, dy, A.part[1]);
+        A.part[2] = __builtin_fmaf(mr3, dz, A.part[2]);
+        A.part[3] = __builtin_fmaf(mr3, wx, A.part[3]);
+        A.part[4] = __builtin_fmaf(mr3, wy, A.part[4]);
+        A.part[5] = __builtin_fmaf(mr3, wz, A.part[5]);
+        A.part[6] -= mr;
+      } else {
+        const float dax = j.a[0] - s.a[0];
+        const float day = j.a[1] - s.a[1];
+        const float daz = j.a[2] - s.a[2];
+        const float vv = __builtin_fmaf(dvz, dvz, __builtin_fmaf(dvy, dvy, dvx * dvx));
+        const float ra = __builtin_fmaf(dz, daz, __builtin_fmaf(dy, day, dx * dax));
+        const float be = __builtin_fmaf(al, al, (vv + ra) * rinv2);
+        const float am3 = al * -3.0f;
+        const float am6 = al * -6.0f;
+        const float bm3 = be * -3.0f;
+        const float a0x = mr3 * dx, a0y = mr3 * dy, a0z = mr3 * dz;
+        const float a1x = __builtin_fmaf(am3, a0x, mr3 * dvx);
+        const float a1y = __builtin_fmaf(am3, a0y, mr3 * dvy);
+        const float a1z = __builtin_fmaf(am3, a0z, mr3 * dvz);
+        const float a2x = __builtin_fmaf(am6, a1x, __builtin_fmaf(bm3, a0x, mr3 * dax));
+        const float a2y = __builtin_fmaf(am6, a1y, __builtin_fmaf(bm3, a0y, mr3 * day));
+        const float a2z = __builtin_fmaf(am6, a1z, __builtin_fmaf(bm3, a0z, mr3 * daz));
+        A.part[0] += a0x; A.part[1] += a0y; A.part[2] += a0z;
+        A.part[3] += a1x; A.part[4] += a1y; A.part[5] += a1z;
+        A.part[6] -= mr;
+        A.part[7] += a2x; A.part[8] += a2y; A.part[9] += a2z;
+      }
     }
     Key key = key_of(r2);
     if constexpr (Guard) key = jidx != self ? key : ~Key(0);
@@ -333,6 +296,11 @@ struct Mixed {
 
 template <int Order>
 struct F64Tile;
+template <>
+struct F64Tile<2> {   // 32 B per source
+  double2 t0[kTile];  // x y
+  double2 t1[kTile];  // z m
+};
 template <>
 struct F64Tile<4> {  // 56 B per source
   double2 t0[kTile];  // x y
@@ -404,10 +372,12 @@ struct F64 {
                                                const double ap[3], double m) {
     tl.t0[e] = make_double2(xp[0], xp[1]);
     tl.t1[e] = make_double2(xp[2], m);
-    tl.t2[e] = make_double2(vp[0], vp[1]);
-    if constexpr (Order == 4) {
+    if constexpr (Order == 2) {
+    } else if constexpr (Order == 4) {
+      tl.t2[e] = make_double2(vp[0], vp[1]);
       tl.t3[e] = vp[2];
     } else {
+      tl.t2[e] = make_double2(vp[0], vp[1]);
       tl.t3[e] = make_double2(vp[2], ap[0]);
       tl.t4[e] = make_double2(ap[1], ap[2]);
     }
@@ -417,12 +387,14 @@ struct F64 {
     J j;
     const double2 a = tl.t0[e];
     const double2 b = tl.t1[e];
-    const double2 c = tl.t2[e];
     j.x[0] = a.x; j.x[1] = a.y; j.x[2] = b.x; j.m = b.y;
-    j.v[0] = c.x; j.v[1] = c.y;
-    if constexpr (Order == 4) {
-      j.v[2] = tl.t3[e];
+    if constexpr (Order == 2) {
+    } else if constexpr (Order == 4) {
+      const double2 c = tl.t2[e];
+      j.v[0] = c.x; j.v[1] = c.y; j.v[2] = tl.t3[e];
     } else {
+      const double2 c = tl.t2[e];
+      j.v[0] = c.x; j.v[1] = c.y;
       const double2 d = tl.t3[e];
       const double2 f = tl.t4[e];
       j.v[2] = d.x; j.a[0] = d.y; j.a[1] = f.x; j.a[2] = f.y;
@@ -462,50 +434,57 @@ struct F64 {
                                                   Comp<double, kValues<Order>> &A, Key &gmin) {
     double dx, dy, dz;
     const double r2 = diff_r2(j, s, dx, dy, dz);
-    const double dvx = j.v[0] - s.v[0];
-    const double dvy = j.v[1] - s.v[1];
-    const double dvz = j.v[2] - s.v[2];
     const double R2 = r2 + eps2;
-    const double rv = fma(dz, dvz, fma(dy, dvy, dx * dvx));
     double rinv = rsqrt64(R2);
     if constexpr (Guard) rinv = jidx != self ? rinv : 0.0;
     const double rinv2 = rinv * rinv;
     const double mr = j.m * rinv;
     const double mr3 = mr * rinv2;
-    const double al = rv * rinv2;
-    if constexpr (Order == 4) {
-      const double am3 = al * -3.0;
-      const double wx = fma(am3, dx, dvx);
-      const double wy = fma(am3, dy, dvy);
-      const double wz = fma(am3, dz, dvz);
+    if constexpr (Order == 2) {
       A.part[0] = fma(mr3, dx, A.part[0]);
       A.part[1] = fma(mr3, dy, A.part[1]);
       A.part[2] = fma(mr3, dz, A.part[2]);
-      A.part[3] = fma(mr3, wx, A.part[3]);
-      A.part[4] = fma(mr3, wy, A.part[4]);
-      A.part[5] = fma(mr3, wz, A.part[5]);
-      A.part[6] -= mr;
+      A.part[3] -= mr;
     } else {
-      const double dax = j.a[0] - s.a[0];
-      const double day = j.a[1] - s.a[1];
-      const double daz = j.a[2] - s.a[2];
-      const double vv = fma(dvz, dvz, fma(dvy, dvy, dvx * dvx));
-      const double ra = fma(dz, daz, fma(dy, day, dx * dax));
-      const double be = fma(al, al, (vv + ra) * rinv2);
-      const double am3 = al * -3.0;
-      const double am6 = al * -6.0;
-      const double bm3 = be * -3.0;
-      const double a0x = mr3 * dx, a0y = mr3 * dy, a0z = mr3 * dz;
-      const double a1x = fma(am3, a0x, mr3 * dvx);
-      const double a1y = fma(am3, a0y, mr3 * dvy);
-      const double a1z = fma(am3, a0z, mr3 * dvz);
-      const double a2x = fma(am6, a1x, fma(bm3, a0x, mr3 * dax));
-      const double a2y = fma(am6, a1y, fma(bm3, a0y, mr3 * day));
-      const double a2z = fma(am6, a1z, fma(bm3, a0z, mr3 * daz));
-      A.part[0] += a0x; A.part[1] += a0y; A.part[2] += a0z;
-      A.part[3] += a1x; A.part[4] += a1y; A.part[5] += a1z;
-      A.part[6] -= mr;
-      A.part[7] += a2x; A.part[8] += a2y; A.part[9] += a2z;
+      const double dvx = j.v[0] - s.v[0];
+      const double dvy = j.v[1] - s.v[1];
+      const double dvz = j.v[2] - s.v[2];
+      const double rv = fma(dz, dvz, fma(dy, dvy, dx * dvx));
+      const double al = rv * rinv2;
+      if constexpr (Order == 4) {
+        const double am3 = al * -3.0;
+        const double wx = fma(am3, dx, dvx);
+        const double wy = fma(am3, dy, dvy);
+        const double wz = fma(am3, dz, dvz);
+        A.part[0] = fma(mr3, dx, A.part[0]);
+        A.part[1] = fma(mr3, dy, A.part[1]);
+        A.part[2] = fma(mr3, dz, A.part[2]);
+        A.part[3] = fma(mr3, wx, A.part[3]);
+        A.part[4] = fma(mr3, wy, A.part[4]);
+        A.part[5] = fma(mr3, wz, A.part[5]);
+        A.part[6] -= mr;
+      } else {
+        const double dax = j.a[0] - s.a[0];
+        const double day = j.a[1] - s.a[1];
+        const double daz = j.a[2] - s.a[2];
+        const double vv = fma(dvz, dvz, fma(dvy, dvy, dvx * dvx));
+        const double ra = fma(dz, daz, fma(dy, day, dx * dax));
+        const double be = fma(al, al, (vv + ra) * rinv2);
+        const double am3 = al * -3.0;
+        const double am6 = al * -6.0;
+        const double bm3 = be * -3.0;
+        const double a0x = mr3 * dx, a0y = mr3 * dy, a0z = mr3 * dz;
+        const double a1x = fma(am3, a0x, mr3 * dvx);
+        const double a1y = fma(am3, a0y, mr3 * dvy);
+        const double a1z = fma(am3, a0z, mr3 * dvz);
+        const double a2x = fma(am6, a1x, fma(bm3, a0x, mr3 * dax));
+        const double a2y = fma(am6, a1y, fma(bm3, a0y, mr3 * day));
+        const double a2z = fma(am6, a1z, fma(bm3, a0z, mr3 * daz));
+        A.part[0] += a0x; A.part[1] += a0y; A.part[2] += a0z;
+        A.part[3] += a1x; A.part[4] += a1y; A.part[5] += a1z;
+        A.part[6] -= mr;
+        A.part[7] += a2x; A.part[8] += a2y; A.part[9] += a2z;
+      }
     }
     Key key = key_of(r2);
     if constexpr (Guard) key = jidx != self ? key : ~Key(0);
@@ -610,10 +589,10 @@ __device__ void finalize_sink(const ForceParams &fp, int q, const double *v, int
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     fp.acc[3 * (size_t)q + k] = v[k];
-    fp.jrk[3 * (size_t)q + k] = v[3 + k];
+    if constexpr (Order != 2) fp.jrk[3 * (size_t)q + k] = v[3 + k];
     if constexpr (Order == 6) fp.snp[3 * (size_t)q + k] = v[7 + k];
   }
-  fp.pot[q] = v[6];
+  fp.pot[q] = v[kPotSlot<Order>];
   if (idx >= 0 && idx < fp.nj) {
     double xi[3], vi[3], ai[3], mi, xj[3], vj[3], aj[3], mj;
     if (ext) {
@@ -774,7 +753,7 @@ __global__ __launch_bounds__(kThreads) void k_force(const ForceParams fp) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         xp[k] = fp.ext_x[3 * (size_t)qq + k];
-        vp[k] = fp.ext_v[3 * (size_t)qq + k];
+        vp[k] = (Order != 2) ? fp.ext_v[3 * (size_t)qq + k] : 0.0;
         ap[k] = (Order == 6) ? fp.ext_a[3 * (size_t)qq + k] : 0.0;
       }
       self[p] = live ? fp.ext_self[qq] : -1;
@@ -1193,10 +1172,22 @@ __global__ __launch_bounds__(256) void k_jupdate(SourceArrays src, int nj_max, i
   }
   const size_t b = 3 * (size_t)k;
   src.pos_mass[ad] = make_double4(x[b], x[b + 1], x[b + 2], m[k]);
-  src.vel_time[ad] = make_double4(v[b], v[b + 1], v[b + 2], t[k]);
   double *aj = src.acc_jrk + 6 * (size_t)ad;
-  aj[0] = a[b]; aj[1] = a[b + 1]; aj[2] = a[b + 2];
-  aj[3] = jk[b]; aj[4] = jk[b + 1]; aj[5] = jk[b + 2];
+  if constexpr (Order == 2) {  // velocity and acceleration optional (NULL: zero), no jerk
+    if (v)
+      src.vel_time[ad] = make_double4(v[b], v[b + 1], v[b + 2], t[k]);
+    else
+      src.vel_time[ad] = make_double4(0.0, 0.0, 0.0, t[k]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      aj[c] = a ? a[b + c] : 0.0;
+      aj[3 + c] = 0.0;
+    }
+  } else {
+    src.vel_time[ad] = make_double4(v[b], v[b + 1], v[b + 2], t[k]);
+    aj[0] = a[b]; aj[1] = a[b + 1]; aj[2] = a[b + 2];
+    aj[3] = jk[b]; aj[4] = jk[b + 1]; aj[5] = jk[b + 2];
+  }
   if constexpr (Order == 6) {
     double *sc = src.snp_crk + 6 * (size_t)ad;
     sc[0] = sn[b]; sc[1] = sn[b + 1]; sc[2] = sn[b + 2];
@@ -1279,7 +1270,7 @@ __global__ __launch_bounds__(256) void k_fill_i32(int32_t *p, int n, int value) 
 // ---------------------------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------------------------
-int values_per_sink(int order) { return order == 6 ? 10 : 7; }
+int values_per_sink(int order) { return order == 6 ? 10 : (order == 4 ? 7 : 4); }
 
 // Launch shape.  A workgroup holds Q = (256 / L) * P sinks and one of S source ranges.
 //   * About 8 workgroups per CU (2048) fill the 256 CUs.
@@ -1370,6 +1361,9 @@ static hipError_t launch_force_op(const ForceParams &fp, const LaunchShape &ls, 
 
 hipError_t launch_force(int order, int precision, const ForceParams &fp, const LaunchShape &ls,
                         hipStream_t stream) {
+  if (order == 2)
+    return precision == NBX_MIXED ? launch_force_op<2, NBX_MIXED>(fp, ls, stream)
+                                  : launch_force_op<2, NBX_FP64>(fp, ls, stream);
   if (order == 4)
     return precision == NBX_MIXED ? launch_force_op<4, NBX_MIXED>(fp, ls, stream)
                                   : launch_force_op<4, NBX_FP64>(fp, ls, stream);
@@ -1384,7 +1378,10 @@ hipError_t launch_jupdate(int order, const SourceArrays &src, int nj_max, int n,
                           const double *v, const double *a, const double *jerk, const double *snap,
                           const double *crackle, int *err, hipStream_t stream) {
   if (n <= 0) return hipSuccess;
-  if (order == 4)
+  if (order == 2)
+    hipLaunchKernelGGL(k_jupdate<2>, dim3(grid_for(n)), dim3(256), 0, stream, src, nj_max, n, addr, id, m, t,
+                       x, v, a, jerk, snap, crackle, err);
+  else if (order == 4)
     hipLaunchKernelGGL(k_jupdate<4>, dim3(grid_for(n)), dim3(256), 0, stream, src, nj_max, n, addr, id, m, t,
                        x, v, a, jerk, snap, crackle, err);
   else
@@ -1395,7 +1392,7 @@ hipError_t launch_jupdate(int order, const SourceArrays &src, int nj_max, int n,
 
 hipError_t launch_pad(int order, const SourceArrays &src, int from, int to, hipStream_t stream) {
   if (to <= from) return hipSuccess;
-  if (order == 4)
+  if (order != 6)
     hipLaunchKernelGGL(k_pad<4>, dim3(grid_for(to - from)), dim3(256), 0, stream, src, from, to);
   else
     hipLaunchKernelGGL(k_pad<6>, dim3(grid_for(to - from)), dim3(256), 0, stream, src, from, to);
@@ -1405,7 +1402,10 @@ hipError_t launch_pad(int order, const SourceArrays &src, int from, int to, hipS
 hipError_t launch_predict_out(int order, const SourceArrays &src, int nj, double t, int n, const int32_t *addr,
                               double *xp, double *vp, double *ap, int *err, hipStream_t stream) {
   if (n <= 0) return hipSuccess;
-  if (order == 4)
+  if (order == 2)
+    hipLaunchKernelGGL(k_predict_out<2>, dim3(grid_for(n)), dim3(256), 0, stream, src, nj, t, n, addr, xp, vp,
+                       ap, err);
+  else if (order == 4)
     hipLaunchKernelGGL(k_predict_out<4>, dim3(grid_for(n)), dim3(256), 0, stream, src, nj, t, n, addr, xp, vp,
                        ap, err);
   else
@@ -1418,7 +1418,7 @@ hipError_t launch_gather_j(int order, const SourceArrays &src, int n, const int3
                            double *m, double *t, double *x, double *v, double *a, double *jerk,
                            double *snap, double *crackle, hipStream_t stream) {
   if (n <= 0) return hipSuccess;
-  if (order == 4)
+  if (order != 6)
     hipLaunchKernelGGL(k_gather_j<4>, dim3(grid_for(n)), dim3(256), 0, stream, src, n, addr, id, m, t, x, v, a,
                        jerk, snap, crackle);
   else

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -53,7 +54,7 @@ struct nbx_ctx {
   int64_t *d_nbr_ids = nullptr;
   // split-combine scratch
   DevBuf part, part_key, part_idx;
-  int *d_err = nullptr;  // [0] bad sink address, [1] bad source address, [2] nbr overflow
+  int *d_err = nullptr;  // [0] bad sink address, [1] bad source address, [2] nbr overflow, [3] dt clamped
   // set_j staging (host path), grown on demand
   DevBuf up;
   int up_cap = 0;
@@ -63,6 +64,16 @@ struct nbx_ctx {
   DevBuf batch_items;
   int batch_n_items = 0;
   int batch_lg[8] = {-1, -1, -1, -1, -1, -1, -1, -1};  // lanes_log2 per size class (-1: default)
+  // block time-step integrator: particle state in the source arrays, addresses 0..n-1
+  struct {
+    bool ready = false;
+    int n = 0;
+    nbx_bs_params p{};
+    double t = 0.0;
+    int64_t blocks = 0, steps = 0;
+    DevBuf dt, tnext, list, acc, jrk, snp, pot, nnid, nnr2, wg_min, wg_cnt, sched;
+    BsSched *h_sched = nullptr;  // pinned host copy of the schedule
+  } bs;
   // state of the last force call (host path)
   int last_ni = -1;
   bool last_nbr = false;
@@ -262,13 +273,17 @@ int batch_enqueue(nbx_ctx *c, hipStream_t stream, const double *d_m, const doubl
 int collect_errors(nbx_ctx *c) {
   int h[4] = {0, 0, 0, 0};
   HIP_TRY(c, hipMemcpy(h, c->d_err, sizeof h, hipMemcpyDeviceToHost));
-  if (h[0] || h[1] || h[2]) {
+  if (h[0] || h[1] || h[2] || h[3]) {
     HIP_TRY(c, launch_fill_i32(c->d_err, 4, 0, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
   }
   if (h[0]) return fail(c, NBX_ERR_ARG, "%d sink address(es) outside [0, nj) were skipped", h[0]);
   if (h[1]) return fail(c, NBX_ERR_ARG, "%d source address(es) out of range were skipped", h[1]);
   if (h[2]) return NBX_WARN_NBR_OVERFLOW;
+  if (h[3]) {
+    fail(c, NBX_OK, "%d block time-step(s) clamped at dt_min or with a criterion that is not a number", h[3]);
+    return NBX_WARN_DT_MIN;
+  }
   return NBX_OK;
 }
 
@@ -295,7 +310,8 @@ int nbx_open(nbx_ctx **out, const nbx_config *cfg) {
   if (!out) return fail(nullptr, NBX_ERR_ARG, "out is NULL");
   *out = nullptr;
   if (!cfg) return fail(nullptr, NBX_ERR_ARG, "cfg is NULL");
-  if (cfg->order != 4 && cfg->order != 6) return fail(nullptr, NBX_ERR_ARG, "order must be 4 or 6");
+  if (cfg->order != 2 && cfg->order != 4 && cfg->order != 6)
+    return fail(nullptr, NBX_ERR_ARG, "order must be 2, 4 or 6");
   if (!valid_prec(cfg->precision)) return fail(nullptr, NBX_ERR_ARG, "precision must be NBX_FP64 or NBX_MIXED");
   if (cfg->nj_max < 1 || cfg->ni_max < 1 || cfg->nbr_max < 0)
     return fail(nullptr, NBX_ERR_ARG, "nj_max and ni_max must be >= 1, nbr_max >= 0");
@@ -327,7 +343,7 @@ int nbx_open(nbx_ctx **out, const nbx_config *cfg) {
   rc = rc ? rc : alloc_n(c, &c->src.id, nj);
   rc = rc ? rc : alloc_n(c, &c->d_iaddr, ni);
   rc = rc ? rc : alloc_n(c, &c->d_acc, 3 * ni);
-  rc = rc ? rc : alloc_n(c, &c->d_jrk, 3 * ni);
+  if (cfg->order != 2) rc = rc ? rc : alloc_n(c, &c->d_jrk, 3 * ni);
   if (cfg->order == 6) rc = rc ? rc : alloc_n(c, &c->d_snp, 3 * ni);
   rc = rc ? rc : alloc_n(c, &c->d_pot, ni);
   rc = rc ? rc : alloc_n(c, &c->d_nnid, ni);
@@ -352,6 +368,7 @@ int nbx_close(nbx_ctx *c) {
   (void)hipSetDevice(c->cfg.device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (void *p : c->owned) (void)hipFree(p);
+  if (c->bs.h_sched) (void)hipHostFree(c->bs.h_sched);
   if (c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
   return NBX_OK;
@@ -382,7 +399,9 @@ int nbx_set_j(nbx_ctx *c, int n, const int32_t *addr, const int64_t *id, const d
   if (n < 0) return fail(c, NBX_ERR_ARG, "n < 0");
   if (n == 0) return NBX_OK;
   if (n > c->cfg.nj_max) return fail(c, NBX_ERR_CAPACITY, "n=%d > nj_max=%d", n, c->cfg.nj_max);
-  if (!addr || !id || !m || !t || !x || !v || !a || !jerk) return fail(c, NBX_ERR_ARG, "NULL input array");
+  const bool two = c->cfg.order == 2;
+  if (!addr || !id || !m || !t || !x || (!two && (!v || !a || !jerk)))
+    return fail(c, NBX_ERR_ARG, "NULL input array");
   const bool six = c->cfg.order == 6;
   if (six && (!snap || !crackle)) return fail(c, NBX_ERR_ARG, "order 6 needs snap and crackle");
   int hi = -1;
@@ -391,8 +410,8 @@ int nbx_set_j(nbx_ctx *c, int n, const int32_t *addr, const int64_t *id, const d
       return fail(c, NBX_ERR_ARG, "addr[%d]=%d outside [0, %d)", k, addr[k], c->cfg.nj_max);
     hi = std::max(hi, addr[k]);
   }
-  // staging layout: addr | id | m | t | x v a jerk [snap crackle]
-  const size_t nv = six ? 6 : 4;
+  // staging layout: addr | id | m | t | x v a [jerk [snap crackle]]
+  const size_t nv = six ? 6 : (two ? 3 : 4);
   const size_t bytes = (size_t)n * (4 + 8 + 8 + 8 + nv * 24) + 256;
   if (int rc = grow(c, c->up, bytes)) return rc;
   char *base = static_cast<char *>(c->up.p);
@@ -407,6 +426,7 @@ int nbx_set_j(nbx_ctx *c, int n, const int32_t *addr, const int64_t *id, const d
   double *d_vec[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   const double *h_vec[6] = {x, v, a, jerk, snap, crackle};
   for (size_t k = 0; k < nv; ++k) {
+    if (!h_vec[k]) continue;  // optional for order 2 (v, a): the copy kernel takes NULL as zero
     d_vec[k] = reinterpret_cast<double *>(base + off);
     off += (size_t)n * 24;
   }
@@ -416,11 +436,12 @@ int nbx_set_j(nbx_ctx *c, int n, const int32_t *addr, const int64_t *id, const d
   HIP_TRY(c, hipMemcpyAsync(d_m, m, (size_t)n * 8, hipMemcpyHostToDevice, s));
   HIP_TRY(c, hipMemcpyAsync(d_t, t, (size_t)n * 8, hipMemcpyHostToDevice, s));
   for (size_t k = 0; k < nv; ++k)
-    HIP_TRY(c, hipMemcpyAsync(d_vec[k], h_vec[k], (size_t)n * 24, hipMemcpyHostToDevice, s));
+    if (d_vec[k]) HIP_TRY(c, hipMemcpyAsync(d_vec[k], h_vec[k], (size_t)n * 24, hipMemcpyHostToDevice, s));
   HIP_TRY(c, launch_jupdate(c->cfg.order, c->src, c->cfg.nj_max, n, d_addr, d_id, d_m, d_t, d_vec[0], d_vec[1],
                             d_vec[2], d_vec[3], d_vec[4], d_vec[5], c->d_err, s));
   HIP_TRY(c, hipStreamSynchronize(s));
   c->nj = std::max(c->nj, hi + 1);
+  c->bs.ready = false;  // the block time-step state lives in the same arrays
   return NBX_OK;
 }
 
@@ -457,14 +478,14 @@ int nbx_force_ext(nbx_ctx *c, int ni, const int64_t *id, const double *x, const 
   if (int rc = check_ctx(c)) return rc;
   if (ni < 0) return fail(c, NBX_ERR_ARG, "ni < 0");
   if (ni > c->cfg.ni_max) return fail(c, NBX_ERR_CAPACITY, "ni=%d > ni_max=%d", ni, c->cfg.ni_max);
-  if (ni > 0 && (!id || !x || !v)) return fail(c, NBX_ERR_ARG, "NULL sink array");
+  if (ni > 0 && (!id || !x || (!v && c->cfg.order != 2))) return fail(c, NBX_ERR_ARG, "NULL sink array");
   if (ni > 0 && c->cfg.order == 6 && !a) return fail(c, NBX_ERR_ARG, "order 6 needs the sink accelerations");
   if (h2 && c->cfg.nbr_max == 0) return fail(c, NBX_ERR_ARG, "neighbour lists need nbr_max > 0");
   if (!c->d_ext_id) {  // explicit-sink buffers, allocated on first use
     const size_t n = (size_t)c->cfg.ni_max;
     int rc = alloc_n(c, &c->d_ext_id, n);
     rc = rc ? rc : alloc_n(c, &c->d_ext_x, 3 * n);
-    rc = rc ? rc : alloc_n(c, &c->d_ext_v, 3 * n);
+    if (c->cfg.order != 2) rc = rc ? rc : alloc_n(c, &c->d_ext_v, 3 * n);
     if (c->cfg.order == 6) rc = rc ? rc : alloc_n(c, &c->d_ext_a, 3 * n);
     rc = rc ? rc : alloc_n(c, &c->d_ext_self, n);
     if (rc) return rc;
@@ -474,7 +495,7 @@ int nbx_force_ext(nbx_ctx *c, int ni, const int64_t *id, const double *x, const 
   if (ni > 0) {
     HIP_TRY(c, hipMemcpyAsync(c->d_ext_id, id, n * 8, hipMemcpyHostToDevice, s));
     HIP_TRY(c, hipMemcpyAsync(c->d_ext_x, x, n * 24, hipMemcpyHostToDevice, s));
-    HIP_TRY(c, hipMemcpyAsync(c->d_ext_v, v, n * 24, hipMemcpyHostToDevice, s));
+    if (c->cfg.order != 2) HIP_TRY(c, hipMemcpyAsync(c->d_ext_v, v, n * 24, hipMemcpyHostToDevice, s));
     if (c->cfg.order == 6) HIP_TRY(c, hipMemcpyAsync(c->d_ext_a, a, n * 24, hipMemcpyHostToDevice, s));
     if (h2) HIP_TRY(c, hipMemcpyAsync(c->d_h2, h2, n * 8, hipMemcpyHostToDevice, s));
     if (c->predicted) HIP_TRY(c, launch_selfmap(c->src, c->nj, ni, c->d_ext_id, c->d_ext_self, s));
@@ -498,7 +519,7 @@ int nbx_get_force(nbx_ctx *c, double *acc, double *jerk, double *snap, double *p
   const size_t n = (size_t)c->last_ni;
   if (n == 0) return rc;
   if (acc) HIP_TRY(c, hipMemcpy(acc, c->d_acc, n * 24, hipMemcpyDeviceToHost));
-  if (jerk) HIP_TRY(c, hipMemcpy(jerk, c->d_jrk, n * 24, hipMemcpyDeviceToHost));
+  if (jerk && c->cfg.order != 2) HIP_TRY(c, hipMemcpy(jerk, c->d_jrk, n * 24, hipMemcpyDeviceToHost));
   if (snap && c->cfg.order == 6) HIP_TRY(c, hipMemcpy(snap, c->d_snp, n * 24, hipMemcpyDeviceToHost));
   if (pot) HIP_TRY(c, hipMemcpy(pot, c->d_pot, n * 8, hipMemcpyDeviceToHost));
   if (nn_id) HIP_TRY(c, hipMemcpy(nn_id, c->d_nnid, n * 8, hipMemcpyDeviceToHost));
@@ -596,11 +617,12 @@ int nbx_set_j_dev(nbx_ctx *c, void *stream, int n, const int32_t *d_addr, const 
   if (n < 0) return fail(c, NBX_ERR_ARG, "n < 0");
   if (n == 0) return NBX_OK;
   if (n > c->cfg.nj_max) return fail(c, NBX_ERR_CAPACITY, "n=%d > nj_max=%d", n, c->cfg.nj_max);
-  if (!d_addr || !d_id || !d_m || !d_t || !d_x || !d_v || !d_a || !d_jerk)
+  if (!d_addr || !d_id || !d_m || !d_t || !d_x || (c->cfg.order != 2 && (!d_v || !d_a || !d_jerk)))
     return fail(c, NBX_ERR_ARG, "NULL input array");
   if (c->cfg.order == 6 && (!d_snap || !d_crackle)) return fail(c, NBX_ERR_ARG, "order 6 needs snap and crackle");
   HIP_TRY(c, launch_jupdate(c->cfg.order, c->src, c->cfg.nj_max, n, d_addr, d_id, d_m, d_t, d_x, d_v, d_a, d_jerk,
                             d_snap, d_crackle, c->d_err, static_cast<hipStream_t>(stream)));
+  c->bs.ready = false;
   return NBX_OK;
 }
 
@@ -611,7 +633,7 @@ int nbx_force_dev(nbx_ctx *c, void *stream, int ni, const int32_t *d_i_addr, dou
   if (ni < 0) return fail(c, NBX_ERR_ARG, "ni < 0");
   if (ni > c->cfg.ni_max) return fail(c, NBX_ERR_CAPACITY, "ni=%d > ni_max=%d", ni, c->cfg.ni_max);
   if (ni == 0) return NBX_OK;
-  if (!d_i_addr || !d_acc || !d_jerk || !d_pot || !d_nn_id || !d_nn_r2)
+  if (!d_i_addr || !d_acc || (!d_jerk && c->cfg.order != 2) || !d_pot || !d_nn_id || !d_nn_r2)
     return fail(c, NBX_ERR_ARG, "NULL device array");
   if (c->cfg.order == 6 && !d_snap) return fail(c, NBX_ERR_ARG, "order 6 needs d_snap");
   if (d_h2 && (c->cfg.nbr_max == 0 || !d_nbr_count || !d_nbr_ids))
@@ -740,6 +762,236 @@ int nbx_batch_tune(nbx_ctx *c, void *stream, const double *d_m, const double *d_
   int rc = batch_upload(c, 0xffu, nullptr, s);
   if (rc) return rc;
   return batch_enqueue(c, s, d_m, d_x, d_v, eps2, d_acc, d_jerk, d_pot);
+}
+
+// ---- block time-step integrator ------------------------------------------------------------------
+
+namespace {
+
+bool pow2(double x) {
+  if (!(x > 0.0) || !(x <= 1.0)) return false;
+  int e = 0;
+  return std::frexp(x, &e) == 0.5;
+}
+
+BlockStepParams bs_params(nbx_ctx *c) {
+  BlockStepParams bp{};
+  bp.src = c->src;
+  bp.n = c->bs.n;
+  bp.eta4 = c->bs.p.eta4;
+  bp.eta6 = c->bs.p.eta6;
+  bp.eta_start = c->bs.p.eta_start;
+  bp.dt_max = c->bs.p.dt_max;
+  bp.dt_min = c->bs.p.dt_min;
+  bp.dt = static_cast<double *>(c->bs.dt.p);
+  bp.tnext = static_cast<double *>(c->bs.tnext.p);
+  bp.list = static_cast<int32_t *>(c->bs.list.p);
+  bp.wg_min = static_cast<double *>(c->bs.wg_min.p);
+  bp.wg_cnt = static_cast<int32_t *>(c->bs.wg_cnt.p);
+  bp.sched = static_cast<BsSched *>(c->bs.sched.p);
+  bp.acc = static_cast<const double *>(c->bs.acc.p);
+  bp.jrk = static_cast<const double *>(c->bs.jrk.p);
+  bp.snp = static_cast<const double *>(c->bs.snp.p);
+  bp.err = c->d_err;
+  return bp;
+}
+
+// Forces on the first ni particles of the list at time t into the integrator's force rows.
+int bs_force(nbx_ctx *c, int ni, double t) {
+  c->t_pred = t;
+  c->predicted = true;
+  return enqueue_force(c, c->stream, ni, static_cast<const int32_t *>(c->bs.list.p), nullptr, nullptr, nullptr,
+                       nullptr, nullptr, c->bs.p.eps2, nullptr, static_cast<double *>(c->bs.acc.p),
+                       static_cast<double *>(c->bs.jrk.p), static_cast<double *>(c->bs.snp.p),
+                       static_cast<double *>(c->bs.pot.p), static_cast<int64_t *>(c->bs.nnid.p),
+                       static_cast<double *>(c->bs.nnr2.p), nullptr, nullptr);
+}
+
+// Schedule the next block step; returns (t_next, count, clamped so far) through the pinned copy.
+int bs_schedule(nbx_ctx *c, double *t_next, int *count, int *clamped) {
+  const BlockStepParams bp = bs_params(c);
+  HIP_TRY(c, launch_bs_schedule(bp, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->bs.h_sched, bp.sched, sizeof(BsSched), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  *t_next = c->bs.h_sched->t_next;
+  *count = c->bs.h_sched->count;
+  *clamped = c->bs.h_sched->clamped;
+  return NBX_OK;
+}
+
+int bs_check(nbx_ctx *c) {
+  if (int rc = check_ctx(c)) return rc;
+  if (!c->bs.ready) return fail(c, NBX_ERR_STATE, "no block time-step state (nbx_bs_init, and no nbx_set_j since)");
+  return NBX_OK;
+}
+
+}  // namespace
+
+int nbx_bs_init(nbx_ctx *c, int n, const int64_t *id, const double *m, const double *x, const double *v,
+                const nbx_bs_params *p) {
+  if (int rc = check_ctx(c)) return rc;
+  if (c->cfg.order != 4 && c->cfg.order != 6) return fail(c, NBX_ERR_ARG, "the integrator needs order 4 or 6");
+  if (n < 1 || !id || !m || !x || !v || !p) return fail(c, NBX_ERR_ARG, "need n >= 1 and every array");
+  if (n > c->cfg.nj_max || n > c->cfg.ni_max)
+    return fail(c, NBX_ERR_CAPACITY, "n=%d exceeds nj_max=%d or ni_max=%d", n, c->cfg.nj_max, c->cfg.ni_max);
+  if (!(p->eps2 >= 0.0) || !(p->eta4 > 0.0) || !(p->eta_start > 0.0) || (c->cfg.order == 6 && !(p->eta6 > 0.0)))
+    return fail(c, NBX_ERR_ARG, "need eps2 >= 0 and positive eta4, eta_start (and eta6 for order 6)");
+  if (!pow2(p->dt_max) || !pow2(p->dt_min) || p->dt_min > p->dt_max)
+    return fail(c, NBX_ERR_ARG, "dt_max and dt_min must be powers of two with dt_min <= dt_max <= 1");
+  c->bs.ready = false;
+  const size_t N = (size_t)n, G = (size_t)bs_groups(n);
+  int rc = NBX_OK;
+  rc = rc ? rc : grow(c, c->bs.dt, N * 8);
+  rc = rc ? rc : grow(c, c->bs.tnext, N * 8);
+  rc = rc ? rc : grow(c, c->bs.list, N * 4);
+  rc = rc ? rc : grow(c, c->bs.acc, N * 24);
+  rc = rc ? rc : grow(c, c->bs.jrk, N * 24);
+  if (c->cfg.order == 6) rc = rc ? rc : grow(c, c->bs.snp, N * 24);
+  rc = rc ? rc : grow(c, c->bs.pot, N * 8);
+  rc = rc ? rc : grow(c, c->bs.nnid, N * 8);
+  rc = rc ? rc : grow(c, c->bs.nnr2, N * 8);
+  rc = rc ? rc : grow(c, c->bs.wg_min, G * 8);
+  rc = rc ? rc : grow(c, c->bs.wg_cnt, G * 4);
+  rc = rc ? rc : grow(c, c->bs.sched, sizeof(BsSched));
+  rc = rc ? rc : grow(c, c->up, N * (8 + 8 + 24 + 24) + 256);
+  if (rc) return rc;
+  if (!c->bs.h_sched) {
+    void *h = nullptr;
+    HIP_TRY(c, hipHostMalloc(&h, sizeof(BsSched)));
+    c->bs.h_sched = static_cast<BsSched *>(h);
+  }
+  c->bs.n = n;
+  c->bs.p = *p;
+  c->bs.t = 0.0;
+  c->bs.blocks = c->bs.steps = 0;
+  c->nj = n;
+  char *base = static_cast<char *>(c->up.p);
+  int64_t *d_id = reinterpret_cast<int64_t *>(base);
+  double *d_m = reinterpret_cast<double *>(base + N * 8);
+  double *d_x = d_m + N;
+  double *d_v = d_x + 3 * N;
+  hipStream_t s = c->stream;
+  HIP_TRY(c, hipMemcpyAsync(d_id, id, N * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(c, hipMemcpyAsync(d_m, m, N * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(c, hipMemcpyAsync(d_x, x, N * 24, hipMemcpyHostToDevice, s));
+  HIP_TRY(c, hipMemcpyAsync(d_v, v, N * 24, hipMemcpyHostToDevice, s));
+  const BlockStepParams bp = bs_params(c);
+  HIP_TRY(c, launch_bs_load(c->cfg.order, bp, d_id, d_m, d_x, d_v, s));
+  // acc and jerk at t = 0; order 6 needs a second pass for the snap, which uses the accelerations
+  if ((rc = bs_force(c, n, 0.0))) return rc;
+  if (c->cfg.order == 6) {
+    HIP_TRY(c, launch_bs_seed(bp, s));
+    if ((rc = bs_force(c, n, 0.0))) return rc;
+  }
+  HIP_TRY(c, launch_bs_seed(bp, s));
+  HIP_TRY(c, launch_bs_start(c->cfg.order, bp, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  c->bs.ready = true;
+  return collect_errors(c);
+}
+
+int nbx_bs_step(nbx_ctx *c, double t_end, int *n_active) {
+  if (int rc = bs_check(c)) return rc;
+  if (n_active) *n_active = 0;
+  double tn = 0.0;
+  int ni = 0, clamped = 0;
+  if (int rc = bs_schedule(c, &tn, &ni, &clamped)) return rc;
+  if (clamped > 0) {  // a step hit dt_min: stop rather than crawl on at the smallest step
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const int rc = collect_errors(c);
+    return rc == NBX_OK ? NBX_WARN_DT_MIN : rc;
+  }
+  if (!(tn <= t_end) || ni < 1) return NBX_OK;
+  if (int rc = bs_force(c, ni, tn)) return rc;
+  HIP_TRY(c, launch_bs_correct(c->cfg.order, bs_params(c), ni, tn, c->stream));
+  c->bs.t = tn;
+  c->bs.blocks += 1;
+  c->bs.steps += ni;
+  if (n_active) *n_active = ni;
+  return NBX_OK;
+}
+
+int nbx_bs_run(nbx_ctx *c, double t_end, nbx_bs_stats *stats) {
+  if (int rc = bs_check(c)) return rc;
+  int rc = NBX_OK;
+  for (;;) {
+    int ni = 0;
+    rc = nbx_bs_step(c, t_end, &ni);
+    if (rc != NBX_OK || ni == 0) break;
+  }
+  if (rc < 0) return rc;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const int rc2 = collect_errors(c);
+  if (rc2 < 0) return rc2;
+  if (rc == NBX_OK) rc = rc2;
+  if (stats) {
+    stats->t = c->bs.t;
+    stats->block_steps = c->bs.blocks;
+    stats->particle_steps = c->bs.steps;
+  }
+  return rc;
+}
+
+int nbx_bs_get_state(nbx_ctx *c, double *t, double *x, double *v, double *dt, double *t_i, nbx_bs_stats *stats) {
+  if (int rc = bs_check(c)) return rc;
+  const size_t N = (size_t)c->bs.n;
+  if (t) *t = c->bs.t;
+  if (stats) {
+    stats->t = c->bs.t;
+    stats->block_steps = c->bs.blocks;
+    stats->particle_steps = c->bs.steps;
+  }
+  if (x || v) {
+    if (int rc = grow(c, c->up, N * 48 + 256)) return rc;
+    double *d_x = static_cast<double *>(c->up.p);
+    double *d_v = d_x + 3 * N;
+    int32_t *list = static_cast<int32_t *>(c->bs.list.p);
+    HIP_TRY(c, launch_iota(list, c->bs.n, c->stream));
+    HIP_TRY(c, launch_predict_out(c->cfg.order, c->src, c->nj, c->bs.t, c->bs.n, list, d_x, d_v, nullptr, c->d_err,
+                                  c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (x) HIP_TRY(c, hipMemcpy(x, d_x, N * 24, hipMemcpyDeviceToHost));
+    if (v) HIP_TRY(c, hipMemcpy(v, d_v, N * 24, hipMemcpyDeviceToHost));
+  }
+  if (dt) HIP_TRY(c, hipMemcpy(dt, c->bs.dt.p, N * 8, hipMemcpyDeviceToHost));
+  if (t_i) {
+    std::vector<double> tn(N), d(N);
+    HIP_TRY(c, hipMemcpy(tn.data(), c->bs.tnext.p, N * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(d.data(), c->bs.dt.p, N * 8, hipMemcpyDeviceToHost));
+    for (size_t k = 0; k < N; ++k) t_i[k] = tn[k] - d[k];
+  }
+  return collect_errors(c);
+}
+
+int nbx_bs_energy(nbx_ctx *c, double *ekin, double *epot) {
+  if (int rc = bs_check(c)) return rc;
+  const int n = c->bs.n;
+  const size_t N = (size_t)n;
+  int32_t *list = static_cast<int32_t *>(c->bs.list.p);
+  HIP_TRY(c, launch_iota(list, n, c->stream));
+  if (int rc = bs_force(c, n, c->bs.t)) return rc;
+  if (int rc = grow(c, c->up, N * 56 + 256)) return rc;
+  double *d_x = static_cast<double *>(c->up.p);
+  double *d_v = d_x + 3 * N;
+  double *d_m = d_v + 3 * N;
+  HIP_TRY(c, launch_predict_out(c->cfg.order, c->src, c->nj, c->bs.t, n, list, d_x, d_v, nullptr, c->d_err,
+                                c->stream));
+  HIP_TRY(c, launch_gather_j(c->cfg.order, c->src, n, list, nullptr, d_m, nullptr, nullptr, nullptr, nullptr, nullptr,
+                             nullptr, nullptr, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  std::vector<double> v(3 * N), m(N), pot(N);
+  HIP_TRY(c, hipMemcpy(v.data(), d_v, N * 24, hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(m.data(), d_m, N * 8, hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(pot.data(), c->bs.pot.p, N * 8, hipMemcpyDeviceToHost));
+  long double k = 0.0L, w = 0.0L;
+  for (size_t i = 0; i < N; ++i) {
+    k += 0.5L * m[i] * ((long double)v[3 * i] * v[3 * i] + (long double)v[3 * i + 1] * v[3 * i + 1] +
+                        (long double)v[3 * i + 2] * v[3 * i + 2]);
+    w += 0.5L * m[i] * pot[i];
+  }
+  if (ekin) *ekin = (double)k;
+  if (epot) *epot = (double)w;
+  return collect_errors(c);
 }
 
 int nbx_sync(nbx_ctx *c, void *stream) {

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libnbx.so")
 
 NBX_OK = 0
 NBX_WARN_NBR_OVERFLOW = 1
+NBX_WARN_DT_MIN = 2
 NBX_ERR_ARG = -1
 NBX_ERR_CAPACITY = -2
 NBX_ERR_STATE = -3
@@ -44,6 +45,7 @@ EXPORTS = (
     "nbx_set_nj", "nbx_set_j", "nbx_predict", "nbx_force", "nbx_force_ext", "nbx_get_force", "nbx_get_nbr",
     "nbx_get_predicted", "nbx_get_j", "nbx_set_j_dev", "nbx_force_dev", "nbx_sync", "nbx_launch_shape",
     "nbx_batch_setup", "nbx_batch_tune", "nbx_batch_force_dev", "nbx_force_vjp_dev",
+    "nbx_bs_init", "nbx_bs_step", "nbx_bs_run", "nbx_bs_get_state", "nbx_bs_energy",
 )
 NBX_BATCH_NMAX = 128
 
@@ -56,6 +58,25 @@ class nbx_config(ctypes.Structure):
         ("nj_max", ctypes.c_int),
         ("ni_max", ctypes.c_int),
         ("nbr_max", ctypes.c_int),
+    ]
+
+
+class nbx_bs_params(ctypes.Structure):
+    _fields_ = [
+        ("eps2", ctypes.c_double),
+        ("eta4", ctypes.c_double),
+        ("eta6", ctypes.c_double),
+        ("eta_start", ctypes.c_double),
+        ("dt_max", ctypes.c_double),
+        ("dt_min", ctypes.c_double),
+    ]
+
+
+class nbx_bs_stats(ctypes.Structure):
+    _fields_ = [
+        ("t", ctypes.c_double),
+        ("block_steps", ctypes.c_int64),
+        ("particle_steps", ctypes.c_int64),
     ]
 
 
@@ -110,6 +131,11 @@ def load(path: str = LIB_PATH):
         "nbx_batch_tune": ([_P, _P, _P, _P, _P, _D, _P, _P, _P, _P], _I),
         "nbx_batch_force_dev": ([_P, _P, _P, _P, _P, _D, _P, _P, _P], _I),
         "nbx_force_vjp_dev": ([_P, _P, _I, _P, _P, _P, _D, _P, _P, _P, _P, _P, _P], _I),
+        "nbx_bs_init": ([_P, _I, _P, _P, _P, _P, ctypes.POINTER(nbx_bs_params)], _I),
+        "nbx_bs_step": ([_P, _D, _P], _I),
+        "nbx_bs_run": ([_P, _D, ctypes.POINTER(nbx_bs_stats)], _I),
+        "nbx_bs_get_state": ([_P, _P, _P, _P, _P, _P, ctypes.POINTER(nbx_bs_stats)], _I),
+        "nbx_bs_energy": ([_P, _P, _P], _I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -203,7 +229,7 @@ def nbx_set_j(ctx, addr, id, m, t, x, v, a, jerk, snap=None, crackle=None):
     n = addr.shape[0]
     id = np.ascontiguousarray(id, dtype=np.int64)
     m, t = _f64(m, n, 0), _f64(t, n, 0)
-    x, v, a, jerk = _f64(x, n), _f64(v, n), _f64(a, n), _f64(jerk, n)
+    x, v, a, jerk = _f64(x, n), _f64(v, n), _f64(a, n), _f64(jerk, n)  # v, a, jerk: None allowed for order 2
     snap, crackle = _f64(snap, n), _f64(crackle, n)
     if id.shape != (n,):
         raise ValueError("id must have shape (n,)")
@@ -227,7 +253,7 @@ def nbx_force_ext(ctx, id, x, v, a, eps2, h2=None):
     x = _f64(x)
     n = x.shape[0]
     id = np.ascontiguousarray(id, dtype=np.int64)
-    v = _f64(v, n)
+    v = None if v is None else _f64(v, n)
     a = None if a is None else _f64(a, n)
     h2 = None if h2 is None else _f64(np.broadcast_to(np.asarray(h2, dtype=np.float64), (n,)), n, 0)
     return _check(ctx, load().nbx_force_ext(ctx, n, _ptr(id), _ptr(x), _ptr(v), _ptr(a), float(eps2), _ptr(h2)))
@@ -237,7 +263,7 @@ def nbx_get_force(ctx, ni, order=4):
     """Results of the last force call on ni sinks, as a dict of numpy arrays (plus 'status')."""
     out = {
         "acc": np.empty((ni, 3)),
-        "jerk": np.empty((ni, 3)),
+        "jerk": np.empty((ni, 3)) if order != 2 else None,
         "snap": np.empty((ni, 3)) if order == 6 else None,
         "pot": np.empty(ni),
         "nn_id": np.empty(ni, dtype=np.int64),
@@ -331,6 +357,54 @@ def nbx_force_vjp_dev(ctx, stream, n, d_m, d_x, d_v, eps2, d_g_acc, d_g_jerk, d_
     return _check(ctx, rc)
 
 
+def nbx_bs_init(ctx, id, m, x, v, eps2, eta4=0.01, eta6=0.1, eta_start=0.01, dt_max=0.125, dt_min=2.0**-30):
+    x = _f64(x)
+    n = x.shape[0]
+    id = np.ascontiguousarray(id, dtype=np.int64)
+    m, v = _f64(m, n, 0), _f64(v, n)
+    if id.shape != (n,):
+        raise ValueError("id must have shape (n,)")
+    p = nbx_bs_params(float(eps2), float(eta4), float(eta6), float(eta_start), float(dt_max), float(dt_min))
+    return _check(ctx, load().nbx_bs_init(ctx, n, _ptr(id), _ptr(m), _ptr(x), _ptr(v), ctypes.byref(p)))
+
+
+def nbx_bs_step(ctx, t_end):
+    """One block step if due by t_end; returns (N_active, status): N_active 0 when no step was
+    taken, status NBX_WARN_DT_MIN once a step has collapsed to dt_min."""
+    ni = ctypes.c_int(0)
+    rc = _check(ctx, load().nbx_bs_step(ctx, float(t_end), ctypes.byref(ni)))
+    return ni.value, rc
+
+
+def _stats(st):
+    return {"t": st.t, "block_steps": st.block_steps, "particle_steps": st.particle_steps}
+
+
+def nbx_bs_run(ctx, t_end):
+    st = nbx_bs_stats()
+    rc = _check(ctx, load().nbx_bs_run(ctx, float(t_end), ctypes.byref(st)))
+    out = _stats(st)
+    out["status"] = rc
+    return out
+
+
+def nbx_bs_get_state(ctx, n):
+    t = ctypes.c_double(0.0)
+    x, v, dt, ti = np.empty((n, 3)), np.empty((n, 3)), np.empty(n), np.empty(n)
+    st = nbx_bs_stats()
+    rc = _check(ctx, load().nbx_bs_get_state(ctx, ctypes.byref(t), _ptr(x), _ptr(v), _ptr(dt), _ptr(ti),
+                                             ctypes.byref(st)))
+    out = {"t": t.value, "x": x, "v": v, "dt": dt, "t_i": ti, "status": rc}
+    out.update({k: val for k, val in _stats(st).items() if k != "t"})
+    return out
+
+
+def nbx_bs_energy(ctx):
+    ek, ep = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(ctx, load().nbx_bs_energy(ctx, ctypes.byref(ek), ctypes.byref(ep)))
+    return ek.value, ep.value
+
+
 class Context:
     """Owns one nbx context; thin convenience wrapper over the entry points above."""
 
@@ -366,7 +440,8 @@ class Context:
     def set_sources(self, src, addr=None):
         """Load a nbody_ics.SourceSet-like object (fields ids, m, t, x, v, a, jerk[, snap, crackle])."""
         addr = np.arange(src.n, dtype=np.int32) if addr is None else addr
-        return nbx_set_j(self.ctx, addr, src.ids, src.m, src.t, src.x, src.v, src.a, src.jerk,
+        return nbx_set_j(self.ctx, addr, src.ids, src.m, src.t, src.x, src.v, src.a,
+                         src.jerk if self.order != 2 else None,
                          src.snap if self.order == 6 else None, src.crackle if self.order == 6 else None)
 
     def predict(self, t):
