@@ -274,7 +274,8 @@ typedef struct nbx_bs_stats {
 
 /* Start an integration at t = 0 from host arrays id[n], m[n], x, v [n][3] (1 <= n <= nj_max and
  * <= ni_max; order 4 or 6).  Computes the starting forces (order 6: two passes, the snap needs the
- * accelerations) and first steps.  Synchronous.  NBX_WARN_DT_MIN if a first step was clamped. */
+ * accelerations) and first steps.  Synchronous.  NBX_WARN_DT_MIN if a first step was clamped at
+ * dt_min (the integration can still proceed; only clamps in later steps stop it). */
 int nbx_bs_init(nbx_ctx *ctx, int n, const int64_t *id, const double *m, const double *x,
                 const double *v, const nbx_bs_params *p);
 

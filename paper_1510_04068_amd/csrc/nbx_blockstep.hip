@@ -322,7 +322,9 @@ __global__ __launch_bounds__(kThreads) void k_bs_start(BlockStepParams bp) {
   if (Order == 6 && ns > 0.0) d0 = fmin(d0, bp.eta_start * sqrt(na / ns));
   double dn = bp.dt_max;
   while (dn > d0 && dn > bp.dt_min) dn *= 0.5;
-  if (!(dn <= d0) && !(d0 >= bp.dt_max)) report_clamp(bp);  // clamped at dt_min (or NaN)
+  // clamped at dt_min (or NaN): reported by nbx_bs_init, but a crude first estimate does not stop
+  // the integration the way a collapsing criterion does
+  if (!(dn <= d0) && !(d0 >= bp.dt_max)) atomicAdd(&bp.err[3], 1);
   if constexpr (Order == 6) {
     double *sc = bp.src.snp_crk + 6 * (size_t)i;
 #pragma unroll

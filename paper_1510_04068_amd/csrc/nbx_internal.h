@@ -22,7 +22,7 @@ namespace nbx {
 constexpr int kThreads = 256;  // workgroup size: 4 wave64s
 constexpr int kTile = 256;     // sources per LDS tile (one per thread when staging)
 // Position of padding sources: far enough that every term is negligible, near enough that R^2
-// (~3e36) stays finite in FP32, so R^-1 and its Newton step stay finite too.
+// (~3e36) stays finite in FP32, so R^-1 (and any Newton step on it) stays finite too.
 constexpr double kPadPos = 1e18;
 
 struct SourceArrays {

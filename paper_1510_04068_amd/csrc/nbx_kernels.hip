@@ -25,9 +25,10 @@
 //
 // Arithmetic per interaction (the pair terms of nbx.h):
 //   MIXED: dx = (xh_j - xh_i) + (xl_j - xl_i) in FP32 from double-single positions, FP32
-//          velocities/masses, v_rsq_f32 with one Newton step, FP32 chunk sums folded into
-//          (hi, lo) TwoSum pairs (acceleration every 16 terms, the rest every 64).  FP32
-//          add/mul/fma issue at twice the FP64 rate on gfx950.
+//          velocities/masses, R^-1 straight from v_rsq_f32 (a Newton step measured no better
+//          in the median, 2x better only in the worst sink, for 10% of the issue slots), FP32
+//          chunk sums folded into (hi, lo) TwoSum pairs (acceleration every 16 terms, the rest
+//          every 64).  FP32 add/mul/fma issue at twice the FP64 rate on gfx950.
 //   FP64:  all IEEE double; R^-1 from v_rsq_f64 plus one third-order Newton correction; FP64
 //          chunk sums folded with TwoSum.
 // Self-interaction (by-address sinks): a sink and its own source copy are predicted by the same
@@ -234,9 +235,7 @@ struct Mixed {
     float dx, dy, dz;
     const float r2 = diff_r2(j, s, dx, dy, dz);
     const float R2 = r2 + eps2;
-    // v_rsq_f32 estimate plus one Newton step: y (3 - R2 y^2) / 2
-    float rinv = __builtin_amdgcn_rsqf(R2);
-    rinv = rinv * __builtin_fmaf(-0.5f * R2, rinv * rinv, 1.5f);
+    float rinv = __builtin_amdgcn_rsqf(R2);  // v_rsq_f32
     if constexpr (Guard) rinv = jidx != self ? rinv : 0.0f;
     const float rinv2 = rinv * rinv;
     const float mr = j.m * rinv;

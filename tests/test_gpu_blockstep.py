@@ -77,6 +77,25 @@ def test_blockstep_mixed_close_to_oracle():
     assert abs((e1 - e0) / e0) < 1e-6
 
 
+def test_blockstep_mixed_order6_completes():
+    """6th order with mixed-precision forces, started with first steps 0.03 |a|/|j| so that no
+    particle starts far below its dynamical time: the run completes, the steps stay well above
+    dt_min and the final state is close to the FP64 oracle's integration with the same parameters."""
+    n, eps2, t_end = 700, 1e-4, 1.0 / 16
+    say("blockstep order=6 mixed eta_start=0.03 n=%d" % n)
+    src = nbody_ics.make_sources(n, seed=63, time_offsets=False)
+    ref = obs.BlockStep(6, src.m, src.x, src.v, eps2, eta_start=0.03).run(t_end)
+    xr, vr = ref.state()
+    log, st, e0, e1 = _gpu_run(6, nbx.NBX_MIXED, src.m, src.x, src.v, eps2, t_end, eta_start=0.03)
+    ex = np.abs(st["x"] - xr).max() / np.abs(xr).max()
+    ev = np.abs(st["v"] - vr).max() / np.abs(vr).max()
+    say("  blocks gpu %d oracle %d; min dt 2^%d; max rel dx %.2e dv %.2e; dE/E %.2e" % (
+        len(log), len(ref.log), int(np.log2(st["dt"].min())), ex, ev, (e1 - e0) / e0))
+    assert st["t"] == t_end and st["dt"].min() >= 2.0**-16
+    assert ex <= 1e-4 and ev <= 1e-3
+    assert abs((e1 - e0) / e0) < 1e-6
+
+
 def test_blockstep_collapse_stops_with_warning():
     """The 6th-order criterion differentiates the interpolated acceleration up to five times, which
     multiplies force rounding noise by ~dt^-5; with FP32-arithmetic forces (~1e-7 relative) on this
