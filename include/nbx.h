@@ -37,8 +37,8 @@
  * none: id -1, r2 +inf.  In NBX_FP64 the choice is made on the exact FP64
  * |r|^2 (ties to the lower source address); in NBX_MIXED it is made on the
  * FP32 value of |r|^2, so sources whose |r|^2 agree to FP32 rounding may be
- * returned in either order.  A distinct source at exactly r = 0 is never
- * reported (its key equals the sink's own).  Neighbour list (Background; Results, perturber
+ * returned in either order.  A distinct source at the sink's position is a
+ * valid nearest neighbour (r2 = 0).  Neighbour list (Background; Results, perturber
  * lists): every other source with |r|^2 < h2_i, at most nbr_max per sink;
  * the count is exact, and when it exceeds nbr_max the stored ids are an
  * unspecified subset and the call returns NBX_WARN_NBR_OVERFLOW.

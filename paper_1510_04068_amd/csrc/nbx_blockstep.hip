@@ -1,8 +1,8 @@
 // nbx_blockstep.hip -- device-resident block time-step Hermite integrator (4th and 6th order).
 //
 // The paper's library leaves the integrator to the host code (Results > Block time-step
-// simulations: the host does the corrections, the time-step computation and the particle copies,
-// the GPU the prediction and the gravity).  Here those host steps run as kernels on the same
+// simulations: between force calls the host corrects the particles, picks their next steps and
+// copies them back; the GPU predicts and computes gravity).  Here those host steps run as kernels on the same
 // stream, so a block step moves no particle data over PCIe: the particle state lives in the
 // library's FP64 source arrays, and only (t_next, N_active) comes back to the host each block step
 // (the force launch shape depends on N_active).

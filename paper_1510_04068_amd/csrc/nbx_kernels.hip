@@ -32,11 +32,11 @@
 //   FP64:  all IEEE double; R^-1 from v_rsq_f64 plus one third-order Newton correction; FP64
 //          chunk sums folded with TwoSum.
 // Self-interaction (by-address sinks): a sink and its own source copy are predicted by the same
-// code, so r = 0 exactly; the nearest-neighbour key (bit pattern of |r|^2 minus one) wraps to the
-// maximum.  A wave checks per tile whether the tile holds the own source of one of its sinks
+// code, so r = 0 exactly.  A wave checks per tile whether the tile holds the own source of one of its sinks
 // (1-2 tiles of nj/256 when the active sinks are consecutive) and only then runs the loop variant
-// that forces R^-1 = 0 for j == self: the self pair never enters a sum, so no -m_i/eps term has
-// to be removed later, and eps2 = 0 needs no special case.
+// that forces R^-1 = 0 and the nearest-neighbour key to its maximum for j == self: the self pair
+// never enters a sum, so no -m_i/eps term has to be removed later, and eps2 = 0 needs no special
+// case.  A distinct source at the sink's position (r = 0) is an ordinary candidate.
 
 #include <cstdio>
 #include <cstdlib>
@@ -219,9 +219,9 @@ struct Mixed {
     return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
   }
 
-  // Nearest-neighbour key: bit pattern of |r|^2 minus one (r2 == 0, the sink itself, wraps to the
-  // maximum and never wins); unsigned order equals the order of |r|^2.
-  __device__ static __forceinline__ Key key_of(float r2) { return __float_as_uint(r2) - 1u; }
+  // Nearest-neighbour key: the bit pattern of |r|^2 >= 0, whose unsigned order is the order of
+  // |r|^2 (the self pair is given the maximum key by the guarded loop).
+  __device__ static __forceinline__ Key key_of(float r2) { return __float_as_uint(r2); }
 
   __device__ static __forceinline__ Key nn_key(const J &j, const Sink &s) {
     float dx, dy, dz;
@@ -420,7 +420,7 @@ struct F64 {
     return fma(dz, dz, fma(dy, dy, dx * dx));
   }
 
-  __device__ static __forceinline__ Key key_of(double r2) { return (Key)__double_as_longlong(r2) - 1ull; }
+  __device__ static __forceinline__ Key key_of(double r2) { return (Key)__double_as_longlong(r2); }
 
   __device__ static __forceinline__ Key nn_key(const J &j, const Sink &s) {
     double dx, dy, dz;
@@ -617,7 +617,7 @@ __device__ void finalize_sink(const ForceParams &fp, int q, const double *v, int
 
 // One LDS tile against the lane's P sinks.  Guard = true is used only for tiles that hold the
 // own source of some sink of the wave: there R^-1 is forced to 0 for j == self, so the self pair
-// adds exact zeros everywhere (its |r|^2 = 0 key already wraps to the maximum).
+// adds exact zeros everywhere and its nearest-neighbour key is the maximum.
 // The lane's sources are taken in groups of kChunkAcc; inside a group only the minimum
 // nearest-neighbour key is kept, and after the group the (key, first source of the group) pair
 // replaces the running best if the key is smaller.  The exact source is found afterwards by

@@ -719,9 +719,16 @@ int nbx_batch_tune(nbx_ctx *c, void *stream, const double *d_m, const double *d_
   hipStream_t s = static_cast<hipStream_t>(stream);
   unsigned present = 0;
   for (int32_t n : c->batch_sizes) present |= 1u << batch_class(n);
-  hipEvent_t e0, e1;
-  HIP_TRY(c, hipEventCreate(&e0));
-  HIP_TRY(c, hipEventCreate(&e1));
+  struct Events {  // destroyed on every return path
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Events() {
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+    }
+  } ev;
+  HIP_TRY(c, hipEventCreate(&ev.e0));
+  HIP_TRY(c, hipEventCreate(&ev.e1));
+  hipEvent_t e0 = ev.e0, e1 = ev.e1;
   int best[8];
   for (int cl = 0; cl < 8; ++cl) {
     best[cl] = -1;
@@ -733,11 +740,7 @@ int nbx_batch_tune(nbx_ctx *c, void *stream, const double *d_m, const double *d_
       int rc = batch_upload(c, 1u << cl, lgs, s);
       for (int rep = 0; rc == NBX_OK && rep < 2; ++rep)
         rc = batch_enqueue(c, s, d_m, d_x, d_v, eps2, d_acc, d_jerk, d_pot);
-      if (rc) {
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        return rc;
-      }
+      if (rc) return rc;
       constexpr int reps = 10;
       HIP_TRY(c, hipEventRecord(e0, s));
       for (int rep = 0; rc == NBX_OK && rep < reps; ++rep)
@@ -753,8 +756,6 @@ int nbx_batch_tune(nbx_ctx *c, void *stream, const double *d_m, const double *d_
       }
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   for (int cl = 0; cl < 8; ++cl) {
     c->batch_lg[cl] = best[cl];
     if (lanes_per_class) lanes_per_class[cl] = best[cl] < 0 ? 0 : 1 << best[cl];

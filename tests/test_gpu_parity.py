@@ -176,6 +176,31 @@ def test_edge_cases(prec):
         _compare(out, ref, prec, 4, sel, src.ids, "eps2=0")
 
 
+@pytest.mark.parametrize("prec", [nbx.NBX_FP64, nbx.NBX_MIXED])
+def test_coincident_distinct_sources(prec):
+    """Two distinct sources at the same position: each is the other's nearest neighbour with
+    r2 = 0 (only the sink's own source is excluded), as in the oracle; eps2 > 0 keeps the forces
+    finite.  Placed in different tiles and in the same tile."""
+    n, eps2 = 700, 1e-4
+    say("coincident sources prec=%s" % PREC_NAME[prec])
+    src = nbody_ics.make_sources(n, seed=35)
+    for k in (18, 600):  # 18: same tile as 17; 600: another tile.  Same orbit, so same predicted position
+        src.x[k], src.v[k], src.a[k], src.jerk[k], src.t[k] = src.x[17], src.v[17], src.a[17], src.jerk[17], src.t[17]
+    sel = np.array([17, 18, 600, 5], dtype=np.int32)
+    ref = oracle_all(src, 4, eps2, 0.0, addr=sel)
+    with nbx.Context(order=4, precision=prec, nj_max=n, ni_max=n) as ctx:
+        ctx.set_sources(src)
+        ctx.predict(0.0)
+        out = run_gpu(ctx, sel, eps2)
+    for k in range(3):
+        assert out["nn_r2"][k] == 0.0 and ref["nn_r2"][k] == 0.0
+        assert out["nn_id"][k] in (17, 18, 600) and out["nn_id"][k] != sel[k]
+    if prec == nbx.NBX_FP64:
+        np.testing.assert_array_equal(out["nn_id"], ref["nn_id"])
+    e = rel_err_vec(out["acc"], ref["acc"])
+    assert e.max() <= (1e-13 if prec == nbx.NBX_FP64 else 1e-6), e
+
+
 def test_error_paths():
     say("error paths")
     n = 300
