@@ -23,7 +23,7 @@ using namespace nbx;
 
 namespace {
 
-constexpr int kVersion = 10000;  // 1.0.0
+constexpr int kVersion = 10100;  // 1.1.0: order 2, block time-step integrator
 
 std::string g_open_error;  // message of the last failed nbx_open
 

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_version():
-    assert nbx.nbx_version() == 10000
+    assert nbx.nbx_version() == 10100
 
 
 def test_argument_errors_without_device():
@@ -53,6 +53,11 @@ def test_argument_errors_without_device():
     assert lib.nbx_get_force(None, None, None, None, None, None, None) == nbx.NBX_ERR_ARG
     assert lib.nbx_set_precision(None, 0) == nbx.NBX_ERR_ARG
     assert lib.nbx_launch_shape(None, 1, None, None, None, None) == nbx.NBX_ERR_ARG
+    assert lib.nbx_bs_init(None, 1, None, None, None, None, None) == nbx.NBX_ERR_ARG
+    assert lib.nbx_bs_step(None, 1.0, None) == nbx.NBX_ERR_ARG
+    assert lib.nbx_bs_run(None, 1.0, None) == nbx.NBX_ERR_ARG
+    assert lib.nbx_bs_get_state(None, None, None, None, None, None, None) == nbx.NBX_ERR_ARG
+    assert lib.nbx_bs_energy(None, None, None) == nbx.NBX_ERR_ARG
 
 
 def test_no_device_is_an_error_code():
