@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     ap.add_argument("--sweep-reps", type=int, default=5)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the launch-shape tuner (nbx_tune) and its tuned N_i sweep")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run one plain device-to-device copy kernel of MIB MiB first (HBM counter calibration)")
     ap.add_argument("--batch", action="store_true",
@@ -460,13 +462,16 @@ def main():
     print("bench: fp64 N_i=N", file=sys.stderr, flush=True)
     sec64, kern64 = timed(torch, nbx, ctx, w, N, stream, max(3, args.steps // 4), 1)
 
-    sweep = []
+    def shape_str(ni):
+        sh = ctx.launch_shape(ni)
+        return "L%d P%d S%d wg%d" % (sh["lanes_per_sink"], sh["sinks_per_lane"], sh["splits"], sh["workgroups"])
+
+    sweep, tune_s = [], None
     if not args.no_sweep:
+        # static launch-shape rule
         for e in range(18):
             ni = 1 << e
-            sh = ctx.launch_shape(ni)
-            row = {"ni": ni, "shape": "L%d P%d S%d wg%d" % (sh["lanes_per_sink"], sh["sinks_per_lane"], sh["splits"],
-                                                          sh["workgroups"])}
+            row = {"ni": ni, "shape": shape_str(ni)}
             for prec, name in ((nbx.NBX_FP64, "fp64"), (nbx.NBX_MIXED, "mixed")):
                 ctx.set_precision(prec)
                 s, k = timed(torch, nbx, ctx, w, ni, stream, args.sweep_reps, 1)
@@ -476,6 +481,26 @@ def main():
             row["speedup"] = round(row["fp64_kernel_ms"] / row["mixed_kernel_ms"], 3)
             sweep.append(row)
             print("bench: sweep %s" % json.dumps(row), file=sys.stderr, flush=True)
+        # the library's tuner picks a shape per N_i class from timed candidates
+        if not args.no_tune:
+            t0 = time.perf_counter()
+            nbx.nbx_predict(ctx.ctx, 0.0)
+            for prec in (nbx.NBX_MIXED, nbx.NBX_FP64):
+                ctx.set_precision(prec)
+                ctx.tune(N)
+            tune_s = time.perf_counter() - t0
+            print("bench: tuned launch shapes in %.1f s" % tune_s, file=sys.stderr, flush=True)
+            for row in sweep:
+                ni = row["ni"]
+                for prec, name in ((nbx.NBX_FP64, "fp64"), (nbx.NBX_MIXED, "mixed")):
+                    ctx.set_precision(prec)
+                    row[name + "_tuned_shape"] = shape_str(ni)
+                    s, k = timed(torch, nbx, ctx, w, ni, stream, args.sweep_reps, 1)
+                    row[name + "_tuned_kernel_ms"] = round(k * 1e3, 5)
+                    row[name + "_tuned_int_s"] = float("%.4g" % (ni * float(N) / k))
+                row["tuned_speedup"] = round(row["fp64_tuned_kernel_ms"] / row["mixed_tuned_kernel_ms"], 3)
+                print("bench: tuned sweep %s" % json.dumps({k: v for k, v in row.items() if "tuned" in k or k == "ni"}),
+                      file=sys.stderr, flush=True)
     nbx.nbx_sync(ctx.ctx, stream)
     ctx.close()
 
@@ -518,7 +543,8 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32,
             "traffic": load_traffic(),
-            "kernel": "k_force<4,mixed,P=2>",
+            "kernel": "k_force<4,mixed> shape L%d P%d S%d" % (shape["lanes_per_sink"], shape["sinks_per_lane"],
+                                                               shape["splits"]),
             "kernel_ms": kern * 1e3,
             "flops_per_interaction": FLOPS_4TH,
         },
@@ -531,6 +557,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "sweep": sweep,
+        "tune_seconds": tune_s,
     }
     if o2 is not None:
         line["order2"] = o2

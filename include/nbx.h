@@ -305,8 +305,22 @@ int nbx_bs_energy(nbx_ctx *ctx, double *ekin, double *epot);
  * recorded since the last nbx_sync. */
 int nbx_sync(nbx_ctx *ctx, void *stream);
 
-/* Launch shape the library would use for ni sinks against the current sources: lanes per sink,
- * sinks per lane, source splits, workgroups.  Lets callers and benchmarks report it. */
+/* Launch-shape tuner.  The paper's library ships tuning runs that pick the block configuration per
+ * GPU (Results > Thread-block configuration; Conclusions).  For every N_i class 2^k up to ni_max
+ * (capped at ni_max of the context and the sources in use) this times candidate shapes of the
+ * gravity kernel (lanes per sink, sinks per lane, source splits) on the current sources at the
+ * current prediction time and precision, with ni evenly strided source addresses as sinks, and
+ * keeps the fastest per class.  Later force calls at that precision use the table while the
+ * number of 256-source tiles stays the same; otherwise, and before tuning, a static rule applies.
+ * shapes_out (may be NULL) receives lanes per sink, sinks per lane and splits for classes
+ * k = 0 .. n_classes-1 (3 ints each).  Requires nbx_predict.  Synchronous; overwrites the results
+ * of the last nbx_force.  Results of every shape agree to rounding; a fixed table keeps runs
+ * bit-reproducible. */
+int nbx_tune(nbx_ctx *ctx, int ni_max, int32_t *shapes_out, int n_classes);
+
+/* Launch shape the library would use for ni sinks against the current sources (tuned table or
+ * static rule): lanes per sink, sinks per lane, source splits, workgroups.  Lets callers and
+ * benchmarks report it. */
 int nbx_launch_shape(nbx_ctx *ctx, int ni, int *lanes_per_sink, int *sinks_per_lane,
                      int *splits, int *workgroups);
 

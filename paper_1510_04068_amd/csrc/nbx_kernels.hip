@@ -694,12 +694,24 @@ __device__ __forceinline__ typename Tr::J staged_j(const ForceParams &fp, int jj
 
 // Find the first source of the winning group whose key equals the best key (the group start g0
 // and lane stride L identify the group; its length is min(kChunkAcc, 256 / L)).
+// When the group lies in the tile still resident in LDS after the loop (the workgroup's last
+// tile: always the case when a workgroup has one tile, i.e. at small and medium N_i), its records
+// are read back from LDS; otherwise they are staged again from global memory.  Either way they are
+// the records the loop used, so the keys match bit for bit.
 template <class Tr, int Order>
-__device__ __forceinline__ int nn_rescan(const ForceParams &fp, const typename Tr::Sink &s, typename Tr::Key key,
-                                         int g0, int lg, int self) {
+__device__ __forceinline__ int nn_rescan(const ForceParams &fp, const typename Tr::Tile &last, int last_tile,
+                                         const typename Tr::Sink &s, typename Tr::Key key, int g0, int lg,
+                                         int self) {
   if (g0 < 0) return -1;
   const int per = kTile >> lg;
   const int len = per < kChunkAcc ? per : kChunkAcc;
+  if ((g0 >> 8) == last_tile) {  // kTile == 256
+    for (int k = 0; k < len; ++k) {
+      const int jj = g0 + (k << lg);
+      if (jj != self && Tr::nn_key(Tr::load(last, jj & (kTile - 1)), s) == key) return jj;
+    }
+    return -1;
+  }
   for (int k = 0; k < len; ++k) {
     const int jj = g0 + (k << lg);
     if (jj != self && Tr::nn_key(staged_j<Tr, Order>(fp, jj), s) == key) return jj;
@@ -817,7 +829,7 @@ __global__ __launch_bounds__(kThreads) void k_force(const ForceParams fp) {
 #pragma unroll
     for (int k = 0; k < K; ++k) v[p][k] = (double)acc[p].hi[k] + (double)acc[p].lo[k];
     kk[p] = (uint64_t)nnk[p];
-    ii[p] = nn_rescan<Tr, Order>(fp, sink[p], nnk[p], nng[p], lg, self[p]);
+    ii[p] = nn_rescan<Tr, Order>(fp, tiles[(t1 - 1 - t0) & 1], t1 - 1, sink[p], nnk[p], nng[p], lg, self[p]);
   }
   group_reduce<P, K>(L, v, kk, ii, red);
 
@@ -1271,15 +1283,21 @@ __global__ __launch_bounds__(256) void k_fill_i32(int32_t *p, int n, int value) 
 // ---------------------------------------------------------------------------------------------
 int values_per_sink(int order) { return order == 6 ? 10 : (order == 4 ? 7 : 4); }
 
-// Launch shape.  A workgroup holds Q = (256 / L) * P sinks and one of S source ranges.
-//   * About 8 workgroups per CU (2048) fill the 256 CUs.
-//   * Partials cost S * ni * 72 bytes of scratch traffic: S * ni <= 2^21.
+// Launch shape (static rule; nbx_tune replaces it by measured choices per N_i class).  A
+// workgroup holds Q = (256 / L) * P sinks and one of S source ranges.
+//   * About 8 workgroups per CU (2048) fill the 256 CUs; 16 per CU (4096) from N_i = 16384 on,
+//     where every workgroup runs many tiles and a finer split evens out the last round of
+//     workgroups on the CUs (5-7 are resident per CU).
+//   * Partials cost S * ni * 72 bytes of scratch traffic: S * ni <= 2^21, and S <= 512 (more
+//     splits only add partial traffic: measured slower at every N_i).
 //   * Staging a tile costs one FP64 prediction per thread, so a thread should get at least 16
 //     interactions per tile: Q >= 16 unless there are fewer sinks than that.
-// Q runs from min(512, ni rounded up to a power of two; 512 = two sinks per lane) down to that
-// floor and the first Q that reaches the
-// workgroup target wins (the largest reuse of each staged source); if none does, the floor is
-// used with the largest S allowed.  NBX_SHAPE="L,P,S" in the environment overrides the rule.
+//   * Two sinks per lane (Q = 512) pay off only at large N_i (>= 65536), where each workgroup
+//     sees many tiles; below that the fixed per-workgroup work of the second sink dominates.
+// Q runs from ni rounded up to a power of two (at most 256, or 512 at large N_i) down to that
+// floor and the first Q that reaches the workgroup target wins (the largest reuse of each staged
+// source); if none does, the floor is used with the largest S allowed.  NBX_SHAPE="L,P,S" in the
+// environment overrides the rule.
 static int ilog2(int v) {
   int l = 0;
   while ((1 << (l + 1)) <= v) ++l;
@@ -1289,10 +1307,11 @@ static int ilog2(int v) {
 LaunchShape choose_shape(int ni, int nj_pad) {
   LaunchShape ls;
   const int ntiles = nj_pad / kTile > 0 ? nj_pad / kTile : 1;
-  const int target = 2048;
+  const int target = ni >= 16384 ? 4096 : 2048;
   const int64_t part_cap = (int64_t)1 << 21;
   int scap = (int)(part_cap / (ni > 0 ? ni : 1));
   if (scap > ntiles) scap = ntiles;
+  if (scap > 512) scap = 512;
   if (scap < 1) scap = 1;
   if (const char *env = getenv("NBX_SHAPE")) {
     int L = 0, P = 0, S = 0;
@@ -1310,7 +1329,8 @@ LaunchShape choose_shape(int ni, int nj_pad) {
   int qmin = 1;
   while (qmin < ni && qmin < 16) qmin *= 2;
   int qcover = 1;  // never more sink slots than the next power of two of ni
-  while (qcover < ni && qcover < 2 * kThreads) qcover *= 2;
+  const int qtop = ni >= 65536 ? 2 * kThreads : kThreads;
+  while (qcover < ni && qcover < qtop) qcover *= 2;
   int Q = qcover > qmin ? qcover : qmin;
   for (; Q >= qmin; Q /= 2) {
     const int64_t blocks = (ni + Q - 1) / Q;

@@ -74,6 +74,14 @@ struct nbx_ctx {
     DevBuf dt, tnext, list, acc, jrk, snp, pot, nnid, nnr2, wg_min, wg_cnt, sched;
     BsSched *h_sched = nullptr;  // pinned host copy of the schedule
   } bs;
+  // launch-shape tables from nbx_tune, per precision: per N_i class k (ni in (2^(k-1), 2^k]),
+  // valid while the number of source tiles is tune_ntiles[precision]; force_shape overrides
+  // everything while tuning
+  struct TunedShape {
+    int lanes_log2 = -1, sinks_per_lane = 1, splits = 1;
+  } tuned[2][32];
+  int tune_ntiles[2] = {0, 0};
+  const LaunchShape *force_shape = nullptr;
   // state of the last force call (host path)
   int last_ni = -1;
   bool last_nbr = false;
@@ -164,6 +172,41 @@ int check_ctx(nbx_ctx *c) {
   return set_device(c);
 }
 
+int ni_class(int ni) {  // smallest k with 2^k >= ni
+  int k = 0;
+  while ((1 << k) < ni && k < 30) ++k;
+  return k;
+}
+
+// Launch shape for ni sinks: the shape under test while tuning, else the tuned table entry of the
+// N_i class (when the source tile count still matches), else the static rule.  NBX_SHAPE in the
+// environment goes to the static rule, which honours it.
+LaunchShape ctx_shape(const nbx_ctx *c, int ni, int nj_pad) {
+  const int ntiles = nj_pad / kTile > 0 ? nj_pad / kTile : 1;
+  const nbx_ctx::TunedShape *t = nullptr;
+  nbx_ctx::TunedShape forced;
+  if (c->force_shape) {
+    forced.lanes_log2 = c->force_shape->lanes_log2;
+    forced.sinks_per_lane = c->force_shape->sinks_per_lane;
+    forced.splits = c->force_shape->splits;
+    t = &forced;
+  } else if (!getenv("NBX_SHAPE") && c->tune_ntiles[c->precision] == ntiles &&
+             c->tuned[c->precision][ni_class(ni)].lanes_log2 >= 0) {
+    t = &c->tuned[c->precision][ni_class(ni)];
+  }
+  if (!t) return choose_shape(ni, nj_pad);
+  LaunchShape ls;
+  ls.lanes_log2 = t->lanes_log2;
+  ls.sinks_per_lane = t->sinks_per_lane;
+  const int Q = (kThreads >> ls.lanes_log2) * ls.sinks_per_lane;
+  ls.blocks = (ni + Q - 1) / Q;
+  int S = t->splits < ntiles ? t->splits : ntiles;
+  const int64_t scap = ((int64_t)1 << 21) / (ni > 0 ? ni : 1);
+  if (S > scap) S = (int)scap;
+  ls.splits = S < 1 ? 1 : S;
+  return ls;
+}
+
 // Shared by the host and device force paths.
 int enqueue_force(nbx_ctx *c, hipStream_t stream, int ni, const int32_t *d_iaddr, const int32_t *ext_self,
                   const int64_t *ext_id, const double *ext_x, const double *ext_v, const double *ext_a,
@@ -173,7 +216,7 @@ int enqueue_force(nbx_ctx *c, hipStream_t stream, int ni, const int32_t *d_iaddr
   if (!(eps2 >= 0.0)) return fail(c, NBX_ERR_ARG, "eps2 must be >= 0 (got %g)", eps2);
   if (ni == 0) return NBX_OK;
   const int nj_pad = (c->nj + kTile - 1) / kTile * kTile;
-  const LaunchShape ls = choose_shape(ni, nj_pad);
+  const LaunchShape ls = ctx_shape(c, ni, nj_pad);
   int rc = ensure_scratch(c, ni, ls);
   if (rc) return rc;
   ForceParams fp{};
@@ -765,6 +808,8 @@ int nbx_batch_tune(nbx_ctx *c, void *stream, const double *d_m, const double *d_
   return batch_enqueue(c, s, d_m, d_x, d_v, eps2, d_acc, d_jerk, d_pot);
 }
 
+}  // extern "C"
+
 // ---- block time-step integrator ------------------------------------------------------------------
 
 namespace {
@@ -827,6 +872,8 @@ int bs_check(nbx_ctx *c) {
 }
 
 }  // namespace
+
+extern "C" {
 
 int nbx_bs_init(nbx_ctx *c, int n, const int64_t *id, const double *m, const double *x, const double *v,
                 const nbx_bs_params *p) {
@@ -995,6 +1042,130 @@ int nbx_bs_energy(nbx_ctx *c, double *ekin, double *epot) {
   return collect_errors(c);
 }
 
+}  // extern "C"
+
+// ---- launch-shape tuner ------------------------------------------------------------------------
+
+namespace {
+
+// Candidate shapes for ni sinks against ntiles source tiles: every lanes-per-sink L (two sinks per
+// lane only with L = 1) whose sink slots are not mostly idle, and every power-of-two split count
+// (and ntiles itself) that gives at most 8192 workgroups and at most 2^21 partial sums; shapes with
+// fewer than 64 workgroups are dropped unless no shape reaches 64 (few sources).
+std::vector<LaunchShape> tune_candidates(int ni, int ntiles) {
+  std::vector<LaunchShape> out;
+  int64_t wmax = 0;
+  int cover = 1;
+  while (cover < ni) cover *= 2;
+  for (int lg = 0; lg <= 8; ++lg) {
+    for (int P = 1; P <= 2; ++P) {
+      if (P == 2 && lg != 0) continue;
+      const int Q = (kThreads >> lg) * P;
+      if (Q > 1 && Q > 2 * cover) continue;
+      const int blocks = (ni + Q - 1) / Q;
+      for (int S = 1; S <= ntiles; S = (S * 2 <= ntiles || S == ntiles) ? S * 2 : ntiles) {
+        const int64_t W = (int64_t)blocks * S;
+        if (W <= 8192 && (int64_t)S * ni <= ((int64_t)1 << 21)) {
+          LaunchShape ls;
+          ls.lanes_log2 = lg;
+          ls.sinks_per_lane = P;
+          ls.splits = S;
+          ls.blocks = blocks;
+          out.push_back(ls);
+          wmax = std::max(wmax, W);
+        }
+        if (S == ntiles) break;
+      }
+    }
+  }
+  const int64_t wmin = std::min<int64_t>(64, wmax);
+  std::vector<LaunchShape> keep;
+  for (const LaunchShape &ls : out)
+    if ((int64_t)ls.blocks * ls.splits >= wmin) keep.push_back(ls);
+  return keep;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nbx_tune(nbx_ctx *c, int ni_max, int32_t *shapes_out, int n_classes) {
+  if (int rc = check_ctx(c)) return rc;
+  if (!c->predicted) return fail(c, NBX_ERR_STATE, "nbx_tune before nbx_predict");
+  if (c->nj < 1) return fail(c, NBX_ERR_STATE, "no sources in use");
+  if (ni_max < 1) return fail(c, NBX_ERR_ARG, "ni_max must be >= 1");
+  if (shapes_out && n_classes < 0) return fail(c, NBX_ERR_ARG, "n_classes < 0");
+  ni_max = std::min(std::min(ni_max, c->cfg.ni_max), c->nj);
+  const int nj_pad = (c->nj + kTile - 1) / kTile * kTile;
+  const int ntiles = nj_pad / kTile;
+  struct Events {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Events() {
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+    }
+  } ev;
+  HIP_TRY(c, hipEventCreate(&ev.e0));
+  HIP_TRY(c, hipEventCreate(&ev.e1));
+  struct Reset {  // leave no shape override behind on any return path
+    nbx_ctx *c;
+    ~Reset() { c->force_shape = nullptr; }
+  } reset{c};
+  const int pr = c->precision;
+  c->tune_ntiles[pr] = 0;
+  for (auto &t : c->tuned[pr]) t = nbx_ctx::TunedShape{};
+  const int kmax = ni_class(ni_max);
+  std::vector<int32_t> addr;
+  for (int k = 0; k <= kmax; ++k) {
+    const int ni = std::min(1 << k, ni_max);
+    addr.resize(ni);
+    for (int i = 0; i < ni; ++i) addr[i] = (int32_t)((int64_t)i * c->nj / ni);  // evenly strided sinks
+    HIP_TRY(c, hipMemcpy(c->d_iaddr, addr.data(), (size_t)ni * 4, hipMemcpyHostToDevice));
+    float best_ms = 1e30f;
+    nbx_ctx::TunedShape best;
+    for (const LaunchShape &cand : tune_candidates(ni, ntiles)) {
+      c->force_shape = &cand;
+      auto launch = [&]() {
+        return enqueue_force(c, c->stream, ni, c->d_iaddr, nullptr, nullptr, nullptr, nullptr, nullptr, 0.0, nullptr,
+                             c->d_acc, c->d_jrk ? c->d_jrk : c->d_acc, c->d_snp, c->d_pot, c->d_nnid, c->d_nnr2,
+                             nullptr, nullptr);
+      };
+      if (int rc = launch()) return rc;  // warm-up, and an estimate of the launch time
+      HIP_TRY(c, hipEventRecord(ev.e0, c->stream));
+      if (int rc = launch()) return rc;
+      HIP_TRY(c, hipEventRecord(ev.e1, c->stream));
+      HIP_TRY(c, hipEventSynchronize(ev.e1));
+      float ms = 0.f;
+      HIP_TRY(c, hipEventElapsedTime(&ms, ev.e0, ev.e1));
+      const int reps = std::max(2, std::min(20, (int)(2.0f / std::max(ms, 1e-3f))));
+      HIP_TRY(c, hipEventRecord(ev.e0, c->stream));
+      for (int r = 0; r < reps; ++r)
+        if (int rc = launch()) return rc;
+      HIP_TRY(c, hipEventRecord(ev.e1, c->stream));
+      HIP_TRY(c, hipEventSynchronize(ev.e1));
+      HIP_TRY(c, hipEventElapsedTime(&ms, ev.e0, ev.e1));
+      ms /= reps;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best.lanes_log2 = cand.lanes_log2;
+        best.sinks_per_lane = cand.sinks_per_lane;
+        best.splits = cand.splits;
+      }
+    }
+    c->force_shape = nullptr;
+    c->tuned[pr][k] = best;
+    if (shapes_out && k < n_classes) {
+      shapes_out[3 * k] = best.lanes_log2 < 0 ? 0 : 1 << best.lanes_log2;
+      shapes_out[3 * k + 1] = best.sinks_per_lane;
+      shapes_out[3 * k + 2] = best.splits;
+    }
+  }
+  c->tune_ntiles[pr] = ntiles;
+  c->last_ni = -1;  // the host-path result buffers hold tuning output
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return collect_errors(c);
+}
+
 int nbx_sync(nbx_ctx *c, void *stream) {
   if (int rc = check_ctx(c)) return rc;
   if (stream) HIP_TRY(c, hipStreamSynchronize(static_cast<hipStream_t>(stream)));
@@ -1006,7 +1177,7 @@ int nbx_sync(nbx_ctx *c, void *stream) {
 int nbx_launch_shape(nbx_ctx *c, int ni, int *lanes_per_sink, int *sinks_per_lane, int *splits, int *workgroups) {
   if (!c || ni < 1) return NBX_ERR_ARG;
   const int nj_pad = (c->nj + kTile - 1) / kTile * kTile;
-  const LaunchShape ls = choose_shape(ni, nj_pad);
+  const LaunchShape ls = ctx_shape(c, ni, nj_pad);
   if (lanes_per_sink) *lanes_per_sink = 1 << ls.lanes_log2;
   if (sinks_per_lane) *sinks_per_lane = ls.sinks_per_lane;
   if (splits) *splits = ls.splits;

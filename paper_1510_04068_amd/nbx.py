@@ -45,7 +45,7 @@ EXPORTS = (
     "nbx_set_nj", "nbx_set_j", "nbx_predict", "nbx_force", "nbx_force_ext", "nbx_get_force", "nbx_get_nbr",
     "nbx_get_predicted", "nbx_get_j", "nbx_set_j_dev", "nbx_force_dev", "nbx_sync", "nbx_launch_shape",
     "nbx_batch_setup", "nbx_batch_tune", "nbx_batch_force_dev", "nbx_force_vjp_dev",
-    "nbx_bs_init", "nbx_bs_step", "nbx_bs_run", "nbx_bs_get_state", "nbx_bs_energy",
+    "nbx_bs_init", "nbx_bs_step", "nbx_bs_run", "nbx_bs_get_state", "nbx_bs_energy", "nbx_tune",
 )
 NBX_BATCH_NMAX = 128
 
@@ -136,6 +136,7 @@ def load(path: str = LIB_PATH):
         "nbx_bs_run": ([_P, _D, ctypes.POINTER(nbx_bs_stats)], _I),
         "nbx_bs_get_state": ([_P, _P, _P, _P, _P, _P, ctypes.POINTER(nbx_bs_stats)], _I),
         "nbx_bs_energy": ([_P, _P, _P], _I),
+        "nbx_tune": ([_P, _I, _P, _I], _I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -330,6 +331,16 @@ def nbx_launch_shape(ctx, ni):
             "workgroups": vals[3].value}
 
 
+def nbx_tune(ctx, ni_max):
+    """Tune the launch shape per N_i class; returns an (n_classes, 3) array of (L, P, S)."""
+    k = 0
+    while (1 << k) < ni_max:
+        k += 1
+    out = np.zeros((k + 1, 3), dtype=np.int32)
+    _check(ctx, load().nbx_tune(ctx, int(ni_max), _ptr(out), int(k + 1)))
+    return out
+
+
 def nbx_batch_setup(ctx, offsets):
     offsets = np.ascontiguousarray(offsets, dtype=np.int32)
     return _check(ctx, load().nbx_batch_setup(ctx, int(offsets.shape[0] - 1), _ptr(offsets)))
@@ -467,6 +478,9 @@ class Context:
 
     def get_j(self, addr):
         return nbx_get_j(self.ctx, addr, self.order)
+
+    def tune(self, ni_max):
+        return nbx_tune(self.ctx, ni_max)
 
     def launch_shape(self, ni):
         return nbx_launch_shape(self.ctx, ni)
