@@ -38,7 +38,7 @@ PEAK_FP32 = 157.3  # TFLOP/s, MI355X FP32 vector
 PEAK_FP64 = 78.6  # TFLOP/s, MI355X FP64 vector
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_force_mixed_plummer131072_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1510_04068_amd", "csrc", f)
-                  for f in ("nbx_kernels.hip", "nbx_internal.h", "nbx_predict.h")]
+                  for f in ("nbx_kernels.hip", "nbx_internal.h", "nbx_predict.h", "nbx_bs_device.h")]
 
 
 def kernel_hash():
@@ -285,7 +285,7 @@ def order2(torch, nbx, ics, dev, steps):
             "flops_per_interaction": FLOPS_2ND, "rows": rows}
 
 
-def blockstep(torch, nbx, ics, sizes):
+def blockstep(torch, nbx, ics, sizes, tune=True):
     """6th-order block time-step runs, one N-body time unit, FP64 (DP) and mixed (DS): wall time from
     the start to the end of the integration, energy error, block steps and mean N_active."""
     import numpy as np
@@ -299,6 +299,9 @@ def blockstep(torch, nbx, ics, sizes):
             t0 = time.perf_counter()
             nbx.nbx_bs_init(ctx.ctx, np.arange(n), m, x, v, BS_EPS2, eta4=0.01, eta6=0.1, eta_start=BS_ETA_START)
             e0 = sum(nbx.nbx_bs_energy(ctx.ctx))
+            tt = time.perf_counter()
+            if tune:  # launch shapes per N_i class for these sources (setup, not part of the run)
+                ctx.tune(n)
             t1 = time.perf_counter()
             for k in range(1, 9):  # one time unit in eighths, with a progress line each
                 st = nbx.nbx_bs_run(ctx.ctx, k / 8.0)
@@ -310,7 +313,8 @@ def blockstep(torch, nbx, ics, sizes):
             t2 = time.perf_counter()
             e1 = sum(nbx.nbx_bs_energy(ctx.ctx))
             ctx.close()
-            row = {"n": n, "precision": name, "init_s": round(t1 - t0, 4), "run_s": round(t2 - t1, 4),
+            row = {"n": n, "precision": name, "init_s": round(tt - t0, 4), "tune_s": round(t1 - tt, 3),
+                   "run_s": round(t2 - t1, 4),
                    "block_steps": st["block_steps"], "particle_steps": st["particle_steps"],
                    "mean_n_active": round(st["particle_steps"] / max(st["block_steps"], 1), 2),
                    "energy_error": float("%.3e" % abs((e1 - e0) / e0)), "status": st["status"],
@@ -505,7 +509,8 @@ def main():
     ctx.close()
 
     o2 = order2(torch, nbx, nbody_ics, dev, max(3, args.steps // 2)) if args.order2 else None
-    bsr = blockstep(torch, nbx, nbody_ics, [int(k) for k in args.blockstep.split(",")]) if args.blockstep else None
+    bsr = (blockstep(torch, nbx, nbody_ics, [int(k) for k in args.blockstep.split(",")], tune=not args.no_tune)
+           if args.blockstep else None)
     o6 = order6(torch, nbx, nbody_ics, dev, max(2, args.steps // 10)) if args.order6 else None
     bt = batch(torch, nbx, nbody_ics, dev, max(20, args.steps)) if args.batch else None
     adj = adjoint(torch, nbx, nbody_ics, dev, max(3, args.steps // 5)) if args.adjoint else None

@@ -8,12 +8,11 @@
 // (the force launch shape depends on N_active).
 //
 // One block step:
-//   1. schedule: t_next = min_i (t_i + dt_i) and the ordered list of the particles with
-//      t_i + dt_i == t_next (k_bs_min, k_bs_count, k_bs_list; no atomics, so the list is in
-//      address order and the step is deterministic);
+//   1. schedule: t_next = min_i (t_i + dt_i) and the list of the particles with
+//      t_i + dt_i == t_next (k_bs_min, k_bs_list);
 //   2. forces on the active particles at t_next: the gravity kernel (fused predictor);
 //   3. correct, choose the next step and write the new state back into the source arrays
-//      (k_bs_correct).
+//      (k_bs_correct, or the split-combine kernel of step 2 when the force launch has splits).
 //
 // Hermite corrector (Makino & Aarseth 1992 for 4th order; Nitadori & Makino 2008 for 6th), with
 // h = dt/2.  Each line is the integral over the step of the Hermite interpolant of the integrand
@@ -45,6 +44,7 @@
 #include "nbx.h"
 #include "nbx_internal.h"
 #include "nbx_predict.h"
+#include "nbx_bs_device.h"
 
 namespace nbx {
 
@@ -52,11 +52,6 @@ constexpr int kBsPer = kBsChunk / kThreads;  // particles per thread in the sche
 
 __device__ __forceinline__ double wave_min(double v) {
   for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
-  return v;
-}
-
-__device__ __forceinline__ int wave_sum(int v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
   return v;
 }
 
@@ -70,18 +65,6 @@ __device__ double block_min(double v, double *red) {
   for (int w = 1; w < kThreads / 64; ++w) m = fmin(m, red[w]);
   __syncthreads();
   return m;
-}
-
-// Sum over the workgroup, returned to every thread.
-__device__ int block_sum(int v, int *red) {
-  v = wave_sum(v);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  int s = 0;
-#pragma unroll
-  for (int w = 0; w < kThreads / 64; ++w) s += red[w];
-  __syncthreads();
-  return s;
 }
 
 // Exclusive prefix sum over the workgroup in thread order; *total receives the sum.
@@ -117,43 +100,28 @@ __global__ __launch_bounds__(kThreads) void k_bs_min(BlockStepParams bp) {
     if (i < bp.n) m = fmin(m, bp.tnext[i]);
   }
   m = block_min(m, red);
-  if (threadIdx.x == 0) bp.wg_min[blockIdx.x] = m;
+  if (threadIdx.x == 0) {
+    bp.wg_min[blockIdx.x] = m;
+    if (blockIdx.x == 0) bp.sched->count = 0;
+  }
 }
 
-// 2. every workgroup reduces all partial minima to t_next, counts its active particles;
-//    workgroup 0 publishes t_next
-__global__ __launch_bounds__(kThreads) void k_bs_count(BlockStepParams bp) {
+// 2. compaction: every workgroup reduces all partial minima to t_next, collects its active
+//    particles in address order (workgroup prefix scan) and reserves their slots in the list with
+//    one atomic add on the count (zeroed by k_bs_min).  The chunks land in the list in arrival
+//    order; every result of a block step depends only on the set of active particles, not on
+//    their order, because each sink's sum order is fixed by the launch shape.  Workgroup 0
+//    publishes t_next.
+__global__ __launch_bounds__(kThreads) void k_bs_list(BlockStepParams bp) {
   __shared__ double red[kThreads / 64];
   __shared__ int redi[kThreads / 64];
+  __shared__ int base;
   const int nwg = gridDim.x;
   double m = __builtin_huge_val();
   for (int k = threadIdx.x; k < nwg; k += kThreads) m = fmin(m, bp.wg_min[k]);
   const double tn = block_min(m, red);
-  const int b0 = blockIdx.x * kBsChunk;
-  int c = 0;
-#pragma unroll
-  for (int r = 0; r < kBsPer; ++r) {
-    const int i = b0 + r * kThreads + threadIdx.x;
-    if (i < bp.n && bp.tnext[i] == tn) ++c;
-  }
-  c = block_sum(c, redi);
-  if (threadIdx.x == 0) {
-    bp.wg_cnt[blockIdx.x] = c;
-    if (blockIdx.x == 0) bp.sched->t_next = tn;
-  }
-}
-
-// 3. ordered compaction: workgroup b writes its active particles, in address order, after those
-//    of workgroups 0..b-1; the last workgroup publishes the count
-__global__ __launch_bounds__(kThreads) void k_bs_list(BlockStepParams bp) {
-  __shared__ int redi[kThreads / 64];
-  const int b = blockIdx.x;
-  int before = 0;
-  for (int k = threadIdx.x; k < b; k += kThreads) before += bp.wg_cnt[k];
-  const int offset = block_sum(before, redi);
-  const double tn = bp.sched->t_next;
   // thread t owns the kBsPer consecutive particles b0 + t*kBsPer ... (address order = thread order)
-  const int i0 = b * kBsChunk + threadIdx.x * kBsPer;
+  const int i0 = blockIdx.x * kBsChunk + threadIdx.x * kBsPer;
   bool act[kBsPer];
   int mine = 0;
 #pragma unroll
@@ -163,110 +131,30 @@ __global__ __launch_bounds__(kThreads) void k_bs_list(BlockStepParams bp) {
     mine += act[r] ? 1 : 0;
   }
   int total = 0;
-  int pos = offset + block_exclusive_scan(mine, redi, &total);
+  const int pos0 = block_exclusive_scan(mine, redi, &total);
+  if (threadIdx.x == 0) {
+    base = total > 0 ? atomicAdd(&bp.sched->count, total) : 0;
+    if (blockIdx.x == 0) bp.sched->t_next = tn;
+  }
+  __syncthreads();
+  int pos = base + pos0;
 #pragma unroll
   for (int r = 0; r < kBsPer; ++r)
     if (act[r]) bp.list[pos++] = i0 + r;
-  if (b == gridDim.x - 1 && threadIdx.x == 0) bp.sched->count = offset + total;
-}
-
-__device__ __forceinline__ double norm3(const double v[3]) { return sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); }
-
-// Power-of-two step for the criterion `crit`, from the current step dt_old ending at t1.
-__device__ void report_clamp(const BlockStepParams &bp) {
-  atomicAdd(&bp.err[3], 1);
-  atomicAdd(&bp.sched->clamped, 1);
-}
-
-__device__ double quantise(double crit, double dt_old, double t1, const BlockStepParams &bp) {
-  if (!(crit >= 0.0)) {  // NaN or negative: keep the step and report it
-    report_clamp(bp);
-    return dt_old;
-  }
-  double dn = dt_old;
-  if (crit < dt_old) {
-    while (dn > crit && dn > bp.dt_min) dn *= 0.5;
-    if (dn > crit) report_clamp(bp);  // clamped at dt_min
-  } else if (crit >= 2.0 * dt_old && 2.0 * dt_old <= bp.dt_max && fmod(t1, 2.0 * dt_old) == 0.0) {
-    dn = 2.0 * dt_old;
-  }
-  return dn;
-}
-
-// Ratio guard: a zero denominator (e.g. a particle far from everything) allows the largest step.
-__device__ __forceinline__ double safe_ratio(double num, double den, double big) {
-  return den > 0.0 ? num / den : big;
 }
 
 template <int Order>
 __global__ __launch_bounds__(kThreads) void k_bs_correct(BlockStepParams bp, int ni, double t1) {
   const int k = blockIdx.x * kThreads + threadIdx.x;
   if (k >= ni) return;
-  const int i = bp.list[k];
-  Raw r;
-  load_raw<Order>(bp.src, i, r);
-  const double dt = bp.dt[i];
-  const double h = 0.5 * dt;
-  const double h2 = h * h;
-  double a1[3], j1[3], s1[3] = {0.0, 0.0, 0.0}, x1[3], v1[3];
-  double d2[3], d3[3], d4[3] = {0.0, 0.0, 0.0}, d5[3] = {0.0, 0.0, 0.0};
+  double a1[3], j1[3], s1[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     a1[c] = bp.acc[3 * (size_t)k + c];
     j1[c] = bp.jrk[3 * (size_t)k + c];
     if constexpr (Order == 6) s1[c] = bp.snp[3 * (size_t)k + c];
-    const double am = a1[c] - r.a[c], ap = a1[c] + r.a[c];
-    const double jm = j1[c] - r.j[c], jp = j1[c] + r.j[c];
-    if constexpr (Order == 4) {
-      v1[c] = r.v[c] + h * ap - (h2 / 3.0) * jm;
-      x1[c] = r.x[c] + h * (r.v[c] + v1[c]) - (h2 / 3.0) * am;
-      const double c2 = jm / (4.0 * h);
-      const double c3 = (h * jp - am) / (4.0 * h2 * h);
-      d2[c] = 2.0 * c2 + 6.0 * c3 * h;
-      d3[c] = 6.0 * c3;
-    } else {
-      const double sm = s1[c] - r.s[c], sp = s1[c] + r.s[c];
-      v1[c] = r.v[c] + h * ap - (0.4 * h2) * jm + (h2 * h / 15.0) * sp;
-      x1[c] = r.x[c] + h * (r.v[c] + v1[c]) - (0.4 * h2) * am + (h2 * h / 15.0) * jp;
-      const double w4 = (h2 * sp - h * jm) / 16.0;               // c4 h^4
-      const double w5 = (h2 * sm - 3.0 * h * jp + 3.0 * am) / 16.0;  // c5 h^5
-      const double w3 = (5.0 * h * jp - 5.0 * am - h2 * sm) / 8.0;   // c3 h^3
-      const double h3 = h2 * h, h4 = h2 * h2, h5 = h4 * h;
-      d2[c] = s1[c];
-      d3[c] = (6.0 * w3 + 24.0 * w4 + 60.0 * w5) / h3;
-      d4[c] = (24.0 * w4 + 120.0 * w5) / h4;
-      d5[c] = 120.0 * w5 / h5;
-    }
   }
-  const double na = norm3(a1), nj = norm3(j1), n2 = norm3(d2), n3 = norm3(d3);
-  const double big = bp.dt_max * bp.dt_max * 4.0;
-  const double num = na * n2 + nj * nj;
-  double crit = sqrt(bp.eta4 * safe_ratio(num, nj * n3 + n2 * n2, big / bp.eta4));
-  if constexpr (Order == 6) {
-    const double n4 = norm3(d4), n5 = norm3(d5);
-    const double q = safe_ratio(num, n3 * n5 + n4 * n4, -1.0);
-    const double dt6 = q < 0.0 ? 2.0 * bp.dt_max : bp.eta6 * pow(q, 1.0 / 6.0);
-    crit = 0.5 * (crit + dt6);
-  }
-  const double dn = quantise(crit, dt, t1, bp);
-  bp.src.pos_mass[i] = make_double4(x1[0], x1[1], x1[2], r.m);
-  bp.src.vel_time[i] = make_double4(v1[0], v1[1], v1[2], t1);
-  double *aj = bp.src.acc_jrk + 6 * (size_t)i;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    aj[c] = a1[c];
-    aj[3 + c] = j1[c];
-  }
-  if constexpr (Order == 6) {
-    double *sc = bp.src.snp_crk + 6 * (size_t)i;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      sc[c] = s1[c];
-      sc[3 + c] = d3[c];  // crackle at t1 for the next prediction
-    }
-  }
-  bp.dt[i] = dn;
-  bp.tnext[i] = t1 + dn;
+  bs_correct_particle<Order>(bp, bp.list[k], t1, a1, j1, s1);
 }
 
 // Start: particles at t = 0 with no derivatives yet; list = 0..n-1.
@@ -355,7 +243,6 @@ int bs_groups(int n) { return (n + kBsChunk - 1) / kBsChunk; }
 hipError_t launch_bs_schedule(const BlockStepParams &bp, hipStream_t stream) {
   const int g = bs_groups(bp.n);
   hipLaunchKernelGGL(k_bs_min, dim3(g), dim3(kThreads), 0, stream, bp);
-  hipLaunchKernelGGL(k_bs_count, dim3(g), dim3(kThreads), 0, stream, bp);
   hipLaunchKernelGGL(k_bs_list, dim3(g), dim3(kThreads), 0, stream, bp);
   return hipGetLastError();
 }

@@ -33,6 +33,27 @@ struct SourceArrays {
   int64_t *id;
 };
 
+// Block time-step integrator (device resident).  The particle state is the source arrays; the
+// force rows acc/jrk/snp are those of the active list (row k = particle list[k]).
+constexpr int kBsChunk = 4 * kThreads;  // particles per workgroup in the scheduling kernels
+struct BsSched {
+  double t_next;  // next block time
+  int count;      // active particles at t_next
+  int clamped;    // steps clamped at dt_min (or with a criterion that is not a number) since the start
+};
+struct BlockStepParams {
+  SourceArrays src;
+  int n;
+  double eta4, eta6, eta_start, dt_max, dt_min;
+  double *dt;       // [n] current step of each particle (power of two)
+  double *tnext;    // [n] t_i + dt_i
+  int32_t *list;    // [n] active particles of the current block step (address order within chunks)
+  double *wg_min;   // [groups] partial minima of tnext
+  BsSched *sched;
+  const double *acc, *jrk, *snp;  // forces of the active list at the block time
+  int *err;                       // [3]: steps clamped at dt_min or criteria that were not numbers
+};
+
 // One force launch.  Sinks are either taken by address from the predicted sources (i_addr) or
 // given explicitly (ext_*, with self-exclusion by id).
 struct ForceParams {
@@ -68,6 +89,11 @@ struct ForceParams {
   uint64_t *part_key;
   int32_t *part_idx;
   int *err;  // device-side error counters: [0] bad sink address, [1] bad source address, [2] list overflow
+  // block time-step step (bs_fuse != 0, only with S > 1): the combine kernel corrects particle
+  // bs.list[q] at time bs_t1 instead of writing sink q's outputs
+  int bs_fuse;
+  double bs_t1;
+  BlockStepParams bs;
 };
 
 // Batched few-body systems: particles of system s are [offset[s], offset[s+1]); items[k] =
@@ -102,28 +128,6 @@ struct VjpParams {
   double *grad_v;
   double *grad_m;
   double *part;
-};
-
-// Block time-step integrator (device resident).  The particle state is the source arrays; the
-// force rows acc/jrk/snp are those of the active list (row k = particle list[k]).
-constexpr int kBsChunk = 4 * kThreads;  // particles per workgroup in the scheduling kernels
-struct BsSched {
-  double t_next;  // next block time
-  int count;      // active particles at t_next
-  int clamped;    // steps clamped at dt_min (or with a criterion that is not a number) since the start
-};
-struct BlockStepParams {
-  SourceArrays src;
-  int n;
-  double eta4, eta6, eta_start, dt_max, dt_min;
-  double *dt;       // [n] current step of each particle (power of two)
-  double *tnext;    // [n] t_i + dt_i
-  int32_t *list;    // [n] active particles of the current block step, address order
-  double *wg_min;   // [groups] partial minima of tnext
-  int32_t *wg_cnt;  // [groups] active particles per group
-  BsSched *sched;
-  const double *acc, *jrk, *snp;  // forces of the active list at the block time
-  int *err;                       // [3]: steps clamped at dt_min or criteria that were not numbers
 };
 
 struct LaunchShape {

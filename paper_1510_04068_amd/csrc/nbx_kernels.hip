@@ -44,6 +44,7 @@
 
 #include "nbx_internal.h"
 #include "nbx_predict.h"
+#include "nbx_bs_device.h"
 
 #include "nbx.h"
 
@@ -890,7 +891,14 @@ __global__ __launch_bounds__(kThreads) void k_combine(const ForceParams fp, int 
     }
   }
   group_reduce<1, K>(R, w, wk, wi, red);
-  if (r == 0 && qg < fp.ni) finalize_sink<Order>(fp, qg, w[0], wi[0]);
+  if (r != 0 || qg >= fp.ni) return;
+  if constexpr (Order != 2) {
+    if (fp.bs_fuse) {  // block time-step: correct the particle right away
+      bs_correct_particle<Order>(fp.bs, fp.bs.list[qg], fp.bs_t1, &w[0][0], &w[0][3], Order == 6 ? &w[0][7] : &w[0][0]);
+      return;
+    }
+  }
+  finalize_sink<Order>(fp, qg, w[0], wi[0]);
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -71,7 +71,7 @@ struct nbx_ctx {
     nbx_bs_params p{};
     double t = 0.0;
     int64_t blocks = 0, steps = 0;
-    DevBuf dt, tnext, list, acc, jrk, snp, pot, nnid, nnr2, wg_min, wg_cnt, sched;
+    DevBuf dt, tnext, list, acc, jrk, snp, pot, nnid, nnr2, wg_min, sched;
     BsSched *h_sched = nullptr;  // pinned host copy of the schedule
   } bs;
   // launch-shape tables from nbx_tune, per precision: per N_i class k (ni in (2^(k-1), 2^k]),
@@ -208,10 +208,14 @@ LaunchShape ctx_shape(const nbx_ctx *c, int ni, int nj_pad) {
 }
 
 // Shared by the host and device force paths.
+// With bs given, a launch with source splits lets the combine kernel run the block-step corrector
+// (at time bs_t1) instead of writing the outputs; *fused tells the caller whether that happened.
 int enqueue_force(nbx_ctx *c, hipStream_t stream, int ni, const int32_t *d_iaddr, const int32_t *ext_self,
                   const int64_t *ext_id, const double *ext_x, const double *ext_v, const double *ext_a,
                   double eps2, const double *d_h2, double *acc, double *jrk, double *snp, double *pot,
-                  int64_t *nn_id, double *nn_r2, int32_t *nbr_cnt, int64_t *nbr_ids) {
+                  int64_t *nn_id, double *nn_r2, int32_t *nbr_cnt, int64_t *nbr_ids,
+                  const BlockStepParams *bs = nullptr, double bs_t1 = 0.0, bool *fused = nullptr) {
+  if (fused) *fused = false;
   if (!c->predicted) return fail(c, NBX_ERR_STATE, "nbx_force before nbx_predict");
   if (!(eps2 >= 0.0)) return fail(c, NBX_ERR_ARG, "eps2 must be >= 0 (got %g)", eps2);
   if (ni == 0) return NBX_OK;
@@ -248,8 +252,14 @@ int enqueue_force(nbx_ctx *c, hipStream_t stream, int ni, const int32_t *d_iaddr
   fp.part_key = static_cast<uint64_t *>(c->part_key.p);
   fp.part_idx = static_cast<int32_t *>(c->part_idx.p);
   fp.err = c->d_err;
+  if (bs && ls.splits > 1 && !d_h2) {
+    fp.bs_fuse = 1;
+    fp.bs_t1 = bs_t1;
+    fp.bs = *bs;
+  }
   hipError_t e = launch_force(c->cfg.order, c->precision, fp, ls, stream);
   if (e != hipSuccess) return hip_fail(c, e, "force kernel launch");
+  if (fused) *fused = fp.bs_fuse != 0;
   return NBX_OK;
 }
 
@@ -833,7 +843,6 @@ BlockStepParams bs_params(nbx_ctx *c) {
   bp.tnext = static_cast<double *>(c->bs.tnext.p);
   bp.list = static_cast<int32_t *>(c->bs.list.p);
   bp.wg_min = static_cast<double *>(c->bs.wg_min.p);
-  bp.wg_cnt = static_cast<int32_t *>(c->bs.wg_cnt.p);
   bp.sched = static_cast<BsSched *>(c->bs.sched.p);
   bp.acc = static_cast<const double *>(c->bs.acc.p);
   bp.jrk = static_cast<const double *>(c->bs.jrk.p);
@@ -842,15 +851,16 @@ BlockStepParams bs_params(nbx_ctx *c) {
   return bp;
 }
 
-// Forces on the first ni particles of the list at time t into the integrator's force rows.
-int bs_force(nbx_ctx *c, int ni, double t) {
+// Forces on the first ni particles of the list at time t into the integrator's force rows.  With
+// step != nullptr (a block step) the corrector may be fused into the combine kernel (*fused).
+int bs_force(nbx_ctx *c, int ni, double t, const BlockStepParams *step = nullptr, bool *fused = nullptr) {
   c->t_pred = t;
   c->predicted = true;
   return enqueue_force(c, c->stream, ni, static_cast<const int32_t *>(c->bs.list.p), nullptr, nullptr, nullptr,
                        nullptr, nullptr, c->bs.p.eps2, nullptr, static_cast<double *>(c->bs.acc.p),
                        static_cast<double *>(c->bs.jrk.p), static_cast<double *>(c->bs.snp.p),
                        static_cast<double *>(c->bs.pot.p), static_cast<int64_t *>(c->bs.nnid.p),
-                       static_cast<double *>(c->bs.nnr2.p), nullptr, nullptr);
+                       static_cast<double *>(c->bs.nnr2.p), nullptr, nullptr, step, t, fused);
 }
 
 // Schedule the next block step; returns (t_next, count, clamped so far) through the pinned copy.
@@ -899,7 +909,6 @@ int nbx_bs_init(nbx_ctx *c, int n, const int64_t *id, const double *m, const dou
   rc = rc ? rc : grow(c, c->bs.nnid, N * 8);
   rc = rc ? rc : grow(c, c->bs.nnr2, N * 8);
   rc = rc ? rc : grow(c, c->bs.wg_min, G * 8);
-  rc = rc ? rc : grow(c, c->bs.wg_cnt, G * 4);
   rc = rc ? rc : grow(c, c->bs.sched, sizeof(BsSched));
   rc = rc ? rc : grow(c, c->up, N * (8 + 8 + 24 + 24) + 256);
   if (rc) return rc;
@@ -950,8 +959,10 @@ int nbx_bs_step(nbx_ctx *c, double t_end, int *n_active) {
     return rc == NBX_OK ? NBX_WARN_DT_MIN : rc;
   }
   if (!(tn <= t_end) || ni < 1) return NBX_OK;
-  if (int rc = bs_force(c, ni, tn)) return rc;
-  HIP_TRY(c, launch_bs_correct(c->cfg.order, bs_params(c), ni, tn, c->stream));
+  const BlockStepParams bp = bs_params(c);
+  bool fused = false;
+  if (int rc = bs_force(c, ni, tn, &bp, &fused)) return rc;
+  if (!fused) HIP_TRY(c, launch_bs_correct(c->cfg.order, bp, ni, tn, c->stream));
   c->bs.t = tn;
   c->bs.blocks += 1;
   c->bs.steps += ni;
