@@ -81,3 +81,42 @@ def test_batch_few_body(prec):
             else:
                 assert e_cond.max() <= 1e-6 and e_acc[kappa <= 2].max() <= tol and e_pot.max() <= tol
             assert np.median(e_jrk) <= 100 * tol
+
+
+@pytest.mark.parametrize("prec", [nbx.NBX_FP64, nbx.NBX_MIXED])
+def test_batch_edge_sizes_and_errors(prec):
+    """Systems at the size limits (1, 2, 63, 64, 65, 127, 128 particles) in one batch, eps2 > 0;
+    a lone particle feels nothing.  Sizes 0 and 129 and a bad first offset are argument errors."""
+    torch = pytest.importorskip("torch")
+    say("batch edge sizes prec=%s" % PREC_NAME[prec])
+    sizes = [1, 2, 63, 64, 65, 127, 128, 1, 128]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    parts = [nbody_ics.plummer(n, seed=20000 + s) for s, n in enumerate(sizes)]
+    m = np.concatenate([p[0] for p in parts])
+    x = np.concatenate([p[1] for p in parts])
+    v = np.concatenate([p[2] for p in parts])
+    eps2 = 1e-4
+    acc_r, jrk_r, pot_r, cond = oracle_batch(off, m, x, v, eps2)
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    n = int(off[-1])
+    acc = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    jrk, pot = torch.empty_like(acc), torch.empty(n, dtype=torch.float64, device=dev)
+    with nbx.Context(order=4, precision=prec, nj_max=1, ni_max=1) as ctx:
+        for bad in ([0, 0, 3], [0, 3, 3 + 129], [1, 4]):
+            with pytest.raises(nbx.NbxError) as e:
+                nbx.nbx_batch_setup(ctx.ctx, np.array(bad, dtype=np.int32))
+            assert e.value.code == nbx.NBX_ERR_ARG
+        nbx.nbx_batch_setup(ctx.ctx, off)
+        nbx.nbx_batch_force_dev(ctx.ctx, None, T(m), T(x), T(v), eps2, acc, jrk, pot)
+        nbx.nbx_sync(ctx.ctx, None)
+        torch.cuda.synchronize()
+        a, p = acc.cpu().numpy(), pot.cpu().numpy()
+    lone = off[:-1][np.array(sizes) == 1]
+    assert np.all(a[lone] == 0.0) and np.all(p[lone] == 0.0)
+    live = np.setdiff1d(np.arange(n), lone)
+    e_cond = np.linalg.norm(a[live] - acc_r[live], axis=1) / cond[live]
+    e_pot = np.abs(p[live] - pot_r[live]) / np.abs(pot_r[live])
+    tol = 1e-13 if prec == nbx.NBX_FP64 else 1e-6
+    say("  acc/cond %.2e pot %.2e" % (e_cond.max(), e_pot.max()))
+    assert e_cond.max() <= tol and e_pot.max() <= tol
