@@ -576,10 +576,32 @@ __device__ __forceinline__ void group_reduce(int gs, double (&v)[P][K], uint64_t
 }
 
 // ---------------------------------------------------------------------------------------------
-// Final write of one sink: results, nearest neighbour id and its exact FP64 |r|^2.
+// Exact FP64 |r|^2 between sink q and source idx (inf when idx is no source): the sink is its own
+// predicted source addr, or its explicit position.  Same predictor as the staging, so the value
+// is the one the oracle computes from the predicted positions.
 // ---------------------------------------------------------------------------------------------
 template <int Order>
-__device__ void finalize_sink(const ForceParams &fp, int q, const double *v, int idx) {
+__device__ double nn_exact_r2(const ForceParams &fp, int q, int addr, int idx) {
+  if (idx < 0 || idx >= fp.nj) return __builtin_huge_val();
+  double xi[3], vi[3], ai[3], mi, xj[3], vj[3], aj[3], mj;
+  if (fp.ext_x) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) xi[k] = fp.ext_x[3 * (size_t)q + k];
+  } else {
+    predict_addr<Order>(fp.src, addr, fp.t, xi, vi, ai, mi);
+  }
+  predict_addr<Order>(fp.src, idx, fp.t, xj, vj, aj, mj);
+  {
+#pragma clang fp contract(off)
+    const double dx = xj[0] - xi[0], dy = xj[1] - xi[1], dz = xj[2] - xi[2];
+    return dx * dx + dy * dy + dz * dz;
+  }
+}
+
+// Final write of one sink: results, nearest neighbour id and its exact FP64 |r|^2 (r2 given by
+// the split that found the neighbour, or computed here when r2 is null).
+template <int Order>
+__device__ void finalize_sink(const ForceParams &fp, int q, const double *v, int idx, const double *r2) {
   const bool ext = fp.ext_x != nullptr;
   const int addr = ext ? -1 : fp.i_addr[q];
   if (!ext && (addr < 0 || addr >= fp.nj)) {
@@ -594,22 +616,8 @@ __device__ void finalize_sink(const ForceParams &fp, int q, const double *v, int
   }
   fp.pot[q] = v[kPotSlot<Order>];
   if (idx >= 0 && idx < fp.nj) {
-    double xi[3], vi[3], ai[3], mi, xj[3], vj[3], aj[3], mj;
-    if (ext) {
-#pragma unroll
-      for (int k = 0; k < 3; ++k) xi[k] = fp.ext_x[3 * (size_t)q + k];
-    } else {
-      predict_addr<Order>(fp.src, addr, fp.t, xi, vi, ai, mi);
-    }
-    predict_addr<Order>(fp.src, idx, fp.t, xj, vj, aj, mj);
-    double r2;
-    {
-#pragma clang fp contract(off)
-      const double dx = xj[0] - xi[0], dy = xj[1] - xi[1], dz = xj[2] - xi[2];
-      r2 = dx * dx + dy * dy + dz * dz;
-    }
     fp.nn_id[q] = fp.src.id[idx];
-    fp.nn_r2[q] = r2;
+    fp.nn_r2[q] = r2 ? *r2 : nn_exact_r2<Order>(fp, q, addr, idx);
   } else {
     fp.nn_id[q] = -1;
     fp.nn_r2[q] = __builtin_huge_val();
@@ -838,7 +846,7 @@ __global__ __launch_bounds__(kThreads) void k_force(const ForceParams fp) {
     if (slot == 0) {
 #pragma unroll
       for (int p = 0; p < P; ++p)
-        if (q[p] < fp.ni) finalize_sink<Order>(fp, q[p], v[p], ii[p]);
+        if (q[p] < fp.ni) finalize_sink<Order>(fp, q[p], v[p], ii[p], nullptr);
     }
     return;
   }
@@ -858,11 +866,13 @@ __global__ __launch_bounds__(kThreads) void k_force(const ForceParams fp) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// Combine kernel for S > 1: R = 2^rlog threads per sink (R >= S when S <= 256); thread r of a
-// sink sums partials s = r, r + R, ... in order, then a butterfly over the R threads.  The sum
-// order depends only on S and R, so results are bit-reproducible.  The paper merged this step
-// into the gravity kernel with atomics (Methods > Other differences); on this multi-XCD part
-// the device-scope fence each workgroup would need costs more than a second launch.
+// Combine kernel for S > 1: R = 2^rlog threads per sink (<= 256 for few sinks, else <= 64: one
+// wave); thread r of a sink sums partials s = r, r + R, ... in order, then a butterfly over the R
+// threads (through LDS when R > 64).  The sum order
+// depends only on S and R, so results are bit-reproducible.  The nearest neighbour is the best
+// (key, address) over the splits; the final write predicts the pair for its exact |r|^2.  The paper merged this step into
+// the gravity kernel with atomics (Methods > Other differences); on this multi-XCD part the
+// device-scope fence each workgroup would need costs more than a second launch.
 // ---------------------------------------------------------------------------------------------
 template <int Order>
 __global__ __launch_bounds__(kThreads) void k_combine(const ForceParams fp, int rlog) {
@@ -879,6 +889,7 @@ __global__ __launch_bounds__(kThreads) void k_combine(const ForceParams fp, int 
 #pragma unroll
   for (int k = 0; k < K; ++k) w[0][k] = 0.0;
   if (qg < fp.ni) {
+#pragma unroll 4
     for (int s = r; s < S; s += R) {
 #pragma unroll
       for (int k = 0; k < K; ++k) w[0][k] += fp.part[((size_t)s * K + k) * fp.ni + qg];
@@ -898,7 +909,7 @@ __global__ __launch_bounds__(kThreads) void k_combine(const ForceParams fp, int 
       return;
     }
   }
-  finalize_sink<Order>(fp, qg, w[0], wi[0]);
+  finalize_sink<Order>(fp, qg, w[0], wi[0], nullptr);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1372,8 +1383,11 @@ static hipError_t launch_force_t(const ForceParams &fp, const LaunchShape &ls, h
     e = hipGetLastError();
   }
   if (e != hipSuccess || ls.splits <= 1) return e;
+  // few sinks: up to 256 threads per sink, so that each loads few partials (latency); many sinks:
+  // at most 64, so that the reduction stays inside a wave (no LDS round)
+  const int rcap = fp.ni <= 256 ? 8 : 6;
   int rlog = 0;
-  while ((1 << rlog) < ls.splits && rlog < 8) ++rlog;
+  while ((1 << rlog) < ls.splits && rlog < rcap) ++rlog;
   const int W = kThreads >> rlog;
   hipLaunchKernelGGL(k_combine<Order>, dim3((fp.ni + W - 1) / W), dim3(kThreads), 0, stream, fp, rlog);
   return hipGetLastError();
