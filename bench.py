@@ -70,7 +70,7 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true", help="skip the N_i sweep")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
-    ap.add_argument("--sweep-reps", type=int, default=5)
+    ap.add_argument("--sweep-reps", type=int, default=5, help="minimum timed steps per sweep point")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the launch-shape tuner (nbx_tune) and its tuned N_i sweep")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -153,6 +153,15 @@ def timed(torch, nbx, ctx, w, ni, stream, steps, warmup):
     t1 = time.perf_counter()
     kern = sum(e0.elapsed_time(e1) for e0, e1 in evs) / steps * 1e-3
     return (t1 - t0) / steps, kern
+
+
+def timed_sweep(torch, nbx, ctx, w, ni, stream, min_reps, budget_s=0.02):
+    """timed() for one sweep point: warm up for ~budget/4 (at least 2 steps) so that the clocks have
+    settled after the previous point, then time enough steps for ~budget of force-kernel time."""
+    _, k = timed(torch, nbx, ctx, w, ni, stream, 2, 1)
+    warm = max(0, int(0.25 * budget_s / k) - 3)
+    reps = max(min_reps, min(400, int(budget_s / k)))
+    return timed(torch, nbx, ctx, w, ni, stream, reps, warm)
 
 
 def cpu_baseline(src, seconds):
@@ -466,45 +475,52 @@ def main():
     print("bench: fp64 N_i=N", file=sys.stderr, flush=True)
     sec64, kern64 = timed(torch, nbx, ctx, w, N, stream, max(3, args.steps // 4), 1)
 
-    def shape_str(ni):
-        sh = ctx.launch_shape(ni)
+    def shape_str(cx, ni):
+        sh = cx.launch_shape(ni)
         return "L%d P%d S%d wg%d" % (sh["lanes_per_sink"], sh["sinks_per_lane"], sh["splits"], sh["workgroups"])
+
+    def time_row(cx, row, ni, suffix):
+        for prec, name in ((nbx.NBX_FP64, "fp64"), (nbx.NBX_MIXED, "mixed")):
+            cx.set_precision(prec)
+            row[name + suffix + "_shape"] = shape_str(cx, ni)
+            s, k = timed_sweep(torch, nbx, cx, w, ni, stream, args.sweep_reps)
+            row[name + suffix + "_kernel_ms"] = round(k * 1e3, 5)
+            if not suffix:
+                row[name + "_step_ms"] = round(s * 1e3, 5)
+            row[name + suffix + "_int_s"] = float("%.4g" % (ni * float(N) / k))
+        row[suffix.lstrip("_") + ("_" if suffix else "") + "speedup"] = round(
+            row["fp64" + suffix + "_kernel_ms"] / row["mixed" + suffix + "_kernel_ms"], 3)
 
     sweep, tune_s = [], None
     if not args.no_sweep:
-        # static launch-shape rule
-        for e in range(18):
-            ni = 1 << e
-            row = {"ni": ni, "shape": shape_str(ni)}
-            for prec, name in ((nbx.NBX_FP64, "fp64"), (nbx.NBX_MIXED, "mixed")):
-                ctx.set_precision(prec)
-                s, k = timed(torch, nbx, ctx, w, ni, stream, args.sweep_reps, 1)
-                row[name + "_kernel_ms"] = round(k * 1e3, 5)
-                row[name + "_step_ms"] = round(s * 1e3, 5)
-                row[name + "_int_s"] = float("%.4g" % (ni * float(N) / k))
-            row["speedup"] = round(row["fp64_kernel_ms"] / row["mixed_kernel_ms"], 3)
-            sweep.append(row)
-            print("bench: sweep %s" % json.dumps(row), file=sys.stderr, flush=True)
-        # the library's tuner picks a shape per N_i class from timed candidates
+        # a second context on the same sources gets the library's tuner (a shape per N_i class from
+        # timed candidates); each N_i is then timed with the static rule and the tuned shapes back to
+        # back, so that clock drift over the sweep does not bias the comparison
+        ctx_t = None
         if not args.no_tune:
+            ctx_t = nbx.Context(order=4, precision=nbx.NBX_MIXED, nj_max=N, ni_max=N)
+            nbx.nbx_set_j_dev(ctx_t.ctx, stream, N, d["addr"], d["id"], d["m"], d["t"], d["x"], d["v"], d["a"],
+                              d["jerk"])
+            nbx.nbx_set_nj(ctx_t.ctx, N)
             t0 = time.perf_counter()
-            nbx.nbx_predict(ctx.ctx, 0.0)
+            nbx.nbx_predict(ctx_t.ctx, 0.0)
             for prec in (nbx.NBX_MIXED, nbx.NBX_FP64):
-                ctx.set_precision(prec)
-                ctx.tune(N)
+                ctx_t.set_precision(prec)
+                ctx_t.tune(N)
+            nbx.nbx_sync(ctx_t.ctx, stream)
             tune_s = time.perf_counter() - t0
             print("bench: tuned launch shapes in %.1f s" % tune_s, file=sys.stderr, flush=True)
-            for row in sweep:
-                ni = row["ni"]
-                for prec, name in ((nbx.NBX_FP64, "fp64"), (nbx.NBX_MIXED, "mixed")):
-                    ctx.set_precision(prec)
-                    row[name + "_tuned_shape"] = shape_str(ni)
-                    s, k = timed(torch, nbx, ctx, w, ni, stream, args.sweep_reps, 1)
-                    row[name + "_tuned_kernel_ms"] = round(k * 1e3, 5)
-                    row[name + "_tuned_int_s"] = float("%.4g" % (ni * float(N) / k))
-                row["tuned_speedup"] = round(row["fp64_tuned_kernel_ms"] / row["mixed_tuned_kernel_ms"], 3)
-                print("bench: tuned sweep %s" % json.dumps({k: v for k, v in row.items() if "tuned" in k or k == "ni"}),
-                      file=sys.stderr, flush=True)
+        for e in range(18):
+            ni = 1 << e
+            row = {"ni": ni}
+            time_row(ctx, row, ni, "")
+            if ctx_t is not None:
+                time_row(ctx_t, row, ni, "_tuned")
+            sweep.append(row)
+            print("bench: sweep %s" % json.dumps(row), file=sys.stderr, flush=True)
+        if ctx_t is not None:
+            nbx.nbx_sync(ctx_t.ctx, stream)
+            ctx_t.close()
     nbx.nbx_sync(ctx.ctx, stream)
     ctx.close()
 

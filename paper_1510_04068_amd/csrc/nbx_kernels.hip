@@ -1323,7 +1323,7 @@ static int ilog2(int v) {
   return l;
 }
 
-LaunchShape choose_shape(int ni, int nj_pad) {
+LaunchShape choose_shape(int ni, int nj_pad, int prec) {
   LaunchShape ls;
   const int ntiles = nj_pad / kTile > 0 ? nj_pad / kTile : 1;
   const int target = ni >= 16384 ? 4096 : 2048;
@@ -1348,7 +1348,8 @@ LaunchShape choose_shape(int ni, int nj_pad) {
   int qmin = 1;
   while (qmin < ni && qmin < 16) qmin *= 2;
   int qcover = 1;  // never more sink slots than the next power of two of ni
-  const int qtop = ni >= 65536 ? 2 * kThreads : kThreads;
+  // two sinks per lane pay off only in FP32 arithmetic (FP64 accumulators double the registers)
+  const int qtop = ni >= 65536 && prec == NBX_MIXED ? 2 * kThreads : kThreads;
   while (qcover < ni && qcover < qtop) qcover *= 2;
   int Q = qcover > qmin ? qcover : qmin;
   for (; Q >= qmin; Q /= 2) {
