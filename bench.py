@@ -87,6 +87,9 @@ def parse():
     ap.add_argument("--blockstep", type=str, default="", metavar="N,N,...",
                     help="also run the 6th-order block time-step Hermite integrator for one N-body time unit "
                          "(eta4=0.01, eta6=0.1, eps2=1e-6) on Plummer spheres of these sizes, FP64 and mixed")
+    ap.add_argument("--blockstep4", type=str, default="", metavar="N,N,...",
+                    help="also run the 4th-order block time-step Hermite integrator (Aarseth criterion, eta4=0.01, "
+                         "eps2=1e-6) for one N-body time unit on Plummer spheres of these sizes, FP64 and mixed")
     ap.add_argument("--order6", action="store_true",
                     help="also time 6th-order forces with neighbour lists on a 1048576-body Plummer/Salpeter "
                          "cluster (eps2=1e-8, h2=1e-4, at most 256 neighbours), N_i in {1024, 65536, 1048576}")
@@ -294,16 +297,17 @@ def order2(torch, nbx, ics, dev, steps):
             "flops_per_interaction": FLOPS_2ND, "rows": rows}
 
 
-def blockstep(torch, nbx, ics, sizes, tune=True):
-    """6th-order block time-step runs, one N-body time unit, FP64 (DP) and mixed (DS): wall time from
-    the start to the end of the integration, energy error, block steps and mean N_active."""
+def blockstep(torch, nbx, ics, sizes, tune=True, order=6):
+    """Block time-step runs (6th order by default; 4th order with the Aarseth criterion), one N-body
+    time unit, FP64 (DP) and mixed (DS): wall time from the start to the end of the integration,
+    energy error, block steps and mean N_active."""
     import numpy as np
 
     rows = []
     for n in sizes:
         m, x, v = ics.plummer(n, seed=7)
         for prec, name in ((nbx.NBX_FP64, "fp64"), (nbx.NBX_MIXED, "mixed")):
-            ctx = nbx.Context(order=6, precision=prec, nj_max=n, ni_max=n)
+            ctx = nbx.Context(order=order, precision=prec, nj_max=n, ni_max=n)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             nbx.nbx_bs_init(ctx.ctx, np.arange(n), m, x, v, BS_EPS2, eta4=0.01, eta6=0.1, eta_start=BS_ETA_START)
@@ -314,9 +318,8 @@ def blockstep(torch, nbx, ics, sizes, tune=True):
             t1 = time.perf_counter()
             for k in range(1, 9):  # one time unit in eighths, with a progress line each
                 st = nbx.nbx_bs_run(ctx.ctx, k / 8.0)
-                print("bench: blockstep n=%d %s t=%g blocks=%d status=%d" % (n, name, st["t"], st["block_steps"],
-                                                                            st["status"]), file=sys.stderr,
-                      flush=True)
+                print("bench: blockstep order %d n=%d %s t=%g blocks=%d status=%d" % (
+                    order, n, name, st["t"], st["block_steps"], st["status"]), file=sys.stderr, flush=True)
                 if st["status"] != nbx.NBX_OK:
                     break
             t2 = time.perf_counter()
@@ -330,9 +333,11 @@ def blockstep(torch, nbx, ics, sizes, tune=True):
                    "interactions_per_s": float("%.4g" % (st["particle_steps"] * float(n) / (t2 - t1)))}
             rows.append(row)
             print("bench: blockstep %s" % json.dumps(row), file=sys.stderr, flush=True)
-    return {"workload": "Plummer spheres (seed 7), 6th-order Hermite block time steps, averaged Aarseth/6th-order "
-                        "criterion eta4=0.01 eta6=0.1, first step %g |a|/|j|, eps2=%g, dt_max=1/8, one N-body time "
-                        "unit" % (BS_ETA_START, BS_EPS2),
+    crit = ("averaged Aarseth/6th-order criterion eta4=0.01 eta6=0.1" if order == 6 else
+            "Aarseth criterion eta4=0.01")
+    return {"workload": "Plummer spheres (seed 7), %s-order Hermite block time steps, %s, first step %g |a|/|j|, "
+                        "eps2=%g, dt_max=1/8, one N-body time unit" % ("6th" if order == 6 else "4th", crit,
+                                                                      BS_ETA_START, BS_EPS2),
             "rows": rows}
 
 
@@ -527,6 +532,8 @@ def main():
     o2 = order2(torch, nbx, nbody_ics, dev, max(3, args.steps // 2)) if args.order2 else None
     bsr = (blockstep(torch, nbx, nbody_ics, [int(k) for k in args.blockstep.split(",")], tune=not args.no_tune)
            if args.blockstep else None)
+    bs4 = (blockstep(torch, nbx, nbody_ics, [int(k) for k in args.blockstep4.split(",")], tune=not args.no_tune,
+                     order=4) if args.blockstep4 else None)
     o6 = order6(torch, nbx, nbody_ics, dev, max(2, args.steps // 10)) if args.order6 else None
     bt = batch(torch, nbx, nbody_ics, dev, max(20, args.steps)) if args.batch else None
     adj = adjoint(torch, nbx, nbody_ics, dev, max(3, args.steps // 5)) if args.adjoint else None
@@ -584,6 +591,8 @@ def main():
         line["order2"] = o2
     if bsr is not None:
         line["blockstep"] = bsr
+    if bs4 is not None:
+        line["blockstep4"] = bs4
     if o6 is not None:
         line["order6"] = o6
     if bt is not None:

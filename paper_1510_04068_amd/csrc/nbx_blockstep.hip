@@ -147,6 +147,9 @@ template <int Order>
 __global__ __launch_bounds__(kThreads) void k_bs_correct(BlockStepParams bp, int ni, double t1) {
   const int k = blockIdx.x * kThreads + threadIdx.x;
   if (k >= ni) return;
+  const int i = bp.list[k];
+  BsState st;
+  bs_load_state<Order>(bp, i, st);
   double a1[3], j1[3], s1[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -154,7 +157,7 @@ __global__ __launch_bounds__(kThreads) void k_bs_correct(BlockStepParams bp, int
     j1[c] = bp.jrk[3 * (size_t)k + c];
     if constexpr (Order == 6) s1[c] = bp.snp[3 * (size_t)k + c];
   }
-  bs_correct_particle<Order>(bp, bp.list[k], t1, a1, j1, s1);
+  bs_correct_particle<Order>(bp, i, st, t1, a1, j1, s1);
 }
 
 // Start: particles at t = 0 with no derivatives yet; list = 0..n-1.

@@ -38,15 +38,27 @@ __device__ __forceinline__ double safe_ratio(double num, double den, double big)
   return den > 0.0 ? num / den : big;
 }
 
-// Correct particle i, whose forces at t1 are a1, j1 (and s1 for order 6): Hermite corrector,
-// interpolated higher derivatives, step criterion and quantisation; the state at t1 is written
-// back into the source arrays.  Called by k_bs_correct and, fused, by the split-combine kernel.
-template <int Order>
-__device__ inline void bs_correct_particle(const BlockStepParams &bp, int i, double t1, const double a1[3],
-                                           const double j1[3], const double s1[3]) {
+// State of particle i at the start of its step: the source record and the step.
+struct BsState {
   Raw r;
-  load_raw<Order>(bp.src, i, r);
-  const double dt = bp.dt[i];
+  double dt;
+};
+
+template <int Order>
+__device__ __forceinline__ void bs_load_state(const BlockStepParams &bp, int i, BsState &st) {
+  load_raw<Order>(bp.src, i, st.r);
+  st.dt = bp.dt[i];
+}
+
+// Correct particle i, whose state at t0 is st and whose forces at t1 are a1, j1 (and s1 for
+// order 6): Hermite corrector, interpolated higher derivatives, step criterion and quantisation;
+// the state at t1 is written back into the source arrays.  Called by k_bs_correct and, fused, by
+// the split-combine kernel (which loads st before it sums the partial forces).
+template <int Order>
+__device__ inline void bs_correct_particle(const BlockStepParams &bp, int i, const BsState &st, double t1,
+                                           const double a1[3], const double j1[3], const double s1[3]) {
+  const Raw &r = st.r;
+  const double dt = st.dt;
   const double h = 0.5 * dt;
   const double h2 = h * h;
   double x1[3], v1[3];

@@ -888,6 +888,16 @@ __global__ __launch_bounds__(kThreads) void k_combine(const ForceParams fp, int 
   int wi[1] = {-1};
 #pragma unroll
   for (int k = 0; k < K; ++k) w[0][k] = 0.0;
+  // block time-step: the particle's state at t0 is loaded first, so that its latency overlaps the
+  // loads of the partials
+  BsState st;
+  int bs_i = -1;
+  if constexpr (Order != 2) {
+    if (fp.bs_fuse && r == 0 && qg < fp.ni) {
+      bs_i = fp.bs.list[qg];
+      bs_load_state<Order>(fp.bs, bs_i, st);
+    }
+  }
   if (qg < fp.ni) {
 #pragma unroll 4
     for (int s = r; s < S; s += R) {
@@ -905,7 +915,7 @@ __global__ __launch_bounds__(kThreads) void k_combine(const ForceParams fp, int 
   if (r != 0 || qg >= fp.ni) return;
   if constexpr (Order != 2) {
     if (fp.bs_fuse) {  // block time-step: correct the particle right away
-      bs_correct_particle<Order>(fp.bs, fp.bs.list[qg], fp.bs_t1, &w[0][0], &w[0][3], Order == 6 ? &w[0][7] : &w[0][0]);
+      bs_correct_particle<Order>(fp.bs, bs_i, st, fp.bs_t1, &w[0][0], &w[0][3], Order == 6 ? &w[0][7] : &w[0][0]);
       return;
     }
   }

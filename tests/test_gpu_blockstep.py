@@ -161,3 +161,32 @@ def test_blockstep_error_paths():
         with pytest.raises(nbx.NbxError) as e:
             nbx.nbx_bs_step(ctx.ctx, 1.0)
         assert e.value.code == nbx.NBX_ERR_STATE
+
+
+def test_blockstep_large_n_schedule():
+    """40000 particles: 40 workgroups schedule each block step (per-chunk minima, then a compaction
+    that reserves list slots with one atomic add per chunk, in arrival order); the run keeps the
+    block-step invariants and conserves energy."""
+    n, eps2, t_end = 40000, 1e-6, 2.0**-7
+    say("blockstep order=4 fp64 n=%d t_end=%g seed=66" % (n, t_end))
+    m, x, v = nbody_ics.plummer(n, seed=66)
+    with nbx.Context(order=4, precision=nbx.NBX_FP64, nj_max=n, ni_max=n) as ctx:
+        nbx.nbx_bs_init(ctx.ctx, np.arange(n), m, x, v, eps2)
+        e0 = sum(nbx.nbx_bs_energy(ctx.ctx))
+        st = nbx.nbx_bs_run(ctx.ctx, t_end)
+        state = nbx.nbx_bs_get_state(ctx.ctx, n)
+        e1 = sum(nbx.nbx_bs_energy(ctx.ctx))
+        nbx.nbx_sync(ctx.ctx)
+    de = abs((e1 - e0) / e0)
+    say("  status %d blocks %d particle steps %d min dt 2^%d dE/E %.2e" % (
+        st["status"], st["block_steps"], st["particle_steps"], int(np.log2(state["dt"].min())), de))
+    assert st["status"] == nbx.NBX_OK and st["t"] == t_end
+    dt, ti = state["dt"], state["t_i"]
+    lv = np.log2(dt)
+    assert np.all(lv == np.round(lv)) and np.all(dt <= 0.125)
+    assert np.all(np.fmod(ti, dt) == 0.0)
+    assert np.all(ti <= t_end) and np.all(ti + dt > t_end)
+    assert st["block_steps"] > 1 and st["particle_steps"] >= n
+    # sanity bound only (a particle dropped from or repeated in a block breaks the invariants above
+    # first): 4th order, eta4 = 0.01, eps = 1e-3, steps down to ~2^-15 in the core
+    assert de < 1e-6
