@@ -48,8 +48,8 @@
  *   NBX_FP64   every operation in IEEE double.
  *   NBX_MIXED  predictor in FP64; positions split into double-single
  *              (hi = fl32(x), lo = fl32(x - hi)) and differenced as
- *              (hi_j - hi_i) + (lo_j - lo_i); everything else in FP32 with
- *              compensated (TwoSum) accumulation.  Results are FP64 arrays.
+ *              (hi_j - hi_i) + (lo_j - lo_i); everything else in FP32, with
+ *              FP32 chunk sums folded into FP64 totals.  Results are FP64 arrays.
  *
  * Conventions shared by every entry point:
  *   - Return value: NBX_OK (0), a negative NBX_ERR_* code, or a positive

@@ -27,8 +27,8 @@
 //   MIXED: dx = (xh_j - xh_i) + (xl_j - xl_i) in FP32 from double-single positions, FP32
 //          velocities/masses, R^-1 straight from v_rsq_f32 (a Newton step measured no better
 //          in the median, 2x better only in the worst sink, for 10% of the issue slots), FP32
-//          chunk sums folded into (hi, lo) TwoSum pairs (acceleration every 16 terms, the rest
-//          every 64).  FP32 add/mul/fma issue at twice the FP64 rate on gfx950.
+//          chunk sums folded into FP64 totals (acceleration every 16 terms, the rest every 64).
+//          FP32 add/mul/fma issue at twice the FP64 rate on gfx950.
 //   FP64:  all IEEE double; R^-1 from v_rsq_f64 plus one third-order Newton correction; FP64
 //          chunk sums folded with TwoSum.
 // Self-interaction (by-address sinks): a sink and its own source copy are predicted by the same
@@ -50,14 +50,16 @@
 
 namespace nbx {
 
-constexpr int kChunkAcc = 16;  // acceleration terms summed in plain FP32/FP64 before a TwoSum fold
+constexpr int kChunkAcc = 16;  // acceleration terms summed in plain FP32/FP64 before a fold
 constexpr int kChunk = 64;     // same for jerk, pot and snap (a multiple of kChunkAcc)
 
 // ---------------------------------------------------------------------------------------------
-// Compensated accumulation: K running values, each a plain chunk sum plus a (hi, lo) pair that
-// absorbs the chunk with TwoSum (Knuth).  The acceleration (values 0..2) is folded every
-// kChunkAcc terms, the other values every kChunk terms: the summation error of a chunk grows with
-// its length, and the acceleration carries the tightest bound.
+// Compensated accumulation: K running values, each a plain chunk sum that is folded every
+// kChunkAcc terms (the acceleration, values 0..2) or kChunk terms (the others) into a running
+// total: the summation error of a chunk grows with its length, and the acceleration carries the
+// tightest bound.  FP64 chunks fold into a (hi, lo) pair with TwoSum (Knuth), i.e. a double-double
+// total; FP32 chunks fold into an FP64 total (a convert and an FP64 add, cheaper in issue slots
+// than a single-single TwoSum and more accurate).
 // ---------------------------------------------------------------------------------------------
 template <typename T, int K>
 struct Comp {
@@ -79,6 +81,29 @@ struct Comp {
       part[k] = T(0);
     }
   }
+  __device__ __forceinline__ double value(int k) const { return (double)hi[k] + (double)lo[k]; }
+};
+
+template <int K>
+struct Comp<float, K> {
+  float part[K];
+  double sum[K];
+  __device__ __forceinline__ void init() {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      part[k] = 0.0f;
+      sum[k] = 0.0;
+    }
+  }
+  template <int K0, int K1>
+  __device__ __forceinline__ void fold() {
+#pragma unroll
+    for (int k = K0; k < K1; ++k) {
+      sum[k] += (double)part[k];
+      part[k] = 0.0f;
+    }
+  }
+  __device__ __forceinline__ double value(int k) const { return sum[k]; }
 };
 
 // value slots: 0..2 acc, 3..5 jerk, 6 pot, 7..9 snap (order 2: 0..2 acc, 3 pot)
@@ -836,7 +861,7 @@ __global__ __launch_bounds__(kThreads) void k_force(const ForceParams fp) {
 #pragma unroll
   for (int p = 0; p < P; ++p) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[p][k] = (double)acc[p].hi[k] + (double)acc[p].lo[k];
+    for (int k = 0; k < K; ++k) v[p][k] = acc[p].value(k);
     kk[p] = (uint64_t)nnk[p];
     ii[p] = nn_rescan<Tr, Order>(fp, tiles[(t1 - 1 - t0) & 1], t1 - 1, sink[p], nnk[p], nng[p], lg, self[p]);
   }
@@ -977,7 +1002,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchParams bp) {
       uint64_t wk[1] = {0};
       int wi[1] = {0};
 #pragma unroll
-      for (int k = 0; k < K; ++k) w[0][k] = (double)acc.hi[k] + (double)acc.lo[k];
+      for (int k = 0; k < K; ++k) w[0][k] = acc.value(k);
       group_reduce<1, K>(L, w, wk, wi, red_unused);  // L <= 64: shuffles only
       if (slot == 0 && live) {
         const size_t q = (size_t)(b + i);
@@ -1128,8 +1153,8 @@ __global__ __launch_bounds__(kThreads) void k_vjp(const VjpParams vp) {
   double g[7];
   const double mp = P.m;
 #pragma unroll
-  for (int k = 0; k < 6; ++k) g[k] = (double)acc.hi[k] + (double)acc.lo[k] + mp * ((double)acc.hi[7 + k] + (double)acc.lo[7 + k]);
-  g[6] = (double)acc.hi[6] + (double)acc.lo[6];
+  for (int k = 0; k < 6; ++k) g[k] = acc.value(k) + mp * acc.value(7 + k);
+  g[6] = acc.value(6);
   if (p >= vp.n) return;
   if (S == 1) {
 #pragma unroll
