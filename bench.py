@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-sweep", action="store_true", help="skip the N_i sweep")
+    ap.add_argument("--no-e2e", action="store_true",
+                    help="skip the end-to-end host-path timing (transfers included) at five N_i")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     ap.add_argument("--sweep-reps", type=int, default=5, help="minimum timed steps per sweep point")
@@ -143,28 +145,65 @@ def step(nbx, ctx, w, ni, stream, ev=None):
         ev[1].record(stream)
 
 
-def timed(torch, nbx, ctx, w, ni, stream, steps, warmup):
-    """Returns (seconds per step, mean force-kernel seconds per launch)."""
+def timed(torch, nbx, ctx, w, ni, stream, steps, warmup, times=None, flush=None):
+    """Returns (seconds per step, mean force-kernel seconds per launch); `times` (a list) receives
+    every launch's seconds.  With `flush` (a large device tensor) each step first overwrites it,
+    which evicts the sources from L2 and the MALL, so the launch reads them from HBM."""
     for _ in range(warmup):
         step(nbx, ctx, w, ni, stream)
     torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     t0 = time.perf_counter()
     for k in range(steps):
+        if flush is not None:
+            flush.fill_(float(k))
         step(nbx, ctx, w, ni, stream, evs[k])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kern = sum(e0.elapsed_time(e1) for e0, e1 in evs) / steps * 1e-3
-    return (t1 - t0) / steps, kern
+    ks = [e0.elapsed_time(e1) * 1e-3 for e0, e1 in evs]
+    if times is not None:
+        times.extend(ks)
+    return (t1 - t0) / steps, sum(ks) / steps
 
 
-def timed_sweep(torch, nbx, ctx, w, ni, stream, min_reps, budget_s=0.02):
+def timed_sweep(torch, nbx, ctx, w, ni, stream, min_reps, budget_s=0.02, times=None):
     """timed() for one sweep point: warm up for ~budget/4 (at least 2 steps) so that the clocks have
     settled after the previous point, then time enough steps for ~budget of force-kernel time."""
     _, k = timed(torch, nbx, ctx, w, ni, stream, 2, 1)
     warm = max(0, int(0.25 * budget_s / k) - 3)
     reps = max(min_reps, min(400, int(budget_s / k)))
-    return timed(torch, nbx, ctx, w, ni, stream, reps, warm)
+    return timed(torch, nbx, ctx, w, ni, stream, reps, warm, times=times)
+
+
+def end_to_end(nbx, ics, src, prec, ni_list, reps):
+    """The host-pointer path with its transfers (the scope of the paper's timings that include
+    PCIe): per step nbx_set_j of the ni updated sources from host arrays, nbx_predict, nbx_force
+    with host sink addresses, nbx_get_force back to host arrays; wall time per step."""
+    import numpy as np
+
+    rows = []
+    with nbx.Context(order=4, precision=prec, nj_max=N, ni_max=N) as ctx:
+        ctx.set_sources(src)
+        for ni in ni_list:
+            sel = ics.active_set(N, ni, seed=1002)
+            arrs = [np.ascontiguousarray(a[sel]) for a in (src.ids, src.m, src.t, src.x, src.v, src.a, src.jerk)]
+
+            def go():
+                nbx.nbx_set_j(ctx.ctx, sel, *arrs)
+                nbx.nbx_predict(ctx.ctx, 0.0)
+                nbx.nbx_force(ctx.ctx, sel, EPS2)
+                return nbx.nbx_get_force(ctx.ctx, ni)
+
+            for _ in range(3):
+                go()
+            n_rep = max(3, min(reps, int(0.2 / max(1e-6, 1e-9 * ni * N))))
+            t0 = time.perf_counter()
+            for _ in range(n_rep):
+                go()
+            dt = (time.perf_counter() - t0) / n_rep
+            rows.append({"ni": ni, "ms": round(dt * 1e3, 4), "int_s": float("%.4g" % (ni * float(N) / dt))})
+    return rows
+
 
 
 def cpu_baseline(src, seconds):
@@ -193,7 +232,14 @@ def cpu_baseline(src, seconds):
     # so this runs last)
     ns1 = max(16, int(ns / max(cores, 1) / 5))
     dt1 = run(ns1, nthreads=1)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": ns * N / dt, "unit": "interactions/s", "cores": cores, "kind": "oracle",
+            "host": {"cpu": model, "nproc": os.cpu_count()},
             "sample": "FP64 oracle, predictor on all %d sources + acc/jerk/pot/NN of %d seeded random sinks "
                       "against all %d sources (%.2e interactions, %.1f s)" % (N, ns, N, ns * float(N), dt),
             "single_thread": {"value": ns1 * N / dt1, "cores": 1,
@@ -495,9 +541,14 @@ def main():
         for prec, name in ((nbx.NBX_FP64, "fp64"), (nbx.NBX_MIXED, "mixed")):
             cx.set_precision(prec)
             row[name + suffix + "_shape"] = shape_str(cx, ni)
-            s, k = timed_sweep(torch, nbx, cx, w, ni, stream, args.sweep_reps)
+            ts = []
+            s, k = timed_sweep(torch, nbx, cx, w, ni, stream, args.sweep_reps, times=ts)
             row[name + suffix + "_kernel_ms"] = round(k * 1e3, 5)
             if not suffix:
+                ts.sort()
+                row[name + "_kernel_ms_median"] = round(ts[len(ts) // 2] * 1e3, 5)
+                row[name + "_kernel_ms_min"] = round(ts[0] * 1e3, 5)
+                row[name + "_reps"] = len(ts)
                 row[name + "_step_ms"] = round(s * 1e3, 5)
             row[name + suffix + "_int_s"] = float("%.4g" % (ni * float(N) / k))
         row[suffix.lstrip("_") + ("_" if suffix else "") + "speedup"] = round(
@@ -533,8 +584,31 @@ def main():
         if ctx_t is not None:
             nbx.nbx_sync(ctx_t.ctx, stream)
             ctx_t.close()
+        # the sweep runs with the sources warm in L2 / the 256 MB MALL; small N_i read them from
+        # HBM when a 512 MiB write precedes every launch
+        flush = torch.empty(1 << 26, dtype=torch.float64, device=dev)
+        for row in sweep:
+            if row["ni"] not in (1, 64, 1024):
+                continue
+            for prec, name in ((nbx.NBX_FP64, "fp64"), (nbx.NBX_MIXED, "mixed")):
+                ctx.set_precision(prec)
+                ts = []
+                timed(torch, nbx, ctx, w, row["ni"], stream, 50, 5, times=ts, flush=flush)
+                ts.sort()
+                row[name + "_flushed_kernel_ms_median"] = round(ts[len(ts) // 2] * 1e3, 5)
+            print("bench: flushed %s" % json.dumps({k: v for k, v in row.items() if "flushed" in k or k == "ni"}),
+                  file=sys.stderr, flush=True)
+        del flush
     nbx.nbx_sync(ctx.ctx, stream)
     ctx.close()
+
+    e2e = None
+    if not args.no_e2e:
+        e2e = {"scope": "host arrays: nbx_set_j of the N_i updated sources, nbx_predict, nbx_force with host "
+                        "sink addresses, nbx_get_force to host arrays; wall time per step", "rows": {}}
+        for prec, name in ((nbx.NBX_FP64, "fp64"), (nbx.NBX_MIXED, "mixed")):
+            e2e["rows"][name] = end_to_end(nbx, nbody_ics, w.src, prec, (1, 64, 1024, 16384, N), 50)
+            print("bench: end-to-end %s %s" % (name, json.dumps(e2e["rows"][name])), file=sys.stderr, flush=True)
 
     o2 = order2(torch, nbx, nbody_ics, dev, max(3, args.steps // 2)) if args.order2 else None
     bsr = (blockstep(torch, nbx, nbody_ics, [int(k) for k in args.blockstep.split(",")], tune=not args.no_tune)
@@ -596,6 +670,8 @@ def main():
     }
     if o2 is not None:
         line["order2"] = o2
+    if e2e is not None:
+        line["end_to_end"] = e2e
     if bsr is not None:
         line["blockstep"] = bsr
     if bs4 is not None:
