@@ -132,7 +132,9 @@ int nbx_set_nj(nbx_ctx *ctx, int nj);
  * (NULL for order 4).  Order 2: v and a may be NULL (taken as zero) and jerk is ignored (may be
  * NULL); the predictor uses x + v dt + a dt^2/2.  Every addr must be in [0, nj_max) (else
  * NBX_ERR_ARG, nothing copied); the number of sources in use grows to cover the highest address
- * written.  Synchronous. */
+ * written.  The host arrays are read before the call returns (packed into pinned staging memory
+ * and moved in one copy); the scatter into the source arrays is enqueued on the context's stream
+ * and ordered before every later call on the context. */
 int nbx_set_j(nbx_ctx *ctx, int n, const int32_t *addr, const int64_t *id, const double *m,
               const double *t, const double *x, const double *v, const double *a,
               const double *jerk, const double *snap, const double *crackle);
@@ -157,7 +159,10 @@ int nbx_force_ext(nbx_ctx *ctx, int ni, const int64_t *id, const double *x, cons
 
 /* Wait for the last nbx_force / nbx_force_ext and copy its results to caller-owned host arrays:
  * acc, jerk [ni][3] (orders 4, 6; never written for order 2), snap [ni][3] (order 6), pot [ni],
- * nn_id [ni], nn_r2 [ni].  Any pointer may be NULL to skip that output.  Returns NBX_WARN_NBR_OVERFLOW if a neighbour list overflowed. */
+ * nn_id [ni], nn_r2 [ni].  Any pointer may be NULL to skip that output.  The results and the
+ * error counters come back in one copy.  Returns NBX_WARN_NBR_OVERFLOW if a neighbour list
+ * overflowed, NBX_ERR_ARG if an address was out of range in a copy or force call since the last
+ * check. */
 int nbx_get_force(nbx_ctx *ctx, double *acc, double *jerk, double *snap, double *pot,
                   int64_t *nn_id, double *nn_r2);
 

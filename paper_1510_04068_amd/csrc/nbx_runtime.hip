@@ -32,6 +32,21 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// Pinned host staging for the host-pointer path: host arrays are packed into it with memcpy and
+// move in one asynchronous copy; `ev` marks the end of the last copy that used it.
+struct Pinned {
+  void *h = nullptr;
+  size_t bytes = 0;
+  hipEvent_t ev = nullptr;
+  bool pending = false;
+};
+
+constexpr size_t kErrDoubles = 8;  // the error counters head the output block (64 bytes)
+// Host transfers up to this size go through pinned staging (one copy, no per-array overhead);
+// larger ones copy straight from / to the caller's pageable arrays, which the runtime pipelines
+// better than a host memcpy followed by one DMA.
+constexpr size_t kStageMax = size_t(1) << 20;
+
 }  // namespace
 
 struct nbx_ctx {
@@ -48,13 +63,19 @@ struct nbx_ctx {
   int64_t *d_ext_id = nullptr;
   double *d_ext_x = nullptr, *d_ext_v = nullptr, *d_ext_a = nullptr;
   int32_t *d_ext_self = nullptr;
+  // results of the last host-path force call, laid out for its ni in one block behind the error
+  // counters (d_out), so that nbx_get_force moves counters and results in one copy
+  double *d_out = nullptr;
+  size_t out_doubles = 0;
   double *d_acc = nullptr, *d_jrk = nullptr, *d_snp = nullptr, *d_pot = nullptr, *d_nnr2 = nullptr;
   int64_t *d_nnid = nullptr;
+  Pinned stage_j, stage_i, stage_out;  // staging of nbx_set_j, of the sink inputs, of the results
   int32_t *d_nbr_cnt = nullptr;
   int64_t *d_nbr_ids = nullptr;
   // split-combine scratch
   DevBuf part, part_key, part_idx;
   int *d_err = nullptr;  // [0] bad sink address, [1] bad source address, [2] nbr overflow, [3] dt clamped
+                         // (the first 16 bytes of d_out)
   // set_j staging (host path), grown on demand
   DevBuf up;
   int up_cap = 0;
@@ -162,6 +183,66 @@ int ensure_scratch(nbx_ctx *c, int ni, const LaunchShape &ls) {
   rc = grow(c, c->part_key, n * sizeof(uint64_t));
   if (rc) return rc;
   return grow(c, c->part_idx, n * sizeof(int32_t));
+}
+
+// Wait until the last copy through the staging buffer has finished, then make it hold `bytes`.
+int pinned_acquire(nbx_ctx *c, Pinned &p, size_t bytes) {
+  if (p.pending) {
+    HIP_TRY(c, hipEventSynchronize(p.ev));
+    p.pending = false;
+  }
+  if (!p.ev) HIP_TRY(c, hipEventCreateWithFlags(&p.ev, hipEventDisableTiming));
+  if (p.bytes < bytes) {
+    if (p.h) (void)hipHostFree(p.h);
+    p.h = nullptr;
+    p.bytes = 0;
+    const size_t nb = (bytes + 65535) / 65536 * 65536;
+    void *h = nullptr;
+    HIP_TRY(c, hipHostMalloc(&h, nb, hipHostMallocDefault));
+    p.h = h;
+    p.bytes = nb;
+  }
+  return NBX_OK;
+}
+
+// The copy just enqueued on `s` reads (or writes) the staging buffer.
+int pinned_release(nbx_ctx *c, Pinned &p, hipStream_t s) {
+  HIP_TRY(c, hipEventRecord(p.ev, s));
+  p.pending = true;
+  return NBX_OK;
+}
+
+void pinned_free(Pinned &p) {
+  if (p.ev) (void)hipEventDestroy(p.ev);
+  if (p.h) (void)hipHostFree(p.h);
+  p = Pinned{};
+}
+
+size_t align16(size_t bytes) { return (bytes + 15) / 16 * 16; }
+
+// Point the host-path result arrays at consecutive pieces of d_out for ni sinks.
+void out_layout(nbx_ctx *c, int ni) {
+  const size_t n = (size_t)ni;
+  double *p = c->d_out + kErrDoubles;
+  c->d_acc = p;
+  p += 3 * n;
+  c->d_jrk = nullptr;
+  c->d_snp = nullptr;
+  if (c->cfg.order != 2) {
+    c->d_jrk = p;
+    p += 3 * n;
+  }
+  if (c->cfg.order == 6) {
+    c->d_snp = p;
+    p += 3 * n;
+  }
+  c->d_pot = p;
+  p += n;
+  c->d_nnid = reinterpret_cast<int64_t *>(p);
+  p += n;
+  c->d_nnr2 = p;
+  p += n;
+  c->out_doubles = (size_t)(p - c->d_out);
 }
 
 bool valid_prec(int p) { return p == NBX_FP64 || p == NBX_MIXED; }
@@ -322,10 +403,8 @@ int batch_enqueue(nbx_ctx *c, hipStream_t stream, const double *d_m, const doubl
   return NBX_OK;
 }
 
-// Read and clear the device error counters (stream must be idle).
-int collect_errors(nbx_ctx *c) {
-  int h[4] = {0, 0, 0, 0};
-  HIP_TRY(c, hipMemcpy(h, c->d_err, sizeof h, hipMemcpyDeviceToHost));
+// Status from error counters read back from the device (stream idle); clears them when set.
+int errors_from(nbx_ctx *c, const int h[4]) {
   if (h[0] || h[1] || h[2] || h[3]) {
     HIP_TRY(c, launch_fill_i32(c->d_err, 4, 0, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -338,6 +417,13 @@ int collect_errors(nbx_ctx *c) {
     return NBX_WARN_DT_MIN;
   }
   return NBX_OK;
+}
+
+// Read and clear the device error counters (stream must be idle).
+int collect_errors(nbx_ctx *c) {
+  int h[4] = {0, 0, 0, 0};
+  HIP_TRY(c, hipMemcpy(h, c->d_err, sizeof h, hipMemcpyDeviceToHost));
+  return errors_from(c, h);
 }
 
 }  // namespace
@@ -395,19 +481,15 @@ int nbx_open(nbx_ctx **out, const nbx_config *cfg) {
   if (cfg->order == 6) rc = rc ? rc : alloc_n(c, &c->src.snp_crk, 6 * nj);
   rc = rc ? rc : alloc_n(c, &c->src.id, nj);
   rc = rc ? rc : alloc_n(c, &c->d_iaddr, ni);
-  rc = rc ? rc : alloc_n(c, &c->d_acc, 3 * ni);
-  if (cfg->order != 2) rc = rc ? rc : alloc_n(c, &c->d_jrk, 3 * ni);
-  if (cfg->order == 6) rc = rc ? rc : alloc_n(c, &c->d_snp, 3 * ni);
-  rc = rc ? rc : alloc_n(c, &c->d_pot, ni);
-  rc = rc ? rc : alloc_n(c, &c->d_nnid, ni);
-  rc = rc ? rc : alloc_n(c, &c->d_nnr2, ni);
+  rc = rc ? rc : alloc_n(c, &c->d_out, kErrDoubles + 12 * ni);
   if (cfg->nbr_max > 0) {
     rc = rc ? rc : alloc_n(c, &c->d_h2, ni);
     rc = rc ? rc : alloc_n(c, &c->d_nbr_cnt, ni);
     rc = rc ? rc : alloc_n(c, &c->d_nbr_ids, ni * (size_t)cfg->nbr_max);
   }
-  rc = rc ? rc : alloc_n(c, &c->d_err, 4);
   if (rc) return bail(rc);
+  c->d_err = reinterpret_cast<int *>(c->d_out);
+  out_layout(c, cfg->ni_max);
   hipError_t e = launch_pad(cfg->order, c->src, 0, cfg->nj_max, c->stream);
   if (e == hipSuccess) e = launch_fill_i32(c->d_err, 4, 0, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -422,6 +504,9 @@ int nbx_close(nbx_ctx *c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (void *p : c->owned) (void)hipFree(p);
   if (c->bs.h_sched) (void)hipHostFree(c->bs.h_sched);
+  pinned_free(c->stage_j);
+  pinned_free(c->stage_i);
+  pinned_free(c->stage_out);
   if (c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
   return NBX_OK;
@@ -463,36 +548,52 @@ int nbx_set_j(nbx_ctx *c, int n, const int32_t *addr, const int64_t *id, const d
       return fail(c, NBX_ERR_ARG, "addr[%d]=%d outside [0, %d)", k, addr[k], c->cfg.nj_max);
     hi = std::max(hi, addr[k]);
   }
-  // staging layout: addr | id | m | t | x v a [jerk [snap crackle]]
+  // device staging layout (16-byte aligned pieces): addr | id | m | t | x v a [jerk [snap crackle]],
+  // then the copy kernel scatters them.  Small updates are packed into pinned memory and move in
+  // one copy, and nothing waits: later work on the context stream is ordered after the scatter.
   const size_t nv = six ? 6 : (two ? 3 : 4);
-  const size_t bytes = (size_t)n * (4 + 8 + 8 + 8 + nv * 24) + 256;
-  if (int rc = grow(c, c->up, bytes)) return rc;
-  char *base = static_cast<char *>(c->up.p);
-  int32_t *d_addr = reinterpret_cast<int32_t *>(base);
-  size_t off = ((size_t)n * 4 + 15) / 16 * 16;
-  int64_t *d_id = reinterpret_cast<int64_t *>(base + off);
-  off += (size_t)n * 8;
-  double *d_m = reinterpret_cast<double *>(base + off);
-  off += (size_t)n * 8;
-  double *d_t = reinterpret_cast<double *>(base + off);
-  off += (size_t)n * 8;
-  double *d_vec[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  const size_t N = (size_t)n;
   const double *h_vec[6] = {x, v, a, jerk, snap, crackle};
+  size_t off_vec[6] = {0, 0, 0, 0, 0, 0};
+  const size_t off_id = align16(N * 4), off_m = off_id + align16(N * 8), off_t = off_m + align16(N * 8);
+  size_t bytes = off_t + align16(N * 8);
   for (size_t k = 0; k < nv; ++k) {
     if (!h_vec[k]) continue;  // optional for order 2 (v, a): the copy kernel takes NULL as zero
-    d_vec[k] = reinterpret_cast<double *>(base + off);
-    off += (size_t)n * 24;
+    off_vec[k] = bytes;
+    bytes += align16(N * 24);
   }
+  if (int rc = grow(c, c->up, bytes)) return rc;
   hipStream_t s = c->stream;
-  HIP_TRY(c, hipMemcpyAsync(d_addr, addr, (size_t)n * 4, hipMemcpyHostToDevice, s));
-  HIP_TRY(c, hipMemcpyAsync(d_id, id, (size_t)n * 8, hipMemcpyHostToDevice, s));
-  HIP_TRY(c, hipMemcpyAsync(d_m, m, (size_t)n * 8, hipMemcpyHostToDevice, s));
-  HIP_TRY(c, hipMemcpyAsync(d_t, t, (size_t)n * 8, hipMemcpyHostToDevice, s));
+  char *base = static_cast<char *>(c->up.p);
+  const bool staged = bytes <= kStageMax;
+  if (staged) {
+    if (int rc = pinned_acquire(c, c->stage_j, bytes)) return rc;
+    char *h = static_cast<char *>(c->stage_j.h);
+    std::memcpy(h, addr, N * 4);
+    std::memcpy(h + off_id, id, N * 8);
+    std::memcpy(h + off_m, m, N * 8);
+    std::memcpy(h + off_t, t, N * 8);
+    for (size_t k = 0; k < nv; ++k)
+      if (h_vec[k]) std::memcpy(h + off_vec[k], h_vec[k], N * 24);
+    HIP_TRY(c, hipMemcpyAsync(base, h, bytes, hipMemcpyHostToDevice, s));
+    if (int rc = pinned_release(c, c->stage_j, s)) return rc;
+  } else {
+    HIP_TRY(c, hipMemcpyAsync(base, addr, N * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(base + off_id, id, N * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(base + off_m, m, N * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(base + off_t, t, N * 8, hipMemcpyHostToDevice, s));
+    for (size_t k = 0; k < nv; ++k)
+      if (h_vec[k]) HIP_TRY(c, hipMemcpyAsync(base + off_vec[k], h_vec[k], N * 24, hipMemcpyHostToDevice, s));
+  }
+  const double *d_vec[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   for (size_t k = 0; k < nv; ++k)
-    if (d_vec[k]) HIP_TRY(c, hipMemcpyAsync(d_vec[k], h_vec[k], (size_t)n * 24, hipMemcpyHostToDevice, s));
-  HIP_TRY(c, launch_jupdate(c->cfg.order, c->src, c->cfg.nj_max, n, d_addr, d_id, d_m, d_t, d_vec[0], d_vec[1],
-                            d_vec[2], d_vec[3], d_vec[4], d_vec[5], c->d_err, s));
-  HIP_TRY(c, hipStreamSynchronize(s));
+    if (h_vec[k]) d_vec[k] = reinterpret_cast<const double *>(base + off_vec[k]);
+  HIP_TRY(c, launch_jupdate(c->cfg.order, c->src, c->cfg.nj_max, n, reinterpret_cast<const int32_t *>(base),
+                            reinterpret_cast<const int64_t *>(base + off_id),
+                            reinterpret_cast<const double *>(base + off_m),
+                            reinterpret_cast<const double *>(base + off_t), d_vec[0], d_vec[1], d_vec[2], d_vec[3],
+                            d_vec[4], d_vec[5], c->d_err, s));
+  if (!staged) HIP_TRY(c, hipStreamSynchronize(s));  // the caller's arrays have been read
   c->nj = std::max(c->nj, hi + 1);
   c->bs.ready = false;  // the block time-step state lives in the same arrays
   return NBX_OK;
@@ -515,8 +616,23 @@ int nbx_force(nbx_ctx *c, int ni, const int32_t *i_addr, double eps2, const doub
     if (i_addr[k] < 0 || i_addr[k] >= c->nj)
       return fail(c, NBX_ERR_ARG, "i_addr[%d]=%d outside [0, nj=%d)", k, i_addr[k], c->nj);
   if (h2 && c->cfg.nbr_max == 0) return fail(c, NBX_ERR_ARG, "neighbour lists need nbr_max > 0");
-  if (ni > 0) HIP_TRY(c, hipMemcpyAsync(c->d_iaddr, i_addr, (size_t)ni * 4, hipMemcpyHostToDevice, c->stream));
-  if (ni > 0 && h2) HIP_TRY(c, hipMemcpyAsync(c->d_h2, h2, (size_t)ni * 8, hipMemcpyHostToDevice, c->stream));
+  const size_t n_i = (size_t)ni, off_h2_i = align16(n_i * 4);
+  if (ni > 0 && off_h2_i + (h2 ? n_i * 8 : 0) > kStageMax) {  // large: straight from the caller's arrays
+    HIP_TRY(c, hipMemcpyAsync(c->d_iaddr, i_addr, n_i * 4, hipMemcpyHostToDevice, c->stream));
+    if (h2) HIP_TRY(c, hipMemcpyAsync(c->d_h2, h2, n_i * 8, hipMemcpyHostToDevice, c->stream));
+  } else if (ni > 0) {  // small: addresses (and radii) through the pinned staging buffer
+    const size_t n = n_i, off_h2 = off_h2_i;
+    if (int rc = pinned_acquire(c, c->stage_i, off_h2 + (h2 ? n * 8 : 0))) return rc;
+    char *h = static_cast<char *>(c->stage_i.h);
+    std::memcpy(h, i_addr, n * 4);
+    HIP_TRY(c, hipMemcpyAsync(c->d_iaddr, h, n * 4, hipMemcpyHostToDevice, c->stream));
+    if (h2) {
+      std::memcpy(h + off_h2, h2, n * 8);
+      HIP_TRY(c, hipMemcpyAsync(c->d_h2, h + off_h2, n * 8, hipMemcpyHostToDevice, c->stream));
+    }
+    if (int rc = pinned_release(c, c->stage_i, c->stream)) return rc;
+  }
+  out_layout(c, ni);
   int rc = enqueue_force(c, c->stream, ni, c->d_iaddr, nullptr, nullptr, nullptr, nullptr, nullptr, eps2,
                          h2 ? c->d_h2 : nullptr, c->d_acc, c->d_jrk, c->d_snp, c->d_pot, c->d_nnid, c->d_nnr2,
                          c->d_nbr_cnt, c->d_nbr_ids);
@@ -545,14 +661,39 @@ int nbx_force_ext(nbx_ctx *c, int ni, const int64_t *id, const double *x, const 
   }
   const size_t n = (size_t)ni;
   hipStream_t s = c->stream;
-  if (ni > 0) {
+  const bool hv = c->cfg.order != 2, ha = c->cfg.order == 6;
+  const size_t off_x = align16(n * 8), off_v = off_x + align16(n * 24), off_a = off_v + (hv ? align16(n * 24) : 0);
+  const size_t off_h2 = off_a + (ha ? align16(n * 24) : 0), bytes = off_h2 + (h2 ? n * 8 : 0);
+  if (ni > 0 && bytes > kStageMax) {  // large: straight from the caller's arrays
     HIP_TRY(c, hipMemcpyAsync(c->d_ext_id, id, n * 8, hipMemcpyHostToDevice, s));
     HIP_TRY(c, hipMemcpyAsync(c->d_ext_x, x, n * 24, hipMemcpyHostToDevice, s));
-    if (c->cfg.order != 2) HIP_TRY(c, hipMemcpyAsync(c->d_ext_v, v, n * 24, hipMemcpyHostToDevice, s));
-    if (c->cfg.order == 6) HIP_TRY(c, hipMemcpyAsync(c->d_ext_a, a, n * 24, hipMemcpyHostToDevice, s));
+    if (hv) HIP_TRY(c, hipMemcpyAsync(c->d_ext_v, v, n * 24, hipMemcpyHostToDevice, s));
+    if (ha) HIP_TRY(c, hipMemcpyAsync(c->d_ext_a, a, n * 24, hipMemcpyHostToDevice, s));
     if (h2) HIP_TRY(c, hipMemcpyAsync(c->d_h2, h2, n * 8, hipMemcpyHostToDevice, s));
     if (c->predicted) HIP_TRY(c, launch_selfmap(c->src, c->nj, ni, c->d_ext_id, c->d_ext_self, s));
+  } else if (ni > 0) {  // small: sink states through the pinned staging buffer: id | x | v | a | h2
+    if (int rc = pinned_acquire(c, c->stage_i, bytes)) return rc;
+    char *h = static_cast<char *>(c->stage_i.h);
+    std::memcpy(h, id, n * 8);
+    std::memcpy(h + off_x, x, n * 24);
+    HIP_TRY(c, hipMemcpyAsync(c->d_ext_id, h, n * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(c->d_ext_x, h + off_x, n * 24, hipMemcpyHostToDevice, s));
+    if (hv) {
+      std::memcpy(h + off_v, v, n * 24);
+      HIP_TRY(c, hipMemcpyAsync(c->d_ext_v, h + off_v, n * 24, hipMemcpyHostToDevice, s));
+    }
+    if (ha) {
+      std::memcpy(h + off_a, a, n * 24);
+      HIP_TRY(c, hipMemcpyAsync(c->d_ext_a, h + off_a, n * 24, hipMemcpyHostToDevice, s));
+    }
+    if (h2) {
+      std::memcpy(h + off_h2, h2, n * 8);
+      HIP_TRY(c, hipMemcpyAsync(c->d_h2, h + off_h2, n * 8, hipMemcpyHostToDevice, s));
+    }
+    if (int rc = pinned_release(c, c->stage_i, s)) return rc;
+    if (c->predicted) HIP_TRY(c, launch_selfmap(c->src, c->nj, ni, c->d_ext_id, c->d_ext_self, s));
   }
+  out_layout(c, ni);
   int rc = enqueue_force(c, s, ni, nullptr, c->d_ext_self, c->d_ext_id, c->d_ext_x, c->d_ext_v,
                          c->cfg.order == 6 ? c->d_ext_a : nullptr, eps2, h2 ? c->d_h2 : nullptr, c->d_acc,
                          c->d_jrk, c->d_snp, c->d_pot, c->d_nnid, c->d_nnr2, c->d_nbr_cnt, c->d_nbr_ids);
@@ -566,17 +707,38 @@ int nbx_get_force(nbx_ctx *c, double *acc, double *jerk, double *snap, double *p
                   double *nn_r2) {
   if (int rc = check_ctx(c)) return rc;
   if (c->last_ni < 0) return fail(c, NBX_ERR_STATE, "nbx_get_force before nbx_force");
+  const size_t bytes = c->out_doubles * sizeof(double);
+  if (bytes > kStageMax) {  // large: straight into the caller's arrays
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const int rc = collect_errors(c);
+    if (rc < 0) return rc;
+    const size_t n = (size_t)c->last_ni;
+    if (acc) HIP_TRY(c, hipMemcpy(acc, c->d_acc, n * 24, hipMemcpyDeviceToHost));
+    if (jerk && c->d_jrk) HIP_TRY(c, hipMemcpy(jerk, c->d_jrk, n * 24, hipMemcpyDeviceToHost));
+    if (snap && c->d_snp) HIP_TRY(c, hipMemcpy(snap, c->d_snp, n * 24, hipMemcpyDeviceToHost));
+    if (pot) HIP_TRY(c, hipMemcpy(pot, c->d_pot, n * 8, hipMemcpyDeviceToHost));
+    if (nn_id) HIP_TRY(c, hipMemcpy(nn_id, c->d_nnid, n * 8, hipMemcpyDeviceToHost));
+    if (nn_r2) HIP_TRY(c, hipMemcpy(nn_r2, c->d_nnr2, n * 8, hipMemcpyDeviceToHost));
+    return rc;
+  }
+  // small: one copy of the error counters and the results (laid out for last_ni by the force call)
+  if (int rc = pinned_acquire(c, c->stage_out, bytes)) return rc;
+  HIP_TRY(c, hipMemcpyAsync(c->stage_out.h, c->d_out, bytes, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  const int rc = collect_errors(c);
+  const char *h = static_cast<const char *>(c->stage_out.h);
+  int err[4];
+  std::memcpy(err, h, sizeof err);
+  const int rc = errors_from(c, err);
   if (rc < 0) return rc;
   const size_t n = (size_t)c->last_ni;
   if (n == 0) return rc;
-  if (acc) HIP_TRY(c, hipMemcpy(acc, c->d_acc, n * 24, hipMemcpyDeviceToHost));
-  if (jerk && c->cfg.order != 2) HIP_TRY(c, hipMemcpy(jerk, c->d_jrk, n * 24, hipMemcpyDeviceToHost));
-  if (snap && c->cfg.order == 6) HIP_TRY(c, hipMemcpy(snap, c->d_snp, n * 24, hipMemcpyDeviceToHost));
-  if (pot) HIP_TRY(c, hipMemcpy(pot, c->d_pot, n * 8, hipMemcpyDeviceToHost));
-  if (nn_id) HIP_TRY(c, hipMemcpy(nn_id, c->d_nnid, n * 8, hipMemcpyDeviceToHost));
-  if (nn_r2) HIP_TRY(c, hipMemcpy(nn_r2, c->d_nnr2, n * 8, hipMemcpyDeviceToHost));
+  auto from = [&](const void *d) { return h + (static_cast<const char *>(d) - reinterpret_cast<const char *>(c->d_out)); };
+  if (acc) std::memcpy(acc, from(c->d_acc), n * 24);
+  if (jerk && c->d_jrk) std::memcpy(jerk, from(c->d_jrk), n * 24);
+  if (snap && c->d_snp) std::memcpy(snap, from(c->d_snp), n * 24);
+  if (pot) std::memcpy(pot, from(c->d_pot), n * 8);
+  if (nn_id) std::memcpy(nn_id, from(c->d_nnid), n * 8);
+  if (nn_r2) std::memcpy(nn_r2, from(c->d_nnr2), n * 8);
   return rc;
 }
 
@@ -1131,7 +1293,9 @@ int nbx_tune(nbx_ctx *c, int ni_max, int32_t *shapes_out, int n_classes) {
     const int ni = std::min(1 << k, ni_max);
     addr.resize(ni);
     for (int i = 0; i < ni; ++i) addr[i] = (int32_t)((int64_t)i * c->nj / ni);  // evenly strided sinks
+    HIP_TRY(c, hipStreamSynchronize(c->stream));  // the previous class's launches read d_iaddr
     HIP_TRY(c, hipMemcpy(c->d_iaddr, addr.data(), (size_t)ni * 4, hipMemcpyHostToDevice));
+    out_layout(c, ni);
     float best_ms = 1e30f;
     nbx_ctx::TunedShape best;
     for (const LaunchShape &cand : tune_candidates(ni, ntiles)) {
