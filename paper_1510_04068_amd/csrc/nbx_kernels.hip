@@ -52,6 +52,7 @@ namespace nbx {
 
 constexpr int kChunkAcc = 16;  // acceleration terms summed in plain FP32/FP64 before a fold
 constexpr int kChunk = 64;     // same for jerk, pot and snap (a multiple of kChunkAcc)
+constexpr int kCombineQ = 16;  // fewest sinks per combine workgroup (when there are that many)
 
 // ---------------------------------------------------------------------------------------------
 // Compensated accumulation: K running values, each a plain chunk sum that is folded every
@@ -891,22 +892,34 @@ __global__ __launch_bounds__(kThreads) void k_force(const ForceParams fp) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// Combine kernel for S > 1: R = 2^rlog threads per sink (<= 256 for few sinks, else <= 64: one
-// wave); thread r of a sink sums partials s = r, r + R, ... in order, then a butterfly over the R
-// threads (through LDS when R > 64).  The sum order
-// depends only on S and R, so results are bit-reproducible.  The nearest neighbour is the best
-// (key, address) over the splits; the final write predicts the pair for its exact |r|^2.  The paper merged this step into
-// the gravity kernel with atomics (Methods > Other differences); on this multi-XCD part the
-// device-scope fence each workgroup would need costs more than a second launch.
+// Combine kernel for S > 1: a workgroup takes W = 2^wlog consecutive sinks with R = 256 / W threads
+// each; thread t serves sink t mod W as its lane r = t / W, so that neighbouring lanes read
+// neighbouring sinks' partials (the partials of one split and value are contiguous over the
+// sinks).  Lane r sums splits s = r, r + R, ... in order; the lanes of a sink inside a wave
+// combine by a butterfly (offsets W .. 32), and the at most four wave partials of a sink in wave
+// order through LDS.  The sum order depends only on S and W, so results are bit-reproducible.
+// The nearest neighbour is the best (key, address) over the splits; the final write predicts the
+// pair for its exact |r|^2.  The paper merged this step into the gravity kernel with atomics
+// (Methods > Other differences); on this multi-XCD part the device-scope fence each workgroup
+// would need costs more than a second launch.
 // ---------------------------------------------------------------------------------------------
+template <int K>
+struct CombineLds {
+  double v[kThreads][K];
+  uint64_t k[kThreads];
+  int i[kThreads];
+};
+
 template <int Order>
-__global__ __launch_bounds__(kThreads) void k_combine(const ForceParams fp, int rlog) {
+__global__ __launch_bounds__(kThreads) void k_combine(const ForceParams fp, int wlog) {
   constexpr int K = kValues<Order>;
-  __shared__ RedLds<1, K> red;
-  const int R = 1 << rlog;
-  const int W = kThreads >> rlog;
-  const int qg = blockIdx.x * W + ((int)threadIdx.x >> rlog);
-  const int r = threadIdx.x & (R - 1);
+  __shared__ CombineLds<K> red;
+  const int t = threadIdx.x;
+  const int W = 1 << wlog;
+  const int R = kThreads >> wlog;
+  const int ql = t & (W - 1);
+  const int r = t >> wlog;
+  const int qg = blockIdx.x * W + ql;
   const int S = fp.splits;
   double w[1][K];
   uint64_t wk[1] = {~0ull};
@@ -936,7 +949,40 @@ __global__ __launch_bounds__(kThreads) void k_combine(const ForceParams fp, int 
       }
     }
   }
-  group_reduce<1, K>(R, w, wk, wi, red);
+  // lanes of one sink inside a wave (W < 64): butterfly over offsets W .. 32; every lane ends
+  // with the same bits
+  for (int off = 32; off >= W; off >>= 1) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) w[0][k] += __shfl_xor(w[0][k], off);
+    const uint64_t ok = __shfl_xor(wk[0], off);
+    const int oi = __shfl_xor(wi[0], off);
+    if (nn_better(ok, oi, wk[0], wi[0])) {
+      wk[0] = ok;
+      wi[0] = oi;
+    }
+  }
+  if (R > 1) {
+    // wave partials of a sink: for W < 64 one per wave at thread 64 w + ql (4 in all); for
+    // W >= 64 lane r sits at thread r W + ql (R <= 4 in all)
+#pragma unroll
+    for (int k = 0; k < K; ++k) red.v[t][k] = w[0][k];
+    red.k[t] = wk[0];
+    red.i[t] = wi[0];
+    __syncthreads();
+    if (r == 0) {
+      const int stride = W < 64 ? 64 : W;
+      const int parts = W < 64 ? kThreads / 64 : R;
+      for (int j = 1; j < parts; ++j) {
+        const int o = j * stride + ql;
+#pragma unroll
+        for (int k = 0; k < K; ++k) w[0][k] += red.v[o][k];
+        if (nn_better(red.k[o], red.i[o], wk[0], wi[0])) {
+          wk[0] = red.k[o];
+          wi[0] = red.i[o];
+        }
+      }
+    }
+  }
   if (r != 0 || qg >= fp.ni) return;
   if constexpr (Order != 2) {
     if (fp.bs_fuse) {  // block time-step: correct the particle right away
@@ -1419,13 +1465,15 @@ static hipError_t launch_force_t(const ForceParams &fp, const LaunchShape &ls, h
     e = hipGetLastError();
   }
   if (e != hipSuccess || ls.splits <= 1) return e;
-  // few sinks: up to 256 threads per sink, so that each loads few partials (latency); many sinks:
-  // at most 64, so that the reduction stays inside a wave (no LDS round)
-  const int rcap = fp.ni <= 256 ? 8 : 6;
+  // threads per sink R = nextpow2(S) (at most 256), but at least min(nextpow2(N_i), kCombineQ)
+  // sinks per workgroup, so that a load instruction covers whole cache lines of partials
+  int qmin = 1;
+  while (qmin < fp.ni && qmin < kCombineQ) qmin *= 2;
   int rlog = 0;
-  while ((1 << rlog) < ls.splits && rlog < rcap) ++rlog;
-  const int W = kThreads >> rlog;
-  hipLaunchKernelGGL(k_combine<Order>, dim3((fp.ni + W - 1) / W), dim3(kThreads), 0, stream, fp, rlog);
+  while ((1 << rlog) < ls.splits && (1 << rlog) < kThreads / qmin) ++rlog;
+  const int wlog = 8 - rlog;
+  const int W = 1 << wlog;
+  hipLaunchKernelGGL(k_combine<Order>, dim3((fp.ni + W - 1) / W), dim3(kThreads), 0, stream, fp, wlog);
   return hipGetLastError();
 }
 
