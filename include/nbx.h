@@ -3,9 +3,11 @@
  *
  * The library is the GPU half of a GRAPE-style direct N-body code, as in
  * Bedorf, Gaburov & Portegies Zwart, "Sapporo2: A versatile direct N-body
- * library" (arXiv:1510.04068).  The host integrator (block time-steps,
- * Hermite corrector, time-step choice) stays with the caller (Background;
- * Results > Block time-step simulations).  One force evaluation is:
+ * library" (arXiv:1510.04068).  In the paper the integrator (block
+ * time-steps, Hermite corrector, time-step choice) stays with the host code
+ * (Background; Results > Block time-step simulations); here it may, or it can
+ * run on the device through the nbx_bs_* entry points below.  One force
+ * evaluation is:
  *
  *   1. nbx_set_j      copy updated sources ("j-particles") into the library
  *                     (the copy kernel of Methods > Other differences);
