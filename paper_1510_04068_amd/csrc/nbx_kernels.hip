@@ -1407,7 +1407,9 @@ static int ilog2(int v) {
 LaunchShape choose_shape(int ni, int nj_pad, int prec) {
   LaunchShape ls;
   const int ntiles = nj_pad / kTile > 0 ? nj_pad / kTile : 1;
-  const int target = ni >= 16384 ? 4096 : 2048;
+  // workgroups to aim for: few sinks take ~512 (two per CU) so that each staged, predicted source
+  // feeds as many sinks as possible; many sinks take more, to even out the last round
+  const int target = ni >= 16384 ? 4096 : (ni >= 256 ? 2048 : 512);
   const int64_t part_cap = (int64_t)1 << 21;
   int scap = (int)(part_cap / (ni > 0 ? ni : 1));
   if (scap > ntiles) scap = ntiles;
