@@ -270,7 +270,7 @@ typedef struct nbx_bs_params {
   double eta6;      /* 6th-order accuracy parameter (the paper: 0.1; order 6 only) */
   double eta_start; /* first-step parameter (e.g. 0.01) */
   double dt_max;    /* largest step, a power of two <= 1 */
-  double dt_min;    /* smallest step, a power of two <= dt_max (smaller requests are clamped) */
+  double dt_min;    /* smallest step, a power of two, 2^-63 <= dt_min <= dt_max (smaller requests are clamped) */
 } nbx_bs_params;
 
 typedef struct nbx_bs_stats {

@@ -8,8 +8,8 @@
 // (the force launch shape depends on N_active).
 //
 // One block step:
-//   1. schedule: t_next = min_i (t_i + dt_i) and the list of the particles with
-//      t_i + dt_i == t_next (k_bs_min, k_bs_list);
+//   1. schedule: t_next = min_i (t_i + dt_i), found from the occupied step levels, and the list
+//      of the particles with t_i + dt_i == t_next (k_bs_list);
 //   2. forces on the active particles at t_next: the gravity kernel (fused predictor);
 //   3. correct, choose the next step and write the new state back into the source arrays
 //      (k_bs_correct, or the split-combine kernel of step 2 when the force launch has splits).
@@ -48,24 +48,7 @@
 
 namespace nbx {
 
-constexpr int kBsPer = kBsChunk / kThreads;  // particles per thread in the scheduling kernels
-
-__device__ __forceinline__ double wave_min(double v) {
-  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
-  return v;
-}
-
-// Minimum over the workgroup, returned to every thread.
-__device__ double block_min(double v, double *red) {
-  v = wave_min(v);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double m = red[0];
-#pragma unroll
-  for (int w = 1; w < kThreads / 64; ++w) m = fmin(m, red[w]);
-  __syncthreads();
-  return m;
-}
+constexpr int kBsPer = kBsChunk / kThreads;  // particles per thread in the scheduling kernel
 
 // Exclusive prefix sum over the workgroup in thread order; *total receives the sum.
 __device__ int block_exclusive_scan(int v, int *red, int *total) {
@@ -89,37 +72,36 @@ __device__ int block_exclusive_scan(int v, int *red, int *total) {
   return before + inc - v;
 }
 
-// 1. per-workgroup minimum of t_i + dt_i over its chunk of kBsChunk particles
-__global__ __launch_bounds__(kThreads) void k_bs_min(BlockStepParams bp) {
-  __shared__ double red[kThreads / 64];
-  const int b0 = blockIdx.x * kBsChunk;
-  double m = __builtin_huge_val();
-#pragma unroll
-  for (int r = 0; r < kBsPer; ++r) {
-    const int i = b0 + r * kThreads + threadIdx.x;
-    if (i < bp.n) m = fmin(m, bp.tnext[i]);
-  }
-  m = block_min(m, red);
-  if (threadIdx.x == 0) {
-    bp.wg_min[blockIdx.x] = m;
-    if (blockIdx.x == 0) bp.sched->count = 0;
-  }
-}
-
-// 2. compaction: every workgroup reduces all partial minima to t_next, collects its active
-//    particles in address order (workgroup prefix scan) and reserves their slots in the list with
-//    one atomic add on the count (zeroed by k_bs_min).  The chunks land in the list in arrival
-//    order; every result of a block step depends only on the set of active particles, not on
-//    their order, because each sink's sum order is fixed by the launch shape.  Workgroup 0
-//    publishes t_next.
-__global__ __launch_bounds__(kThreads) void k_bs_list(BlockStepParams bp) {
-  __shared__ double red[kThreads / 64];
+// Schedule.  Every particle sits on the grid of its own step: t_i is a multiple of dt_i and
+// t_i <= T < t_i + dt_i at the last block time T, so t_i + dt_i is the first multiple of dt_i after
+// T.  The smallest of these belongs to the finest occupied step level kmax (dt = 2^-kmax), so
+// t_next = (floor(T / dt) + 1) dt with no pass over the particles: the per-level counts, kept by
+// the start and corrector kernels, name kmax.  The active particles are those with
+// t_i + dt_i == t_next.  Each workgroup collects its chunk of kBsChunk particles in address order
+// (prefix scan) and reserves their slots in the list with one atomic add on count[parity], which
+// the previous schedule zeroed; the chunks land in the list in arrival order.  Every result of a
+// block step depends only on the set of active particles, not on their order, because each sink's
+// sum order is fixed by the launch shape.  Workgroup 0 publishes t_next and zeroes the other
+// counter for the next schedule.
+__global__ __launch_bounds__(kThreads) void k_bs_list(BlockStepParams bp, double t_now, int parity) {
   __shared__ int redi[kThreads / 64];
   __shared__ int base;
-  const int nwg = gridDim.x;
-  double m = __builtin_huge_val();
-  for (int k = threadIdx.x; k < nwg; k += kThreads) m = fmin(m, bp.wg_min[k]);
-  const double tn = block_min(m, red);
+  __shared__ double tn_sh;
+  if (threadIdx.x < 64) {
+    const bool occ = bp.level_count[threadIdx.x] > 0;
+    const uint64_t m = __ballot(occ);
+    if (threadIdx.x == 0) {
+      double tn = __builtin_huge_val();
+      if (m != 0) {
+        const int kmax = 63 - __clzll(m);
+        const double dt = ldexp(1.0, -kmax);
+        tn = (floor(t_now / dt) + 1.0) * dt;
+      }
+      tn_sh = tn;
+    }
+  }
+  __syncthreads();
+  const double tn = tn_sh;
   // thread t owns the kBsPer consecutive particles b0 + t*kBsPer ... (address order = thread order)
   const int i0 = blockIdx.x * kBsChunk + threadIdx.x * kBsPer;
   bool act[kBsPer];
@@ -133,8 +115,11 @@ __global__ __launch_bounds__(kThreads) void k_bs_list(BlockStepParams bp) {
   int total = 0;
   const int pos0 = block_exclusive_scan(mine, redi, &total);
   if (threadIdx.x == 0) {
-    base = total > 0 ? atomicAdd(&bp.sched->count, total) : 0;
-    if (blockIdx.x == 0) bp.sched->t_next = tn;
+    base = total > 0 ? atomicAdd(&bp.sched->count[parity], total) : 0;
+    if (blockIdx.x == 0) {
+      bp.sched->t_next = tn;
+      bp.sched->count[parity ^ 1] = 0;
+    }
   }
   __syncthreads();
   int pos = base + pos0;
@@ -179,7 +164,11 @@ __global__ __launch_bounds__(kThreads) void k_bs_load(BlockStepParams bp, const 
   }
   bp.src.id[i] = id[i];
   bp.list[i] = i;
-  if (i == 0) bp.sched->clamped = 0;
+  if (i == 0) {
+    bp.sched->t_next = 0.0;
+    bp.sched->count[0] = bp.sched->count[1] = 0;
+    bp.sched->clamped = 0;
+  }
 }
 
 // Start, after a force pass on every particle (row i = particle i): store a and j (the 6th-order
@@ -226,6 +215,7 @@ __global__ __launch_bounds__(kThreads) void k_bs_start(BlockStepParams bp) {
   }
   bp.dt[i] = dn;
   bp.tnext[i] = dn;
+  atomicAdd(&bp.level_count[bs_level(dn)], 1);
 }
 
 __global__ __launch_bounds__(kThreads) void k_iota(int32_t *p, int n) {
@@ -243,10 +233,9 @@ hipError_t launch_iota(int32_t *p, int n, hipStream_t stream) {
 
 int bs_groups(int n) { return (n + kBsChunk - 1) / kBsChunk; }
 
-hipError_t launch_bs_schedule(const BlockStepParams &bp, hipStream_t stream) {
+hipError_t launch_bs_schedule(const BlockStepParams &bp, double t_now, int parity, hipStream_t stream) {
   const int g = bs_groups(bp.n);
-  hipLaunchKernelGGL(k_bs_min, dim3(g), dim3(kThreads), 0, stream, bp);
-  hipLaunchKernelGGL(k_bs_list, dim3(g), dim3(kThreads), 0, stream, bp);
+  hipLaunchKernelGGL(k_bs_list, dim3(g), dim3(kThreads), 0, stream, bp, t_now, parity);
   return hipGetLastError();
 }
 

@@ -11,6 +11,11 @@ namespace nbx {
 
 __device__ __forceinline__ double norm3(const double v[3]) { return sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); }
 
+// Step level k of a power-of-two step dt = 2^-k (0 <= k < kBsLevels), from the exponent bits.
+__device__ __forceinline__ int bs_level(double dt) {
+  return 1023 - (int)((__double_as_longlong(dt) >> 52) & 0x7ff);
+}
+
 // A step clamped at dt_min (or a criterion that is not a number): counted for the host.
 __device__ inline void report_clamp(const BlockStepParams &bp) {
   atomicAdd(&bp.err[3], 1);
@@ -99,6 +104,10 @@ __device__ inline void bs_correct_particle(const BlockStepParams &bp, int i, con
     crit = 0.5 * (crit + dt6);
   }
   const double dn = quantise(crit, dt, t1, bp);
+  if (dn != dt) {  // the particle changes step level
+    atomicAdd(&bp.level_count[bs_level(dt)], -1);
+    atomicAdd(&bp.level_count[bs_level(dn)], 1);
+  }
   bp.src.pos_mass[i] = make_double4(x1[0], x1[1], x1[2], r.m);
   bp.src.vel_time[i] = make_double4(v1[0], v1[1], v1[2], t1);
   double *aj = bp.src.acc_jrk + 6 * (size_t)i;

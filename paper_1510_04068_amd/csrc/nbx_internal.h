@@ -35,11 +35,13 @@ struct SourceArrays {
 
 // Block time-step integrator (device resident).  The particle state is the source arrays; the
 // force rows acc/jrk/snp are those of the active list (row k = particle list[k]).
-constexpr int kBsChunk = 4 * kThreads;  // particles per workgroup in the scheduling kernels
+constexpr int kBsChunk = 4 * kThreads;  // particles per workgroup in the scheduling kernel
+constexpr int kBsLevels = 64;            // step levels k, dt = 2^-k (dt_min >= 2^-63)
 struct BsSched {
   double t_next;  // next block time
-  int count;      // active particles at t_next
+  int count[2];   // active particles at t_next; schedules alternate between the two counters
   int clamped;    // steps clamped at dt_min (or with a criterion that is not a number) since the start
+  int pad;
 };
 struct BlockStepParams {
   SourceArrays src;
@@ -48,7 +50,7 @@ struct BlockStepParams {
   double *dt;       // [n] current step of each particle (power of two)
   double *tnext;    // [n] t_i + dt_i
   int32_t *list;    // [n] active particles of the current block step (address order within chunks)
-  double *wg_min;   // [groups] partial minima of tnext
+  int *level_count;  // [kBsLevels] particles per step level k (dt = 2^-k)
   BsSched *sched;
   const double *acc, *jrk, *snp;  // forces of the active list at the block time
   int *err;                       // [3]: steps clamped at dt_min or criteria that were not numbers
@@ -159,7 +161,8 @@ hipError_t launch_selfmap(const SourceArrays &src, int nj, int ni, const int64_t
 
 // Block time-step kernels (defined in nbx_blockstep.hip).
 int bs_groups(int n);
-hipError_t launch_bs_schedule(const BlockStepParams &bp, hipStream_t stream);
+// Schedules the block step after the last block time t_now, counting into sched->count[parity].
+hipError_t launch_bs_schedule(const BlockStepParams &bp, double t_now, int parity, hipStream_t stream);
 hipError_t launch_bs_correct(int order, const BlockStepParams &bp, int ni, double t1, hipStream_t stream);
 hipError_t launch_bs_load(int order, const BlockStepParams &bp, const int64_t *id, const double *m, const double *x,
                           const double *v, hipStream_t stream);

@@ -92,7 +92,8 @@ struct nbx_ctx {
     nbx_bs_params p{};
     double t = 0.0;
     int64_t blocks = 0, steps = 0;
-    DevBuf dt, tnext, list, acc, jrk, snp, pot, nnid, nnr2, wg_min, sched;
+    DevBuf dt, tnext, list, acc, jrk, snp, pot, nnid, nnr2, level_count, sched;
+    int parity = 0;  // counter of the next schedule
     BsSched *h_sched = nullptr;  // pinned host copy of the schedule
   } bs;
   // launch-shape tables from nbx_tune, per precision: per N_i class k (ni in (2^(k-1), 2^k]),
@@ -1004,7 +1005,7 @@ BlockStepParams bs_params(nbx_ctx *c) {
   bp.dt = static_cast<double *>(c->bs.dt.p);
   bp.tnext = static_cast<double *>(c->bs.tnext.p);
   bp.list = static_cast<int32_t *>(c->bs.list.p);
-  bp.wg_min = static_cast<double *>(c->bs.wg_min.p);
+  bp.level_count = static_cast<int *>(c->bs.level_count.p);
   bp.sched = static_cast<BsSched *>(c->bs.sched.p);
   bp.acc = static_cast<const double *>(c->bs.acc.p);
   bp.jrk = static_cast<const double *>(c->bs.jrk.p);
@@ -1028,11 +1029,13 @@ int bs_force(nbx_ctx *c, int ni, double t, const BlockStepParams *step = nullptr
 // Schedule the next block step; returns (t_next, count, clamped so far) through the pinned copy.
 int bs_schedule(nbx_ctx *c, double *t_next, int *count, int *clamped) {
   const BlockStepParams bp = bs_params(c);
-  HIP_TRY(c, launch_bs_schedule(bp, c->stream));
+  const int parity = c->bs.parity;
+  HIP_TRY(c, launch_bs_schedule(bp, c->bs.t, parity, c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->bs.h_sched, bp.sched, sizeof(BsSched), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->bs.parity = parity ^ 1;
   *t_next = c->bs.h_sched->t_next;
-  *count = c->bs.h_sched->count;
+  *count = c->bs.h_sched->count[parity];
   *clamped = c->bs.h_sched->clamped;
   return NBX_OK;
 }
@@ -1056,10 +1059,12 @@ int nbx_bs_init(nbx_ctx *c, int n, const int64_t *id, const double *m, const dou
     return fail(c, NBX_ERR_CAPACITY, "n=%d exceeds nj_max=%d or ni_max=%d", n, c->cfg.nj_max, c->cfg.ni_max);
   if (!(p->eps2 >= 0.0) || !(p->eta4 > 0.0) || !(p->eta_start > 0.0) || (c->cfg.order == 6 && !(p->eta6 > 0.0)))
     return fail(c, NBX_ERR_ARG, "need eps2 >= 0 and positive eta4, eta_start (and eta6 for order 6)");
-  if (!pow2(p->dt_max) || !pow2(p->dt_min) || p->dt_min > p->dt_max)
-    return fail(c, NBX_ERR_ARG, "dt_max and dt_min must be powers of two with dt_min <= dt_max <= 1");
+  if (!pow2(p->dt_max) || !pow2(p->dt_min) || p->dt_min > p->dt_max ||
+      p->dt_min < std::ldexp(1.0, -(kBsLevels - 1)))
+    return fail(c, NBX_ERR_ARG, "dt_max and dt_min must be powers of two with 2^-%d <= dt_min <= dt_max <= 1",
+                kBsLevels - 1);
   c->bs.ready = false;
-  const size_t N = (size_t)n, G = (size_t)bs_groups(n);
+  const size_t N = (size_t)n;
   int rc = NBX_OK;
   rc = rc ? rc : grow(c, c->bs.dt, N * 8);
   rc = rc ? rc : grow(c, c->bs.tnext, N * 8);
@@ -1070,7 +1075,7 @@ int nbx_bs_init(nbx_ctx *c, int n, const int64_t *id, const double *m, const dou
   rc = rc ? rc : grow(c, c->bs.pot, N * 8);
   rc = rc ? rc : grow(c, c->bs.nnid, N * 8);
   rc = rc ? rc : grow(c, c->bs.nnr2, N * 8);
-  rc = rc ? rc : grow(c, c->bs.wg_min, G * 8);
+  rc = rc ? rc : grow(c, c->bs.level_count, kBsLevels * sizeof(int));
   rc = rc ? rc : grow(c, c->bs.sched, sizeof(BsSched));
   rc = rc ? rc : grow(c, c->up, N * (8 + 8 + 24 + 24) + 256);
   if (rc) return rc;
@@ -1082,6 +1087,7 @@ int nbx_bs_init(nbx_ctx *c, int n, const int64_t *id, const double *m, const dou
   c->bs.n = n;
   c->bs.p = *p;
   c->bs.t = 0.0;
+  c->bs.parity = 0;
   c->bs.blocks = c->bs.steps = 0;
   c->nj = n;
   char *base = static_cast<char *>(c->up.p);
@@ -1095,6 +1101,7 @@ int nbx_bs_init(nbx_ctx *c, int n, const int64_t *id, const double *m, const dou
   HIP_TRY(c, hipMemcpyAsync(d_x, x, N * 24, hipMemcpyHostToDevice, s));
   HIP_TRY(c, hipMemcpyAsync(d_v, v, N * 24, hipMemcpyHostToDevice, s));
   const BlockStepParams bp = bs_params(c);
+  HIP_TRY(c, launch_fill_i32(bp.level_count, kBsLevels, 0, s));  // counted by the start kernel
   HIP_TRY(c, launch_bs_load(c->cfg.order, bp, d_id, d_m, d_x, d_v, s));
   // acc and jerk at t = 0; order 6 needs a second pass for the snap, which uses the accelerations
   if ((rc = bs_force(c, n, 0.0))) return rc;

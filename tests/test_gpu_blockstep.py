@@ -154,6 +154,9 @@ def test_blockstep_error_paths():
         with pytest.raises(nbx.NbxError) as e:
             nbx.nbx_bs_init(ctx.ctx, src.ids, src.m, src.x, src.v, 1e-4, dt_max=0.1)
         assert e.value.code == nbx.NBX_ERR_ARG
+        with pytest.raises(nbx.NbxError) as e:  # below the finest step level
+            nbx.nbx_bs_init(ctx.ctx, src.ids, src.m, src.x, src.v, 1e-4, dt_min=2.0**-64)
+        assert e.value.code == nbx.NBX_ERR_ARG
         nbx.nbx_bs_init(ctx.ctx, src.ids, src.m, src.x, src.v, 1e-4)
         assert nbx.nbx_bs_step(ctx.ctx, 1.0)[0] > 0
         assert nbx.nbx_bs_step(ctx.ctx, 0.0)[0] == 0  # nothing due by t_end = 0
