@@ -103,7 +103,7 @@ struct ForceParams {
 constexpr int kBatchMax = 128;  // largest system of a batch
 struct BatchParams {
   int n_items;
-  const int2 *items;
+  const int4 *items;  // (system, lanes_log2, first sink, end sink), the costliest first
   const int32_t *offset;
   const double *m;
   const double *x;

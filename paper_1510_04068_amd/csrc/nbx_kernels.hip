@@ -1014,9 +1014,10 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchParams bp) {
   const int nwaves = gridDim.x * (kThreads / 64);
   const T eps2 = (T)bp.eps2;
   for (int it = blockIdx.x * (kThreads / 64) + wslot; it < bp.n_items; it += nwaves) {
-    const int2 item = bp.items[it];  // (system, lanes_log2)
+    const int4 item = bp.items[it];  // (system, lanes_log2, first sink, end sink)
     const int b = bp.offset[item.x];
     const int n = bp.offset[item.x + 1] - b;
+    const int s_end = item.w < n ? item.w : n;
     const double zero[3] = {0.0, 0.0, 0.0};
     for (int k = lane; k < n; k += 64) {
       double x[3], v[3];
@@ -1031,10 +1032,10 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchParams bp) {
     __builtin_amdgcn_wave_barrier();
     const int lg = item.y;
     const int L = 1 << lg;
-    for (int base = 0; base < n; base += 64 >> lg) {
+    for (int base = item.z; base < s_end; base += 64 >> lg) {
       const int i = base + (lane >> lg);
       const int slot = lane & (L - 1);
-      const bool live = i < n;
+      const bool live = i < s_end;
       const typename Tr::Sink si = Tr::sink_from_j(lds[live ? i : 0]);
       Comp<T, K> acc;
       acc.init();

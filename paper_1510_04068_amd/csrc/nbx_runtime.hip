@@ -41,6 +41,7 @@ struct Pinned {
   bool pending = false;
 };
 
+constexpr int kBatchMaxGroups = 8 * 256;  // batched launch: at most 8 workgroups per CU
 constexpr size_t kErrDoubles = 8;  // the error counters head the output block (64 bytes)
 // Host transfers up to this size go through pinned staging (one copy, no per-array overhead);
 // larger ones copy straight from / to the caller's pageable arrays, which the runtime pipelines
@@ -356,29 +357,60 @@ int batch_default_lg(int c) {  // L = 64 / 2^c, at least 1
   return c >= 6 ? 0 : 6 - c;
 }
 
-// Build and upload the schedule: items (system, lanes_log2) of the selected classes (mask), the
-// largest systems first (ties by system index), one wave each.
+// Build and upload the schedule of the selected size classes (mask): items (system, lanes_log2,
+// first sink, end sink), one wave each.  A system's sinks go in rounds of 64 / L; its rounds are
+// split into items of about the mean cost per wave of the whole batch (cost = rounds x the
+// sources each lane visits per round), so that the largest systems do not set the launch time.
+// Items are ordered by cost, the costliest first (ties by system index), and the waves take them
+// round-robin.  Each sink is computed by exactly one item, with the same arithmetic as unsplit.
 int batch_upload(nbx_ctx *c, unsigned class_mask, const int *lg_override, hipStream_t stream) {
   const int n_sys = (int)c->batch_sizes.size();
-  std::vector<int> order;
-  order.reserve(n_sys);
-  for (int k = 0; k < n_sys; ++k)
-    if (class_mask & (1u << batch_class(c->batch_sizes[k]))) order.push_back(k);
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return c->batch_sizes[a] > c->batch_sizes[b]; });
-  std::vector<int2> items(order.size());
-  for (size_t k = 0; k < order.size(); ++k) {
-    const int cl = batch_class(c->batch_sizes[order[k]]);
+  struct Sys {
+    int k, lg, n, per_round, rounds;
+    int64_t round_cost;
+  };
+  std::vector<Sys> sys;
+  int64_t total = 0;
+  for (int k = 0; k < n_sys; ++k) {
+    const int n = c->batch_sizes[k];
+    const int cl = batch_class(n);
+    if (!(class_mask & (1u << cl))) continue;
     int lg = lg_override ? lg_override[cl] : c->batch_lg[cl];
     if (lg < 0) lg = batch_default_lg(cl);
-    items[k] = make_int2(order[k], lg);
+    Sys q;
+    q.k = k;
+    q.lg = lg;
+    q.n = n;
+    q.per_round = 64 >> lg;
+    q.rounds = (n + q.per_round - 1) / q.per_round;
+    q.round_cost = (n + (1 << lg) - 1) >> lg;
+    total += q.rounds * q.round_cost;
+    sys.push_back(q);
   }
-  if (int rc = grow(c, c->batch_items, std::max<size_t>(1, items.size()) * sizeof(int2))) return rc;
-  if (!items.empty())
-    HIP_TRY(c, hipMemcpyAsync(c->batch_items.p, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice,
+  const int64_t waves = (int64_t)kBatchMaxGroups * (kThreads / 64);
+  const int64_t target = std::max<int64_t>(1, (total + waves - 1) / waves);
+  struct Item {
+    int4 v;
+    int64_t cost;
+  };
+  std::vector<Item> items;
+  for (const Sys &q : sys) {
+    const int per_item = (int)std::max<int64_t>(1, target / q.round_cost);  // rounds per item
+    for (int r0 = 0; r0 < q.rounds; r0 += per_item) {
+      const int r1 = std::min(q.rounds, r0 + per_item);
+      items.push_back({make_int4(q.k, q.lg, r0 * q.per_round, std::min(q.n, r1 * q.per_round)),
+                       (r1 - r0) * q.round_cost});
+    }
+  }
+  std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) { return a.cost > b.cost; });
+  std::vector<int4> packed(items.size());
+  for (size_t k = 0; k < items.size(); ++k) packed[k] = items[k].v;
+  if (int rc = grow(c, c->batch_items, std::max<size_t>(1, packed.size()) * sizeof(int4))) return rc;
+  if (!packed.empty())
+    HIP_TRY(c, hipMemcpyAsync(c->batch_items.p, packed.data(), packed.size() * sizeof(int4), hipMemcpyHostToDevice,
                               stream));
   HIP_TRY(c, hipStreamSynchronize(stream));
-  c->batch_n_items = (int)items.size();
+  c->batch_n_items = (int)packed.size();
   return NBX_OK;
 }
 
@@ -386,7 +418,7 @@ int batch_enqueue(nbx_ctx *c, hipStream_t stream, const double *d_m, const doubl
                   double eps2, double *d_acc, double *d_jerk, double *d_pot) {
   BatchParams bp{};
   bp.n_items = c->batch_n_items;
-  bp.items = static_cast<const int2 *>(c->batch_items.p);
+  bp.items = static_cast<const int4 *>(c->batch_items.p);
   bp.offset = c->d_batch_offset;
   bp.m = d_m;
   bp.x = d_x;
@@ -397,7 +429,7 @@ int batch_enqueue(nbx_ctx *c, hipStream_t stream, const double *d_m, const doubl
   bp.pot = d_pot;
   const int waves_per_wg = kThreads / 64;
   int grid = (bp.n_items + waves_per_wg - 1) / waves_per_wg;
-  if (grid > 8 * 256) grid = 8 * 256;  // persistent: at most 8 workgroups per CU, waves loop over items
+  if (grid > kBatchMaxGroups) grid = kBatchMaxGroups;  // persistent: waves loop over items
   if (grid < 1) grid = 1;
   hipError_t e = launch_batch(c->precision, bp, grid, stream);
   if (e != hipSuccess) return hip_fail(c, e, "batch kernel launch");
