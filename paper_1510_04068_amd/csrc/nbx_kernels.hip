@@ -996,10 +996,10 @@ __global__ __launch_bounds__(kThreads) void k_combine(const ForceParams fp, int 
 // ---------------------------------------------------------------------------------------------
 // Batched few-body systems (4th order: acc, jerk, pot).  One persistent launch; each wave takes
 // the work items w, w + W, w + 2W, ... of a cost-sorted schedule (W = waves in the grid).  An
-// item is one system of n <= kBatchMax particles: the wave stages the system in its own LDS
-// slice, then covers the sinks 64/L at a time with L lanes per sink, each lane summing every L-th
-// source (self excluded by index), and a butterfly over the L lanes.  L comes per item from the
-// schedule (chosen per size class by nbx_batch_tune).
+// item is a range of sinks of one system of n <= kBatchMax particles: the wave stages the whole
+// system in its own LDS slice, then covers its sinks 64/L at a time with L lanes per sink, each
+// lane summing every L-th source (self excluded by index), and a butterfly over the L lanes.  L
+// comes per item from the schedule (chosen per size class by nbx_batch_tune).
 // ---------------------------------------------------------------------------------------------
 template <int Prec>
 __global__ __launch_bounds__(kThreads) void k_batch(const BatchParams bp) {
