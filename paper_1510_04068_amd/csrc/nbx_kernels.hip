@@ -247,8 +247,12 @@ struct Mixed {
   }
 
   // Nearest-neighbour key: the bit pattern of |r|^2 >= 0, whose unsigned order is the order of
-  // |r|^2 (the self pair is given the maximum key by the guarded loop).
+  // |r|^2 (the self pair is given the maximum key by the guarded loop).  The minimum over a group
+  // of sources is kept on the keys themselves (one min3 per two keys).
   __device__ static __forceinline__ Key key_of(float r2) { return __float_as_uint(r2); }
+  using GKey = Key;
+  __device__ static __forceinline__ GKey gkey_none() { return ~Key(0); }
+  __device__ static __forceinline__ Key group_key(GKey g) { return g; }
 
   __device__ static __forceinline__ Key nn_key(const J &j, const Sink &s) {
     float dx, dy, dz;
@@ -258,7 +262,7 @@ struct Mixed {
   // One pair; returns the unsoftened |r|^2 (for the neighbour-list test).
   template <bool Guard>
   __device__ static __forceinline__ float interact(const J &j, const Sink &s, float eps2, int jidx, int self,
-                                                  Comp<float, kValues<Order>> &A, Key &gmin) {
+                                                  Comp<float, kValues<Order>> &A, GKey &gmin) {
     float dx, dy, dz;
     const float r2 = diff_r2(j, s, dx, dy, dz);
     const float R2 = r2 + eps2;
@@ -448,6 +452,20 @@ struct F64 {
   }
 
   __device__ static __forceinline__ Key key_of(double r2) { return (Key)__double_as_longlong(r2); }
+  // Orders 2 and 4 keep the minimum over a group of sources on the FP64 values (one min per pair
+  // instead of a 64-bit compare and two selects); the self pair counts as +inf, and a group with
+  // no other source maps to the "none" key.  Order 6 keeps it on the keys: there the FP64 form
+  // needs two more registers and the launch would lose half its waves (256 -> 258 per lane).
+  static constexpr bool kFloatMin = Order != 6;
+  using GKey = std::conditional_t<kFloatMin, double, Key>;
+  __device__ static __forceinline__ GKey gkey_none() {
+    if constexpr (kFloatMin) return __builtin_huge_val();
+    else return ~Key(0);
+  }
+  __device__ static __forceinline__ Key group_key(GKey g) {
+    if constexpr (kFloatMin) return g < __builtin_huge_val() ? key_of(g) : ~Key(0);
+    else return g;
+  }
 
   __device__ static __forceinline__ Key nn_key(const J &j, const Sink &s) {
     double dx, dy, dz;
@@ -457,7 +475,7 @@ struct F64 {
   // One pair; returns the unsoftened |r|^2 (for the neighbour-list test).
   template <bool Guard>
   __device__ static __forceinline__ double interact(const J &j, const Sink &s, double eps2, int jidx, int self,
-                                                  Comp<double, kValues<Order>> &A, Key &gmin) {
+                                                  Comp<double, kValues<Order>> &A, GKey &gmin) {
     double dx, dy, dz;
     const double r2 = diff_r2(j, s, dx, dy, dz);
     const double R2 = r2 + eps2;
@@ -512,9 +530,15 @@ struct F64 {
         A.part[7] += a2x; A.part[8] += a2y; A.part[9] += a2z;
       }
     }
-    Key key = key_of(r2);
-    if constexpr (Guard) key = jidx != self ? key : ~Key(0);
-    gmin = key < gmin ? key : gmin;
+    if constexpr (kFloatMin) {
+      double gk = r2;
+      if constexpr (Guard) gk = jidx != self ? gk : __builtin_huge_val();
+      gmin = fmin(gk, gmin);
+    } else {
+      Key key = key_of(r2);
+      if constexpr (Guard) key = jidx != self ? key : ~Key(0);
+      gmin = key < gmin ? key : gmin;
+    }
     return r2;
   }
 };
@@ -676,9 +700,9 @@ __device__ __forceinline__ void tile_compute(const ForceParams &fp, const typena
   const int per = L1 ? kTile : kTile >> lg;
   for (int c = 0; c < per; c += kChunkAcc) {
     const int ce = per < c + kChunkAcc ? per : c + kChunkAcc;
-    Key gmin[P];
+    typename Tr::GKey gmin[P];
 #pragma unroll
-    for (int p = 0; p < P; ++p) gmin[p] = ~Key(0);
+    for (int p = 0; p < P; ++p) gmin[p] = Tr::gkey_none();
 #pragma unroll 2
     for (int u = c; u < ce; ++u) {
       const int e = L1 ? u : slot + (u << lg);
@@ -695,8 +719,9 @@ __device__ __forceinline__ void tile_compute(const ForceParams &fp, const typena
     const int g0 = L1 ? jb + c : jb + (c << lg);
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-      if (gmin[p] < nnk[p]) {
-        nnk[p] = gmin[p];
+      const Key gk = Tr::group_key(gmin[p]);
+      if (gk < nnk[p]) {
+        nnk[p] = gk;
         nng[p] = g0;
       }
     }
@@ -1039,7 +1064,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchParams bp) {
       const typename Tr::Sink si = Tr::sink_from_j(lds[live ? i : 0]);
       Comp<T, K> acc;
       acc.init();
-      typename Tr::Key dummy = ~typename Tr::Key(0);
+      typename Tr::GKey dummy = Tr::gkey_none();
       for (int j0 = slot; j0 < n; j0 += kChunkAcc << lg) {
         const int je = n < j0 + (kChunkAcc << lg) ? n : j0 + (kChunkAcc << lg);
         for (int j = j0; j < je; j += L) Tr::template interact<true>(lds[j], si, eps2, j, i, acc, dummy);
