@@ -17,7 +17,9 @@ from .oracle import (  # noqa: F401
     lib_path,
     max_threads,
     predict,
+    predict_jerk,
     force,
+    force8,
     force_vjp,
     hermite4_correct,
     total_energy,

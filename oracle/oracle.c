@@ -38,6 +38,20 @@
  *        acc = sum A0, jerk = sum A1, snap = sum A2, pot = -sum m_j / R
  *    Sources whose id equals the sink's id are left out of every output.
  *
+ *  - oracle_force8, oracle_predict_jerk: the 8th-order mode.  The paper keeps
+ *    its data in double precision so that higher-order Hermite integrators,
+ *    6th and 8th order (Nitadori & Makino 2008), can be added without
+ *    changing the host code (Methods > Numerical Accuracy; Conclusions: the
+ *    library could be expanded with an 8th-order integrator).  That needs the
+ *    third derivative of the pair acceleration (crackle) along the predicted
+ *    motion, which also uses the relative jerk j = j_j - j_i:
+ *        gamma = (3 v.a + r.j) / R^2 + alpha (3 beta - 4 alpha^2)
+ *        A3 = m_j j / R^3 - 9 alpha A2 - 9 beta A1 - 3 gamma A0
+ *    (d/dt R^-3 = -3 alpha R^-3, d alpha/dt = beta - 3 alpha^2 and
+ *    d beta/dt = (3 v.a + r.j) / R^2 - 4 alpha^3 give it from A2), crackle =
+ *    sum A3.  Sources carry x, v, a, jerk, snap and crackle as in 6th order;
+ *    the predictor adds the jerk, jerk_p = jerk + snap dt + crackle dt^2/2.
+ *
  * Arithmetic: every per-pair term is evaluated in IEEE double exactly as
  * written above (1/sqrt for R^-1, no fused multiply-add, no reassociation);
  * the sums over sources run in source index order and are kept in
@@ -66,7 +80,8 @@
  *   order 2:  x_p = x + v dt + a dt^2/2,  v_p = v + a dt,  a_p = a
  *   order 4:  x_p = x + v dt + a dt^2/2 + jerk dt^3/6
  *             v_p = v + a dt + jerk dt^2/2,  a_p = a + jerk dt
- *   order 6:  x_p = x + v dt + a dt^2/2 + jerk dt^3/6 + snap dt^4/24 + crackle dt^5/120
+ *   order 6 (and 8):
+ *             x_p = x + v dt + a dt^2/2 + jerk dt^3/6 + snap dt^4/24 + crackle dt^5/120
  *             v_p = v + a dt + jerk dt^2/2 + snap dt^3/6 + crackle dt^4/24
  *             a_p = a + jerk dt + snap dt^2/2 + crackle dt^3/6
  * Arrays are [n][3] row-major; tj is [n].  ap may be NULL for orders 2 and 4; jerk may be NULL
@@ -74,10 +89,11 @@
 int oracle_predict(int n, int order, double t, const double *tj, const double *x, const double *v,
                    const double *a, const double *jerk, const double *snap, const double *crackle,
                    double *xp, double *vp, double *ap) {
-  if (n < 0 || (order != 2 && order != 4 && order != 6) || !tj || !x || !v || !a || !xp || !vp)
+  if (n < 0 || (order != 2 && order != 4 && order != 6 && order != 8) || !tj || !x || !v || !a || !xp ||
+      !vp)
     return ORACLE_ERR_ARG;
   if (order != 2 && !jerk) return ORACLE_ERR_ARG;
-  if (order == 6 && (!snap || !crackle || !ap)) return ORACLE_ERR_ARG;
+  if (order >= 6 && (!snap || !crackle || !ap)) return ORACLE_ERR_ARG;
   for (int p = 0; p < n; ++p) {
     const double dt = t - tj[p];
     const double dt2 = dt * dt, dt3 = dt2 * dt, dt4 = dt3 * dt, dt5 = dt4 * dt;
@@ -193,6 +209,103 @@ int oracle_force(int order, double eps2, int nj, const int64_t *idj, const doubl
       cond[3 * (size_t)i + 1] = (order == 2) ? 0.0 : (double)s_c1;
       cond[3 * (size_t)i + 2] = (double)s_c2;
     }
+  }
+  return ORACLE_OK;
+}
+
+/* 8th-order mode, predicted jerk: jp = jerk + snap dt + crackle dt^2/2, dt = t - tj. */
+int oracle_predict_jerk(int n, double t, const double *tj, const double *jerk, const double *snap,
+                        const double *crackle, double *jp) {
+  if (n < 0 || !tj || !jerk || !snap || !crackle || !jp) return ORACLE_ERR_ARG;
+  for (int p = 0; p < n; ++p) {
+    const double dt = t - tj[p];
+    for (int k = 0; k < 3; ++k) {
+      const int q = 3 * p + k;
+      jp[q] = jerk[q] + snap[q] * dt + crackle[q] * dt * dt / 2.0;
+    }
+  }
+  return ORACLE_OK;
+}
+
+/* 8th-order mode: as oracle_force at order 6, plus the sources' and sinks' jerks jj[nj][3],
+ * ji[ni][3] and the output crackle[ni][3]; cond is [ni][4] (sum |A0|, |A1|, |A2|, |A3|). */
+int oracle_force8(double eps2, int nj, const int64_t *idj, const double *mj, const double *xj,
+                  const double *vj, const double *aj, const double *jj, int ni, const int64_t *idi,
+                  const double *xi, const double *vi, const double *ai, const double *ji, const double *h2,
+                  int nbr_max, double *acc, double *jerk, double *snap, double *crackle, double *pot,
+                  int64_t *nn_id, double *nn_r2, int32_t *nbr_count, int64_t *nbr_ids, double *cond,
+                  int nthreads) {
+  if (nj < 0 || ni < 0 || !idj || !mj || !xj || !vj || !aj || !jj || !idi || !xi || !vi || !ai || !ji ||
+      !acc)
+    return ORACLE_ERR_ARG;
+  if (h2 && (nbr_max < 0 || !nbr_count || (nbr_max > 0 && !nbr_ids))) return ORACLE_ERR_ARG;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+
+#pragma omp parallel for schedule(static)
+  for (int i = 0; i < ni; ++i) {
+    long double s[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, s_pot = 0, s_c[4] = {0, 0, 0, 0};
+    double best_r2 = INFINITY;
+    int64_t best_id = -1;
+    int32_t count = 0;
+    const double *x0 = xi + 3 * (size_t)i, *v0 = vi + 3 * (size_t)i, *a0 = ai + 3 * (size_t)i;
+    const double *j0 = ji + 3 * (size_t)i;
+    for (int j = 0; j < nj; ++j) {
+      if (idj[j] == idi[i]) continue;
+      double r[3], v[3], a[3], jr[3];
+      for (int k = 0; k < 3; ++k) {
+        r[k] = xj[3 * (size_t)j + k] - x0[k];
+        v[k] = vj[3 * (size_t)j + k] - v0[k];
+        a[k] = aj[3 * (size_t)j + k] - a0[k];
+        jr[k] = jj[3 * (size_t)j + k] - j0[k];
+      }
+      const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+      const double Rinv = 1.0 / sqrt(r2 + eps2);
+      const double Rinv2 = Rinv * Rinv;
+      const double mR3 = mj[j] * Rinv * Rinv2;
+      const double va = v[0] * a[0] + v[1] * a[1] + v[2] * a[2];
+      const double rj = r[0] * jr[0] + r[1] * jr[1] + r[2] * jr[2];
+      const double alpha = (r[0] * v[0] + r[1] * v[1] + r[2] * v[2]) * Rinv2;
+      const double beta =
+          (v[0] * v[0] + v[1] * v[1] + v[2] * v[2] + r[0] * a[0] + r[1] * a[1] + r[2] * a[2]) * Rinv2 +
+          alpha * alpha;
+      const double gamma = (3.0 * va + rj) * Rinv2 + alpha * (3.0 * beta - 4.0 * alpha * alpha);
+      double A[4][3];
+      for (int k = 0; k < 3; ++k) {
+        A[0][k] = mR3 * r[k];
+        A[1][k] = mR3 * v[k] - 3.0 * alpha * A[0][k];
+        A[2][k] = mR3 * a[k] - 6.0 * alpha * A[1][k] - 3.0 * beta * A[0][k];
+        A[3][k] = mR3 * jr[k] - 9.0 * alpha * A[2][k] - 9.0 * beta * A[1][k] - 3.0 * gamma * A[0][k];
+      }
+      for (int d = 0; d < 4; ++d) {
+        for (int k = 0; k < 3; ++k) s[d][k] += A[d][k];
+        s_c[d] += sqrt(A[d][0] * A[d][0] + A[d][1] * A[d][1] + A[d][2] * A[d][2]);
+      }
+      s_pot -= mj[j] * Rinv;
+      if (r2 < best_r2) { /* strict: an equal r^2 later in index order loses */
+        best_r2 = r2;
+        best_id = idj[j];
+      }
+      if (h2 && r2 < h2[i]) {
+        if (count < nbr_max) nbr_ids[(size_t)i * nbr_max + count] = idj[j];
+        ++count;
+      }
+    }
+    for (int k = 0; k < 3; ++k) {
+      acc[3 * (size_t)i + k] = (double)s[0][k];
+      if (jerk) jerk[3 * (size_t)i + k] = (double)s[1][k];
+      if (snap) snap[3 * (size_t)i + k] = (double)s[2][k];
+      if (crackle) crackle[3 * (size_t)i + k] = (double)s[3][k];
+    }
+    if (pot) pot[i] = (double)s_pot;
+    if (nn_id) nn_id[i] = best_id;
+    if (nn_r2) nn_r2[i] = best_r2;
+    if (h2) nbr_count[i] = count;
+    if (cond)
+      for (int d = 0; d < 4; ++d) cond[4 * (size_t)i + d] = (double)s_c[d];
   }
   return ORACLE_OK;
 }

@@ -54,6 +54,13 @@ def _load():
             [ctypes.c_int, ctypes.c_double, ctypes.c_int, lp, dp, dp, dp, dp, ctypes.c_int, lp, dp, dp, dp, dp,
              ctypes.c_int, dp, dp, dp, dp, lp, dp, ip, lp, dp, ctypes.c_int]
         )
+        lib.oracle_force8.restype = ctypes.c_int
+        lib.oracle_force8.argtypes = (
+            [ctypes.c_double, ctypes.c_int, lp, dp, dp, dp, dp, dp, ctypes.c_int, lp, dp, dp, dp, dp, dp,
+             ctypes.c_int, dp, dp, dp, dp, dp, lp, dp, ip, lp, dp, ctypes.c_int]
+        )
+        lib.oracle_predict_jerk.restype = ctypes.c_int
+        lib.oracle_predict_jerk.argtypes = [ctypes.c_int, ctypes.c_double] + [dp] * 5
         lib.oracle_force_vjp.restype = ctypes.c_int
         lib.oracle_force_vjp.argtypes = [ctypes.c_double, ctypes.c_int, dp, dp, dp, dp, dp, dp, ctypes.c_int, ip, dp,
                                          dp, dp, ctypes.c_int]
@@ -85,10 +92,10 @@ def max_threads() -> int:
 def predict(order, t, tj, x, v, a, jerk, snap=None, crackle=None):
     """Taylor-predict every particle from its own time tj to t.
 
-    Returns (xp, vp, ap); ap is the predicted acceleration (6th order), for
-    order 4 it is a + jerk*dt and for order 2 it is a (returned for
-    convenience, unused by 2nd- and 4th-order forces).  jerk may be None for
-    order 2.
+    Returns (xp, vp, ap); ap is the predicted acceleration (6th and 8th
+    order), for order 4 it is a + jerk*dt and for order 2 it is a (returned
+    for convenience, unused by 2nd- and 4th-order forces).  jerk may be None
+    for order 2.  Order 8 predicts x, v, a as order 6 (see predict_jerk).
     """
     lib = _load()
     x = _f64(x)
@@ -96,8 +103,8 @@ def predict(order, t, tj, x, v, a, jerk, snap=None, crackle=None):
     tj = _f64(tj, (n,))
     v, a = _f64(v, (n, 3)), _f64(a, (n, 3))
     jerk = _f64(jerk, (n, 3)) if order != 2 else None
-    snap = _f64(snap, (n, 3)) if order == 6 else None
-    crackle = _f64(crackle, (n, 3)) if order == 6 else None
+    snap = _f64(snap, (n, 3)) if order >= 6 else None
+    crackle = _f64(crackle, (n, 3)) if order >= 6 else None
     xp, vp, ap = np.empty((n, 3)), np.empty((n, 3)), np.empty((n, 3))
     d = ctypes.c_double
     rc = lib.oracle_predict(n, order, float(t), _ptr(tj, d), _ptr(x, d), _ptr(v, d), _ptr(a, d), _ptr(jerk, d),
@@ -105,6 +112,57 @@ def predict(order, t, tj, x, v, a, jerk, snap=None, crackle=None):
     if rc != 0:
         raise ValueError("oracle_predict rejected its arguments")
     return xp, vp, ap
+
+
+def predict_jerk(t, tj, jerk, snap, crackle):
+    """8th-order mode: the predicted jerk, jerk + snap dt + crackle dt^2/2."""
+    lib = _load()
+    jerk = _f64(jerk)
+    n = jerk.shape[0]
+    tj, snap, crackle = _f64(tj, (n,)), _f64(snap, (n, 3)), _f64(crackle, (n, 3))
+    jp = np.empty((n, 3))
+    d = ctypes.c_double
+    rc = lib.oracle_predict_jerk(n, float(t), _ptr(tj, d), _ptr(jerk, d), _ptr(snap, d), _ptr(crackle, d),
+                                 _ptr(jp, d))
+    if rc != 0:
+        raise ValueError("oracle_predict_jerk rejected its arguments")
+    return jp
+
+
+def force8(eps2, idj, mj, xj, vj, aj, jj, idi, xi, vi, ai, ji, h2=None, nbr_max=0, nthreads=0):
+    """8th-order mode: acc, jerk, snap, crackle, pot, nn_id, nn_r2, cond [ni][4] (and the neighbour
+    lists when h2 is given) of the sources (with their accelerations aj and jerks jj) on the sinks."""
+    lib = _load()
+    xj = _f64(xj)
+    nj = xj.shape[0]
+    xi = _f64(xi)
+    ni = xi.shape[0]
+    idj = np.ascontiguousarray(idj, dtype=np.int64)
+    idi = np.ascontiguousarray(idi, dtype=np.int64)
+    mj = _f64(mj, (nj,))
+    vj, aj, jj = _f64(vj, (nj, 3)), _f64(aj, (nj, 3)), _f64(jj, (nj, 3))
+    vi, ai, ji = _f64(vi, (ni, 3)), _f64(ai, (ni, 3)), _f64(ji, (ni, 3))
+    if idj.shape != (nj,) or idi.shape != (ni,):
+        raise ValueError("id arrays have the wrong length")
+    if h2 is not None:
+        h2 = _f64(np.broadcast_to(np.asarray(h2, dtype=np.float64), (ni,)).copy(), (ni,))
+    out = {
+        "acc": np.zeros((ni, 3)), "jerk": np.zeros((ni, 3)), "snap": np.zeros((ni, 3)),
+        "crackle": np.zeros((ni, 3)), "pot": np.zeros(ni), "nn_id": np.zeros(ni, dtype=np.int64),
+        "nn_r2": np.zeros(ni), "cond": np.zeros((ni, 4)),
+        "nbr_count": np.zeros(ni, dtype=np.int32) if h2 is not None else None,
+        "nbr_ids": np.full((ni, max(nbr_max, 0)), -1, dtype=np.int64) if h2 is not None else None,
+    }
+    d, L, I = ctypes.c_double, ctypes.c_int64, ctypes.c_int32
+    rc = lib.oracle_force8(
+        float(eps2), nj, _ptr(idj, L), _ptr(mj, d), _ptr(xj, d), _ptr(vj, d), _ptr(aj, d), _ptr(jj, d), ni,
+        _ptr(idi, L), _ptr(xi, d), _ptr(vi, d), _ptr(ai, d), _ptr(ji, d), _ptr(h2, d), int(nbr_max),
+        _ptr(out["acc"], d), _ptr(out["jerk"], d), _ptr(out["snap"], d), _ptr(out["crackle"], d),
+        _ptr(out["pot"], d), _ptr(out["nn_id"], L), _ptr(out["nn_r2"], d), _ptr(out["nbr_count"], I),
+        _ptr(out["nbr_ids"], L), _ptr(out["cond"], d), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_force8 rejected its arguments")
+    return out
 
 
 def force(order, eps2, idj, mj, xj, vj, idi, xi, vi, aj=None, ai=None, h2=None, nbr_max=0, nthreads=0):

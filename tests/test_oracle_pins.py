@@ -427,3 +427,78 @@ def test_order2_leapfrog_circular_orbit_second_order():
         errs.append(np.abs(x[1] - exact).max())
     for e1, e2 in zip(errs, errs[1:]):
         assert 3.0 < e1 / e2 < 5.0, errs  # 2^2 = 4
+
+
+# --------------------------------------------------------------------------------------------
+# 8th-order mode (crackle, the third time derivative of the pair acceleration).
+# --------------------------------------------------------------------------------------------
+def _all_pairs8(eps2, m, x, v, a, j, **kw):
+    ids = np.arange(len(m), dtype=np.int64)
+    return oracle.force8(eps2, ids, m, x, v, a, j, ids, x, v, a, j, **kw)
+
+
+@pytest.mark.parametrize("eps2", [0.0, 1e-2, 0.3])
+@pytest.mark.parametrize("m1,m2", [(0.5, 0.5), (0.9, 0.1)])
+def test_order8_circular_binary_kinematics(eps2, m1, m2):
+    # same exact orbit as above: acc .. crackle are the 2nd .. 5th time derivatives of x(t)
+    d, M = 0.7, m1 + m2
+    R = math.sqrt(d * d + eps2)
+    w = math.sqrt(M / R**3)
+    th = 1.1
+
+    def r_deriv(k):
+        c, s = math.cos(th + k * math.pi / 2), math.sin(th + k * math.pi / 2)
+        return d * w**k * np.array([c, s, 0.0])
+
+    def body(k):
+        return np.array([-(m2 / M) * r_deriv(k), (m1 / M) * r_deriv(k)])
+
+    out = _all_pairs8(eps2, np.array([m1, m2]), body(0), body(1), body(2), body(3))
+    scale = np.abs(body(2)).max()
+    for key, k in (("acc", 2), ("jerk", 3), ("snap", 4), ("crackle", 5)):
+        np.testing.assert_allclose(out[key], body(k), rtol=0, atol=1e-14 * scale * w ** (k - 2))
+    np.testing.assert_allclose(out["pot"], [-m2 / R, -m1 / R], rtol=1e-15)
+    assert out["cond"].shape == (2, 4)
+
+
+@pytest.mark.parametrize("eps2", [1e-2, 1e-1])
+def test_crackle_is_time_derivative_of_snap(eps2):
+    # every particle moves on x + v t + a t^2/2 + j t^3/6 (velocity, acceleration and jerk
+    # following); the snap along that motion has the crackle as its time derivative
+    src = nbody_ics.make_sources(24, seed=16, order=6, masses="salpeter")
+    rng = np.random.default_rng(17)
+    a, j = src.a, rng.normal(0, 1, size=src.a.shape)
+    out = _all_pairs8(eps2, src.m, src.x, src.v, a, j)
+
+    def snap_at(s):
+        return _all_pairs8(eps2, src.m, src.x + src.v * s + a * s * s / 2 + j * s**3 / 6,
+                           src.v + a * s + j * s * s / 2, a + j * s, j)["snap"]
+
+    fd = _fd(snap_at, 4e-4)
+    np.testing.assert_allclose(out["crackle"], fd, rtol=0, atol=1e-7 * np.abs(out["crackle"]).max())
+    # and the lower derivatives are those of the 6th-order path
+    out6 = _all_pairs(6, eps2, src.m, src.x, src.v, a=a)
+    for key in ("acc", "jerk", "snap", "pot", "nn_id", "nn_r2"):
+        np.testing.assert_array_equal(out[key], out6[key])
+
+
+def test_order8_newton_third_law():
+    src = nbody_ics.make_sources(96, seed=18, order=6, masses="salpeter")
+    j = np.random.default_rng(19).normal(0, 1, size=src.a.shape)
+    out = _all_pairs8(1e-4, src.m, src.x, src.v, src.a, j)
+    q = out["crackle"]
+    total = np.sum(src.m[:, None] * q, axis=0)
+    assert np.all(np.abs(total) <= 1e-14 * np.sum(src.m[:, None] * np.abs(q)))
+
+
+def test_order8_predicted_jerk_exact_on_quintics():
+    # x(t) quintic: the jerk x''' is quadratic, so jerk + snap dt + crackle dt^2/2 is exact
+    rng = np.random.default_rng(20)
+    n = 30
+    c = rng.normal(0, 1, size=(6, n, 3))  # x(t) = sum_k c_k (t - tj)^k
+    tj = rng.uniform(-1, 0, size=n)
+    t = 0.3
+    dt = (t - tj)[:, None]
+    jerk, snap, crackle = 6 * c[3], 24 * c[4], 120 * c[5]
+    exact = 6 * c[3] + 24 * c[4] * dt + 60 * c[5] * dt * dt
+    np.testing.assert_allclose(oracle.predict_jerk(t, tj, jerk, snap, crackle), exact, rtol=1e-13, atol=1e-13)
