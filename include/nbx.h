@@ -21,16 +21,20 @@
  *
  * Force law (the paper prints none; this is the reading used): Newtonian
  * gravity, G = 1, Plummer softening R^2 = |r|^2 + eps2, r = x_j - x_i,
- * v = v_j - v_i, a = a_j - a_i (predicted), alpha = r.v / R^2,
- * beta = (v.v + r.a) / R^2 + alpha^2:
- *     acc  += m_j r / R^3
- *     jerk += m_j v / R^3 - 3 alpha (m_j r / R^3)
- *     snap += m_j a / R^3 - 6 alpha A1 - 3 beta A0          (order 6)
- *     pot  -= m_j / R
- * Sources with the sink's own id are excluded from every output.  Jerk and
- * snap are the time derivatives of the softened acceleration along the
- * predicted motion, as a 4th/6th-order Hermite integrator needs them
- * (Results; Results > Sixth order performance).  Order 2 is the GRAPE-5 mode
+ * v = v_j - v_i, a = a_j - a_i, j = j_j - j_i (predicted), alpha = r.v / R^2,
+ * beta = (v.v + r.a) / R^2 + alpha^2,
+ * gamma = (3 v.a + r.j) / R^2 + alpha (3 beta - 4 alpha^2):
+ *     acc     += m_j r / R^3                                           (= A0)
+ *     jerk    += m_j v / R^3 - 3 alpha A0                              (= A1)
+ *     snap    += m_j a / R^3 - 6 alpha A1 - 3 beta A0      (orders 6, 8; = A2)
+ *     crackle += m_j j / R^3 - 9 alpha A2 - 9 beta A1 - 3 gamma A0   (order 8)
+ *     pot     -= m_j / R
+ * Sources with the sink's own id are excluded from every output.  Jerk, snap
+ * and crackle are the time derivatives of the softened acceleration along the
+ * predicted motion, as a 4th/6th/8th-order Hermite integrator needs them
+ * (Results; Results > Sixth order performance; order 8 is the next step the
+ * Conclusions name for the double-precision storage: it predicts the jerk of
+ * every source and sink as well, j + s dt + c dt^2/2).  Order 2 is the GRAPE-5 mode
  * for a 2nd-order leapfrog (Background; Conclusions): acc and pot only, from
  * positions and masses; its predictor stops at the acceleration term.
  *
@@ -96,7 +100,7 @@ typedef struct nbx_ctx nbx_ctx; /* opaque; owns every device buffer it allocates
 typedef struct nbx_config {
   int device;    /* HIP device ordinal */
   int order;     /* 2: acc, pot (GRAPE-5 mode);  4: acc, jerk, pot;  6: also snap (needs snap and
-                    crackle of the sources) */
+                    crackle of the sources);  8: also crackle (same source data as order 6) */
   int precision; /* NBX_FP64 or NBX_MIXED; can be changed later with nbx_set_precision */
   int nj_max;    /* source capacity (addresses 0 .. nj_max-1) */
   int ni_max;    /* largest number of sinks in one nbx_force call */
@@ -110,7 +114,7 @@ int nbx_version(void);
 int nbx_device_count(int *count);
 
 /* Create a context on cfg->device and allocate its source/sink buffers.
- * Errors: NBX_ERR_ARG (NULL, order not 2/4/6, bad precision, nj_max < 1,
+ * Errors: NBX_ERR_ARG (NULL, order not 2/4/6/8, bad precision, nj_max < 1,
  * ni_max < 1, nbr_max < 0), NBX_ERR_NO_DEVICE, NBX_ERR_OOM, NBX_ERR_DEVICE.
  * On error *out is NULL. */
 int nbx_open(nbx_ctx **out, const nbx_config *cfg);
@@ -130,8 +134,8 @@ int nbx_set_precision(nbx_ctx *ctx, int precision);
 int nbx_set_nj(nbx_ctx *ctx, int nj);
 
 /* Copy n sources from host arrays into addresses addr[k] (the copy step).  id[n], m[n], t[n]
- * (the time the Taylor data refers to), x, v, a, jerk [n][3]; snap and crackle [n][3] for order 6
- * (NULL for order 4).  Order 2: v and a may be NULL (taken as zero) and jerk is ignored (may be
+ * (the time the Taylor data refers to), x, v, a, jerk [n][3]; snap and crackle [n][3] for orders
+ * 6 and 8 (NULL for order 4).  Order 2: v and a may be NULL (taken as zero) and jerk is ignored (may be
  * NULL); the predictor uses x + v dt + a dt^2/2.  Every addr must be in [0, nj_max) (else
  * NBX_ERR_ARG, nothing copied); the number of sources in use grows to cover the highest address
  * written.  The host arrays are read before the call returns (packed into pinned staging memory
@@ -155,12 +159,12 @@ int nbx_force(nbx_ctx *ctx, int ni, const int32_t *i_addr, double eps2, const do
 
 /* Forces on ni sinks given explicitly (they need not be sources): id[ni], x, v [ni][3] (v may be
  * NULL for order 2), a [ni][3] for order 6 (else NULL).  A source with the sink's id is excluded.  The sink state is used as
- * given (no prediction).  Otherwise as nbx_force. */
+ * given (no prediction).  Otherwise as nbx_force.  Not available at order 8 (NBX_ERR_ARG). */
 int nbx_force_ext(nbx_ctx *ctx, int ni, const int64_t *id, const double *x, const double *v,
                   const double *a, double eps2, const double *h2);
 
 /* Wait for the last nbx_force / nbx_force_ext and copy its results to caller-owned host arrays:
- * acc, jerk [ni][3] (orders 4, 6; never written for order 2), snap [ni][3] (order 6), pot [ni],
+ * acc, jerk [ni][3] (orders 4, 6, 8; never written for order 2), snap [ni][3] (orders 6, 8), pot [ni],
  * nn_id [ni], nn_r2 [ni].  Any pointer may be NULL to skip that output.  The results and the
  * error counters come back in one copy.  Returns NBX_WARN_NBR_OVERFLOW if a neighbour list
  * overflowed, NBX_ERR_ARG if an address was out of range in a copy or force call since the last
@@ -168,12 +172,17 @@ int nbx_force_ext(nbx_ctx *ctx, int ni, const int64_t *id, const double *x, cons
 int nbx_get_force(nbx_ctx *ctx, double *acc, double *jerk, double *snap, double *pot,
                   int64_t *nn_id, double *nn_r2);
 
+/* Order 8 (Conclusions: the next expansion of the double-precision storage): wait for the last
+ * nbx_force and copy its crackle [ni][3] to a caller-owned host array.  NBX_ERR_ARG for another
+ * order or NULL; NBX_ERR_STATE before the first force call; error counters as nbx_get_force. */
+int nbx_get_crackle(nbx_ctx *ctx, double *crackle);
+
 /* Neighbour lists of the last force call: count[ni] (exact) and ids[ni][nbr_max] (the first
  * min(count, nbr_max) entries of each row are valid, in no particular order). */
 int nbx_get_nbr(nbx_ctx *ctx, int32_t *count, int64_t *ids);
 
 /* Predicted FP64 state of n sources at the current prediction time: xp, vp [n][3]; ap [n][3]
- * (order 6; NULL to skip).  addr[n] in [0, nj).  Synchronous.  Uses the same predictor as the
+ * (NULL to skip).  addr[n] in [0, nj).  Synchronous.  Uses the same predictor as the
  * force kernel. */
 int nbx_get_predicted(nbx_ctx *ctx, int n, const int32_t *addr, double *xp, double *vp, double *ap);
 
@@ -198,11 +207,19 @@ int nbx_set_j_dev(nbx_ctx *ctx, void *stream, int n, const int32_t *d_addr, cons
  * d_snap [ni][3] (order 6, else may be NULL), d_pot [ni],
  * d_nn_id [ni], d_nn_r2 [ni] (required); d_nbr_count [ni] and d_nbr_ids [ni][nbr_max] when d_h2
  * is given.  Sink addresses outside [0, nj) make the kernel skip that sink (its outputs are left
- * untouched) and are counted for nbx_sync. */
+ * untouched) and are counted for nbx_sync.  An order-8 context returns NBX_ERR_ARG: use
+ * nbx_force8_dev. */
 int nbx_force_dev(nbx_ctx *ctx, void *stream, int ni, const int32_t *d_i_addr, double eps2,
                   const double *d_h2, double *d_acc, double *d_jerk, double *d_snap,
                   double *d_pot, int64_t *d_nn_id, double *d_nn_r2, int32_t *d_nbr_count,
                   int64_t *d_nbr_ids);
+
+/* Order 8 (Conclusions): as nbx_force_dev, with d_snap and d_crackle [ni][3] both required.
+ * NBX_ERR_ARG on a context of another order. */
+int nbx_force8_dev(nbx_ctx *ctx, void *stream, int ni, const int32_t *d_i_addr, double eps2,
+                   const double *d_h2, double *d_acc, double *d_jerk, double *d_snap,
+                   double *d_crackle, double *d_pot, int64_t *d_nn_id, double *d_nn_r2,
+                   int32_t *d_nbr_count, int64_t *d_nbr_ids);
 
 /* ---- adjoint -----------------------------------------------------------------------------------
  * Gradients of L = sum_i (g_acc_i . acc_i + g_jerk_i . jerk_i + g_pot_i pot_i) with respect to the

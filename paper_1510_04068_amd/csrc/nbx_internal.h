@@ -7,7 +7,7 @@
 //   pos_mass[a] = (x, y, z, m)            32 B
 //   vel_time[a] = (vx, vy, vz, t_j)       32 B
 //   acc_jrk[a]  = (ax, ay, az, jx, jy, jz) 48 B
-//   snp_crk[a]  = (sx, sy, sz, cx, cy, cz) 48 B   (order 6 only)
+//   snp_crk[a]  = (sx, sy, sz, cx, cy, cz) 48 B   (orders 6 and 8 only)
 //   id[a]       int64
 // The arrays hold nj_max entries; entries never written hold a massless source at
 // (1e18, 1e18, 1e18) with id -1.  The force kernel reads addresses [0, nj) and substitutes
@@ -80,6 +80,7 @@ struct ForceParams {
   double *acc;
   double *jrk;
   double *snp;
+  double *crk;  // order 8: crackle of the sinks
   double *pot;
   int64_t *nn_id;
   double *nn_r2;
@@ -99,7 +100,7 @@ struct ForceParams {
 };
 
 // Batched few-body systems: particles of system s are [offset[s], offset[s+1]); items[k] =
-// (system, lanes_log2), one wave per item, in schedule order.
+// (system, lanes_log2, first sink, end sink), one wave per item, in schedule order.
 constexpr int kBatchMax = 128;  // largest system of a batch
 struct BatchParams {
   int n_items;

@@ -107,9 +107,9 @@ struct Comp<float, K> {
   __device__ __forceinline__ double value(int k) const { return sum[k]; }
 };
 
-// value slots: 0..2 acc, 3..5 jerk, 6 pot, 7..9 snap (order 2: 0..2 acc, 3 pot)
+// value slots: 0..2 acc, 3..5 jerk, 6 pot, 7..9 snap, 10..12 crackle (order 2: 0..2 acc, 3 pot)
 template <int Order>
-constexpr int kValues = Order == 6 ? 10 : (Order == 4 ? 7 : 4);
+constexpr int kValues = Order == 8 ? 13 : (Order == 6 ? 10 : (Order == 4 ? 7 : 4));
 template <int Order>
 constexpr int kPotSlot = Order == 2 ? 3 : 6;
 
@@ -136,6 +136,13 @@ struct MixedTile<6> {  // 52 B per source
   float4 t2[kTile];    // vy vz ax ay
   float t3[kTile];     // az
 };
+template <>
+struct MixedTile<8> {  // 64 B per source
+  float4 t0[kTile];    // xh.x xh.y xh.z m
+  float4 t1[kTile];    // xl.x xl.y xl.z vx
+  float4 t2[kTile];    // vy vz ax ay
+  float4 t3[kTile];    // az jx jy jz
+};
 
 __device__ __forceinline__ void ds_split(double x, float &hi, float &lo) {
   hi = (float)x;
@@ -149,12 +156,12 @@ struct Mixed {
   static constexpr int kK = kValues<Order>;
   using Tile = MixedTile<Order>;
   struct Sink {
-    float xh[3], xl[3], v[3], a[3];
+    float xh[3], xl[3], v[3], a[3], j[3];  // j: order 8
     float m;
     int64_t id;
   };
   struct J {
-    float xh[3], m, xl[3], v[3], a[3];
+    float xh[3], m, xl[3], v[3], a[3], j[3];
   };
 
   // A sink whose state is exactly a staged source record (batched systems).
@@ -166,20 +173,23 @@ struct Mixed {
       s.xl[k] = j.xl[k];
       s.v[k] = j.v[k];
       s.a[k] = j.a[k];
+      s.j[k] = j.j[k];
     }
     s.m = j.m;
     s.id = -1;
     return s;
   }
 
+  // ap: the acceleration [3], followed for order 8 by the jerk [3]
   __device__ static __forceinline__ Sink make_sink(const double xp[3], const double vp[3],
-                                                   const double ap[3], double m) {
+                                                   const double ap[6], double m) {
     Sink s;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       ds_split(xp[k], s.xh[k], s.xl[k]);
       s.v[k] = (float)vp[k];
       s.a[k] = (float)ap[k];
+      s.j[k] = Order == 8 ? (float)ap[3 + k] : 0.0f;
     }
     s.m = (float)m;
     s.id = -1;
@@ -187,7 +197,7 @@ struct Mixed {
   }
 
   __device__ static __forceinline__ void store(Tile &tl, int e, const double xp[3], const double vp[3],
-                                               const double ap[3], double m) {
+                                               const double ap[6], double m) {
     float xh[3], xl[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) ds_split(xp[k], xh[k], xl[k]);
@@ -197,10 +207,14 @@ struct Mixed {
     } else if constexpr (Order == 4) {
       tl.t1[e] = make_float4(xl[0], xl[1], xl[2], (float)vp[0]);
       tl.t2[e] = make_float2((float)vp[1], (float)vp[2]);
-    } else {
+    } else if constexpr (Order == 6) {
       tl.t1[e] = make_float4(xl[0], xl[1], xl[2], (float)vp[0]);
       tl.t2[e] = make_float4((float)vp[1], (float)vp[2], (float)ap[0], (float)ap[1]);
       tl.t3[e] = (float)ap[2];
+    } else {
+      tl.t1[e] = make_float4(xl[0], xl[1], xl[2], (float)vp[0]);
+      tl.t2[e] = make_float4((float)vp[1], (float)vp[2], (float)ap[0], (float)ap[1]);
+      tl.t3[e] = make_float4((float)ap[2], (float)ap[3], (float)ap[4], (float)ap[5]);
     }
   }
 
@@ -215,23 +229,30 @@ struct Mixed {
     } else if constexpr (Order == 4) {
       const float2 c = tl.t2[e];
       j.v[0] = b.w; j.v[1] = c.x; j.v[2] = c.y;
-    } else {
+    } else if constexpr (Order == 6) {
       const float4 c = tl.t2[e];
       j.v[0] = b.w;
       j.v[1] = c.x; j.v[2] = c.y; j.a[0] = c.z; j.a[1] = c.w;
       j.a[2] = tl.t3[e];
+    } else {
+      const float4 c = tl.t2[e];
+      const float4 d = tl.t3[e];
+      j.v[0] = b.w;
+      j.v[1] = c.x; j.v[2] = c.y; j.a[0] = c.z; j.a[1] = c.w;
+      j.a[2] = d.x; j.j[0] = d.y; j.j[1] = d.z; j.j[2] = d.w;
     }
     return j;
   }
 
   // The source record as the force loop sees it after staging (same conversions as store/load).
-  __device__ static __forceinline__ J make_j(const double xp[3], const double vp[3], const double ap[3], double m) {
+  __device__ static __forceinline__ J make_j(const double xp[3], const double vp[3], const double ap[6], double m) {
     J j;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       ds_split(xp[k], j.xh[k], j.xl[k]);
       j.v[k] = (float)vp[k];
       j.a[k] = (float)ap[k];
+      j.j[k] = Order == 8 ? (float)ap[3 + k] : 0.0f;
     }
     j.m = (float)m;
     return j;
@@ -315,6 +336,23 @@ struct Mixed {
         A.part[3] += a1x; A.part[4] += a1y; A.part[5] += a1z;
         A.part[6] -= mr;
         A.part[7] += a2x; A.part[8] += a2y; A.part[9] += a2z;
+        if constexpr (Order == 8) {
+          // crackle: gamma = (3 v.a + r.j) / R^2 + alpha (3 beta - 4 alpha^2),
+          // A3 = m j / R^3 - 9 alpha A2 - 9 beta A1 - 3 gamma A0
+          const float djx = j.j[0] - s.j[0];
+          const float djy = j.j[1] - s.j[1];
+          const float djz = j.j[2] - s.j[2];
+          const float va = __builtin_fmaf(dvz, daz, __builtin_fmaf(dvy, day, dvx * dax));
+          const float rj = __builtin_fmaf(dz, djz, __builtin_fmaf(dy, djy, dx * djx));
+          const float ga = __builtin_fmaf(__builtin_fmaf(3.0f, va, rj), rinv2,
+                                          al * __builtin_fmaf(-4.0f * al, al, 3.0f * be));
+          const float am9 = al * -9.0f;
+          const float bm9 = be * -9.0f;
+          const float gm3 = ga * -3.0f;
+          A.part[10] += __builtin_fmaf(am9, a2x, __builtin_fmaf(bm9, a1x, __builtin_fmaf(gm3, a0x, mr3 * djx)));
+          A.part[11] += __builtin_fmaf(am9, a2y, __builtin_fmaf(bm9, a1y, __builtin_fmaf(gm3, a0y, mr3 * djy)));
+          A.part[12] += __builtin_fmaf(am9, a2z, __builtin_fmaf(bm9, a1z, __builtin_fmaf(gm3, a0z, mr3 * djz)));
+        }
       }
     }
     Key key = key_of(r2);
@@ -346,6 +384,16 @@ struct F64Tile<6> {  // 80 B per source
   double2 t3[kTile];  // vz ax
   double2 t4[kTile];  // ay az
 };
+template <>
+struct F64Tile<8> {  // 104 B per source
+  double2 t0[kTile];  // x y
+  double2 t1[kTile];  // z m
+  double2 t2[kTile];  // vx vy
+  double2 t3[kTile];  // vz ax
+  double2 t4[kTile];  // ay az
+  double2 t5[kTile];  // jx jy
+  double t6[kTile];   // jz
+};
 
 // R^-1 in FP64: v_rsq_f64 estimate y, e = 1 - x y^2, y (1 + e/2 + 3e^2/8) (third-order Newton).
 __device__ __forceinline__ double rsqrt64(double x) {
@@ -363,12 +411,12 @@ struct F64 {
   static constexpr int kK = kValues<Order>;
   using Tile = F64Tile<Order>;
   struct Sink {
-    double x[3], v[3], a[3];
+    double x[3], v[3], a[3], j[3];  // j: order 8
     double m;
     int64_t id;
   };
   struct J {
-    double x[3], m, v[3], a[3];
+    double x[3], m, v[3], a[3], j[3];
   };
 
   __device__ static __forceinline__ Sink sink_from_j(const J &j) {
@@ -378,20 +426,23 @@ struct F64 {
       s.x[k] = j.x[k];
       s.v[k] = j.v[k];
       s.a[k] = j.a[k];
+      s.j[k] = j.j[k];
     }
     s.m = j.m;
     s.id = -1;
     return s;
   }
 
+  // ap: the acceleration [3], followed for order 8 by the jerk [3]
   __device__ static __forceinline__ Sink make_sink(const double xp[3], const double vp[3],
-                                                   const double ap[3], double m) {
+                                                   const double ap[6], double m) {
     Sink s;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       s.x[k] = xp[k];
       s.v[k] = vp[k];
       s.a[k] = ap[k];
+      s.j[k] = Order == 8 ? ap[3 + k] : 0.0;
     }
     s.m = m;
     s.id = -1;
@@ -399,7 +450,7 @@ struct F64 {
   }
 
   __device__ static __forceinline__ void store(Tile &tl, int e, const double xp[3], const double vp[3],
-                                               const double ap[3], double m) {
+                                               const double ap[6], double m) {
     tl.t0[e] = make_double2(xp[0], xp[1]);
     tl.t1[e] = make_double2(xp[2], m);
     if constexpr (Order == 2) {
@@ -410,6 +461,10 @@ struct F64 {
       tl.t2[e] = make_double2(vp[0], vp[1]);
       tl.t3[e] = make_double2(vp[2], ap[0]);
       tl.t4[e] = make_double2(ap[1], ap[2]);
+      if constexpr (Order == 8) {
+        tl.t5[e] = make_double2(ap[3], ap[4]);
+        tl.t6[e] = ap[5];
+      }
     }
   }
 
@@ -428,17 +483,22 @@ struct F64 {
       const double2 d = tl.t3[e];
       const double2 f = tl.t4[e];
       j.v[2] = d.x; j.a[0] = d.y; j.a[1] = f.x; j.a[2] = f.y;
+      if constexpr (Order == 8) {
+        const double2 g = tl.t5[e];
+        j.j[0] = g.x; j.j[1] = g.y; j.j[2] = tl.t6[e];
+      }
     }
     return j;
   }
 
-  __device__ static __forceinline__ J make_j(const double xp[3], const double vp[3], const double ap[3], double m) {
+  __device__ static __forceinline__ J make_j(const double xp[3], const double vp[3], const double ap[6], double m) {
     J j;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       j.x[k] = xp[k];
       j.v[k] = vp[k];
       j.a[k] = ap[k];
+      j.j[k] = Order == 8 ? ap[3 + k] : 0.0;
     }
     j.m = m;
     return j;
@@ -454,9 +514,9 @@ struct F64 {
   __device__ static __forceinline__ Key key_of(double r2) { return (Key)__double_as_longlong(r2); }
   // Orders 2 and 4 keep the minimum over a group of sources on the FP64 values (one min per pair
   // instead of a 64-bit compare and two selects); the self pair counts as +inf, and a group with
-  // no other source maps to the "none" key.  Order 6 keeps it on the keys: there the FP64 form
-  // needs two more registers and the launch would lose half its waves (256 -> 258 per lane).
-  static constexpr bool kFloatMin = Order != 6;
+  // no other source maps to the "none" key.  Orders 6 and 8 keep it on the keys: there the FP64
+  // form needs two more registers and the launch would lose half its waves (256 -> 258 per lane).
+  static constexpr bool kFloatMin = Order <= 4;
   using GKey = std::conditional_t<kFloatMin, double, Key>;
   __device__ static __forceinline__ GKey gkey_none() {
     if constexpr (kFloatMin) return __builtin_huge_val();
@@ -528,6 +588,22 @@ struct F64 {
         A.part[3] += a1x; A.part[4] += a1y; A.part[5] += a1z;
         A.part[6] -= mr;
         A.part[7] += a2x; A.part[8] += a2y; A.part[9] += a2z;
+        if constexpr (Order == 8) {
+          // crackle: gamma = (3 v.a + r.j) / R^2 + alpha (3 beta - 4 alpha^2),
+          // A3 = m j / R^3 - 9 alpha A2 - 9 beta A1 - 3 gamma A0
+          const double djx = j.j[0] - s.j[0];
+          const double djy = j.j[1] - s.j[1];
+          const double djz = j.j[2] - s.j[2];
+          const double va = fma(dvz, daz, fma(dvy, day, dvx * dax));
+          const double rj = fma(dz, djz, fma(dy, djy, dx * djx));
+          const double ga = fma(fma(3.0, va, rj), rinv2, al * fma(-4.0 * al, al, 3.0 * be));
+          const double am9 = al * -9.0;
+          const double bm9 = be * -9.0;
+          const double gm3 = ga * -3.0;
+          A.part[10] += fma(am9, a2x, fma(bm9, a1x, fma(gm3, a0x, mr3 * djx)));
+          A.part[11] += fma(am9, a2y, fma(bm9, a1y, fma(gm3, a0y, mr3 * djy)));
+          A.part[12] += fma(am9, a2z, fma(bm9, a1z, fma(gm3, a0z, mr3 * djz)));
+        }
       }
     }
     if constexpr (kFloatMin) {
@@ -633,7 +709,7 @@ __device__ __forceinline__ void group_reduce(int gs, double (&v)[P][K], uint64_t
 template <int Order>
 __device__ double nn_exact_r2(const ForceParams &fp, int q, int addr, int idx) {
   if (idx < 0 || idx >= fp.nj) return __builtin_huge_val();
-  double xi[3], vi[3], ai[3], mi, xj[3], vj[3], aj[3], mj;
+  double xi[3], vi[3], ai[6], mi, xj[3], vj[3], aj[6], mj;
   if (fp.ext_x) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) xi[k] = fp.ext_x[3 * (size_t)q + k];
@@ -662,7 +738,8 @@ __device__ void finalize_sink(const ForceParams &fp, int q, const double *v, int
   for (int k = 0; k < 3; ++k) {
     fp.acc[3 * (size_t)q + k] = v[k];
     if constexpr (Order != 2) fp.jrk[3 * (size_t)q + k] = v[3 + k];
-    if constexpr (Order == 6) fp.snp[3 * (size_t)q + k] = v[7 + k];
+    if constexpr (Order >= 6) fp.snp[3 * (size_t)q + k] = v[7 + k];
+    if constexpr (Order == 8) fp.crk[3 * (size_t)q + k] = v[10 + k];
   }
   fp.pot[q] = v[kPotSlot<Order>];
   if (idx >= 0 && idx < fp.nj) {
@@ -737,7 +814,7 @@ __device__ __forceinline__ void tile_compute(const ForceParams &fp, const typena
 // Source record of address j exactly as staged by the gravity kernel (padding beyond nj).
 template <class Tr, int Order>
 __device__ __forceinline__ typename Tr::J staged_j(const ForceParams &fp, int jj) {
-  double xp[3], vp[3], ap[3], m;
+  double xp[3], vp[3], ap[6], m;
   if (jj < fp.nj) {
     predict_addr<Order>(fp.src, jj, fp.t, xp, vp, ap, m);
   } else {
@@ -746,6 +823,7 @@ __device__ __forceinline__ typename Tr::J staged_j(const ForceParams &fp, int jj
       xp[k] = kPadPos;
       vp[k] = 0.0;
       ap[k] = 0.0;
+      ap[3 + k] = 0.0;
     }
     m = 0.0;
   }
@@ -818,14 +896,15 @@ __global__ __launch_bounds__(kThreads) void k_force(const ForceParams fp) {
   for (int p = 0; p < P; ++p) {
     q[p] = ib * Q + p * G + grp;
     const bool live = q[p] < fp.ni;
-    double xp[3], vp[3], ap[3], m = 0.0;
-    if (fp.ext_x) {  // explicit sink state, used as given
+    double xp[3], vp[3], ap[6], m = 0.0;
+    if (fp.ext_x) {  // explicit sink state, used as given (orders 2, 4 and 6)
       const int qq = live ? q[p] : 0;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         xp[k] = fp.ext_x[3 * (size_t)qq + k];
         vp[k] = (Order != 2) ? fp.ext_v[3 * (size_t)qq + k] : 0.0;
         ap[k] = (Order == 6) ? fp.ext_a[3 * (size_t)qq + k] : 0.0;
+        ap[3 + k] = 0.0;
       }
       self[p] = live ? fp.ext_self[qq] : -1;
     } else {  // by address: the sink's own predicted source state
@@ -847,7 +926,7 @@ __global__ __launch_bounds__(kThreads) void k_force(const ForceParams fp) {
   // zeros in both precisions and its address marks "no neighbour".
   auto stage = [&](int tile, int buf) {
     const int jj = tile * kTile + tid;
-    double xp[3], vp[3], ap[3], m;
+    double xp[3], vp[3], ap[6], m;
     if (jj < fp.nj) {
       predict_addr<Order>(fp.src, jj, fp.t, xp, vp, ap, m);
     } else {
@@ -856,6 +935,7 @@ __global__ __launch_bounds__(kThreads) void k_force(const ForceParams fp) {
         xp[k] = kPadPos;
         vp[k] = 0.0;
         ap[k] = 0.0;
+        ap[3 + k] = 0.0;
       }
       m = 0.0;
     }
@@ -955,7 +1035,7 @@ __global__ __launch_bounds__(kThreads) void k_combine(const ForceParams fp, int 
   // loads of the partials
   BsState st;
   int bs_i = -1;
-  if constexpr (Order != 2) {
+  if constexpr (Order == 4 || Order == 6) {  // the integrator runs at orders 4 and 6
     if (fp.bs_fuse && r == 0 && qg < fp.ni) {
       bs_i = fp.bs.list[qg];
       bs_load_state<Order>(fp.bs, bs_i, st);
@@ -1009,7 +1089,7 @@ __global__ __launch_bounds__(kThreads) void k_combine(const ForceParams fp, int 
     }
   }
   if (r != 0 || qg >= fp.ni) return;
-  if constexpr (Order != 2) {
+  if constexpr (Order == 4 || Order == 6) {
     if (fp.bs_fuse) {  // block time-step: correct the particle right away
       bs_correct_particle<Order>(fp.bs, bs_i, st, fp.bs_t1, &w[0][0], &w[0][3], Order == 6 ? &w[0][7] : &w[0][0]);
       return;
@@ -1407,7 +1487,7 @@ __global__ __launch_bounds__(256) void k_fill_i32(int32_t *p, int n, int value) 
 // ---------------------------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------------------------
-int values_per_sink(int order) { return order == 6 ? 10 : (order == 4 ? 7 : 4); }
+int values_per_sink(int order) { return order == 8 ? 13 : (order == 6 ? 10 : (order == 4 ? 7 : 4)); }
 
 // Launch shape (static rule; nbx_tune replaces it by measured choices per N_i class).  A
 // workgroup holds Q = (256 / L) * P sinks and one of S source ranges.
@@ -1520,12 +1600,17 @@ hipError_t launch_force(int order, int precision, const ForceParams &fp, const L
   if (order == 4)
     return precision == NBX_MIXED ? launch_force_op<4, NBX_MIXED>(fp, ls, stream)
                                   : launch_force_op<4, NBX_FP64>(fp, ls, stream);
-  return precision == NBX_MIXED ? launch_force_op<6, NBX_MIXED>(fp, ls, stream)
-                                : launch_force_op<6, NBX_FP64>(fp, ls, stream);
+  if (order == 6)
+    return precision == NBX_MIXED ? launch_force_op<6, NBX_MIXED>(fp, ls, stream)
+                                  : launch_force_op<6, NBX_FP64>(fp, ls, stream);
+  return precision == NBX_MIXED ? launch_force_op<8, NBX_MIXED>(fp, ls, stream)
+                                : launch_force_op<8, NBX_FP64>(fp, ls, stream);
 }
 
 static inline int grid_for(int n) { return (n + 255) / 256; }
 
+// Source storage, padding, read-back and the x, v, a predictor are the same at orders 6 and 8
+// (order 8 adds only the predicted jerk, used inside the force kernel).
 hipError_t launch_jupdate(int order, const SourceArrays &src, int nj_max, int n, const int32_t *addr,
                           const int64_t *id, const double *m, const double *t, const double *x,
                           const double *v, const double *a, const double *jerk, const double *snap,
@@ -1545,7 +1630,7 @@ hipError_t launch_jupdate(int order, const SourceArrays &src, int nj_max, int n,
 
 hipError_t launch_pad(int order, const SourceArrays &src, int from, int to, hipStream_t stream) {
   if (to <= from) return hipSuccess;
-  if (order != 6)
+  if (order < 6)
     hipLaunchKernelGGL(k_pad<4>, dim3(grid_for(to - from)), dim3(256), 0, stream, src, from, to);
   else
     hipLaunchKernelGGL(k_pad<6>, dim3(grid_for(to - from)), dim3(256), 0, stream, src, from, to);
@@ -1571,7 +1656,7 @@ hipError_t launch_gather_j(int order, const SourceArrays &src, int n, const int3
                            double *m, double *t, double *x, double *v, double *a, double *jerk,
                            double *snap, double *crackle, hipStream_t stream) {
   if (n <= 0) return hipSuccess;
-  if (order != 6)
+  if (order < 6)
     hipLaunchKernelGGL(k_gather_j<4>, dim3(grid_for(n)), dim3(256), 0, stream, src, n, addr, id, m, t, x, v, a,
                        jerk, snap, crackle);
   else

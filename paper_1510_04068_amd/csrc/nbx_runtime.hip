@@ -23,7 +23,7 @@ using namespace nbx;
 
 namespace {
 
-constexpr int kVersion = 10100;  // 1.1.0: order 2, block time-step integrator
+constexpr int kVersion = 10200;  // 1.2.0: order 8 (crackle)
 
 std::string g_open_error;  // message of the last failed nbx_open
 
@@ -68,7 +68,8 @@ struct nbx_ctx {
   // counters (d_out), so that nbx_get_force moves counters and results in one copy
   double *d_out = nullptr;
   size_t out_doubles = 0;
-  double *d_acc = nullptr, *d_jrk = nullptr, *d_snp = nullptr, *d_pot = nullptr, *d_nnr2 = nullptr;
+  double *d_acc = nullptr, *d_jrk = nullptr, *d_snp = nullptr, *d_crk = nullptr, *d_pot = nullptr,
+         *d_nnr2 = nullptr;
   int64_t *d_nnid = nullptr;
   Pinned stage_j, stage_i, stage_out;  // staging of nbx_set_j, of the sink inputs, of the results
   int32_t *d_nbr_cnt = nullptr;
@@ -230,12 +231,17 @@ void out_layout(nbx_ctx *c, int ni) {
   p += 3 * n;
   c->d_jrk = nullptr;
   c->d_snp = nullptr;
+  c->d_crk = nullptr;
   if (c->cfg.order != 2) {
     c->d_jrk = p;
     p += 3 * n;
   }
-  if (c->cfg.order == 6) {
+  if (c->cfg.order >= 6) {
     c->d_snp = p;
+    p += 3 * n;
+  }
+  if (c->cfg.order == 8) {
+    c->d_crk = p;
     p += 3 * n;
   }
   c->d_pot = p;
@@ -295,7 +301,7 @@ LaunchShape ctx_shape(const nbx_ctx *c, int ni, int nj_pad) {
 // (at time bs_t1) instead of writing the outputs; *fused tells the caller whether that happened.
 int enqueue_force(nbx_ctx *c, hipStream_t stream, int ni, const int32_t *d_iaddr, const int32_t *ext_self,
                   const int64_t *ext_id, const double *ext_x, const double *ext_v, const double *ext_a,
-                  double eps2, const double *d_h2, double *acc, double *jrk, double *snp, double *pot,
+                  double eps2, const double *d_h2, double *acc, double *jrk, double *snp, double *crk, double *pot,
                   int64_t *nn_id, double *nn_r2, int32_t *nbr_cnt, int64_t *nbr_ids,
                   const BlockStepParams *bs = nullptr, double bs_t1 = 0.0, bool *fused = nullptr) {
   if (fused) *fused = false;
@@ -326,6 +332,7 @@ int enqueue_force(nbx_ctx *c, hipStream_t stream, int ni, const int32_t *d_iaddr
   fp.acc = acc;
   fp.jrk = jrk;
   fp.snp = snp;
+  fp.crk = crk;
   fp.pot = pot;
   fp.nn_id = nn_id;
   fp.nn_r2 = nn_r2;
@@ -459,6 +466,24 @@ int collect_errors(nbx_ctx *c) {
   return errors_from(c, h);
 }
 
+// Shared by nbx_force_dev and nbx_force8_dev (d_crackle: order 8 only).
+int force_dev(nbx_ctx *c, void *stream, int ni, const int32_t *d_i_addr, double eps2, const double *d_h2,
+              double *d_acc, double *d_jerk, double *d_snap, double *d_crackle, double *d_pot, int64_t *d_nn_id,
+              double *d_nn_r2, int32_t *d_nbr_count, int64_t *d_nbr_ids) {
+  if (ni < 0) return fail(c, NBX_ERR_ARG, "ni < 0");
+  if (ni > c->cfg.ni_max) return fail(c, NBX_ERR_CAPACITY, "ni=%d > ni_max=%d", ni, c->cfg.ni_max);
+  if (ni == 0) return NBX_OK;
+  if (!d_i_addr || !d_acc || (!d_jerk && c->cfg.order != 2) || !d_pot || !d_nn_id || !d_nn_r2)
+    return fail(c, NBX_ERR_ARG, "NULL device array");
+  if (c->cfg.order >= 6 && !d_snap) return fail(c, NBX_ERR_ARG, "orders 6 and 8 need d_snap");
+  if (c->cfg.order == 8 && !d_crackle) return fail(c, NBX_ERR_ARG, "order 8 needs d_crackle");
+  if (d_h2 && (c->cfg.nbr_max == 0 || !d_nbr_count || !d_nbr_ids))
+    return fail(c, NBX_ERR_ARG, "neighbour lists need nbr_max > 0 and count/id arrays");
+  if (c->nj < 1) return fail(c, NBX_ERR_STATE, "no sources in use (nbx_set_nj)");
+  return enqueue_force(c, static_cast<hipStream_t>(stream), ni, d_i_addr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                       eps2, d_h2, d_acc, d_jerk, d_snap, d_crackle, d_pot, d_nn_id, d_nn_r2, d_nbr_count, d_nbr_ids);
+}
+
 }  // namespace
 
 extern "C" {
@@ -482,8 +507,8 @@ int nbx_open(nbx_ctx **out, const nbx_config *cfg) {
   if (!out) return fail(nullptr, NBX_ERR_ARG, "out is NULL");
   *out = nullptr;
   if (!cfg) return fail(nullptr, NBX_ERR_ARG, "cfg is NULL");
-  if (cfg->order != 2 && cfg->order != 4 && cfg->order != 6)
-    return fail(nullptr, NBX_ERR_ARG, "order must be 2, 4 or 6");
+  if (cfg->order != 2 && cfg->order != 4 && cfg->order != 6 && cfg->order != 8)
+    return fail(nullptr, NBX_ERR_ARG, "order must be 2, 4, 6 or 8");
   if (!valid_prec(cfg->precision)) return fail(nullptr, NBX_ERR_ARG, "precision must be NBX_FP64 or NBX_MIXED");
   if (cfg->nj_max < 1 || cfg->ni_max < 1 || cfg->nbr_max < 0)
     return fail(nullptr, NBX_ERR_ARG, "nj_max and ni_max must be >= 1, nbr_max >= 0");
@@ -511,10 +536,10 @@ int nbx_open(nbx_ctx **out, const nbx_config *cfg) {
   rc = rc ? rc : alloc_n(c, &c->src.pos_mass, nj);
   rc = rc ? rc : alloc_n(c, &c->src.vel_time, nj);
   rc = rc ? rc : alloc_n(c, &c->src.acc_jrk, 6 * nj);
-  if (cfg->order == 6) rc = rc ? rc : alloc_n(c, &c->src.snp_crk, 6 * nj);
+  if (cfg->order >= 6) rc = rc ? rc : alloc_n(c, &c->src.snp_crk, 6 * nj);
   rc = rc ? rc : alloc_n(c, &c->src.id, nj);
   rc = rc ? rc : alloc_n(c, &c->d_iaddr, ni);
-  rc = rc ? rc : alloc_n(c, &c->d_out, kErrDoubles + 12 * ni);
+  rc = rc ? rc : alloc_n(c, &c->d_out, kErrDoubles + 15 * ni);
   if (cfg->nbr_max > 0) {
     rc = rc ? rc : alloc_n(c, &c->d_h2, ni);
     rc = rc ? rc : alloc_n(c, &c->d_nbr_cnt, ni);
@@ -573,8 +598,8 @@ int nbx_set_j(nbx_ctx *c, int n, const int32_t *addr, const int64_t *id, const d
   const bool two = c->cfg.order == 2;
   if (!addr || !id || !m || !t || !x || (!two && (!v || !a || !jerk)))
     return fail(c, NBX_ERR_ARG, "NULL input array");
-  const bool six = c->cfg.order == 6;
-  if (six && (!snap || !crackle)) return fail(c, NBX_ERR_ARG, "order 6 needs snap and crackle");
+  const bool six = c->cfg.order >= 6;
+  if (six && (!snap || !crackle)) return fail(c, NBX_ERR_ARG, "orders 6 and 8 need snap and crackle");
   int hi = -1;
   for (int k = 0; k < n; ++k) {
     if (addr[k] < 0 || addr[k] >= c->cfg.nj_max)
@@ -667,8 +692,8 @@ int nbx_force(nbx_ctx *c, int ni, const int32_t *i_addr, double eps2, const doub
   }
   out_layout(c, ni);
   int rc = enqueue_force(c, c->stream, ni, c->d_iaddr, nullptr, nullptr, nullptr, nullptr, nullptr, eps2,
-                         h2 ? c->d_h2 : nullptr, c->d_acc, c->d_jrk, c->d_snp, c->d_pot, c->d_nnid, c->d_nnr2,
-                         c->d_nbr_cnt, c->d_nbr_ids);
+                         h2 ? c->d_h2 : nullptr, c->d_acc, c->d_jrk, c->d_snp, c->d_crk, c->d_pot, c->d_nnid,
+                         c->d_nnr2, c->d_nbr_cnt, c->d_nbr_ids);
   if (rc < 0) return rc;
   c->last_ni = ni;
   c->last_nbr = h2 != nullptr;
@@ -680,6 +705,7 @@ int nbx_force_ext(nbx_ctx *c, int ni, const int64_t *id, const double *x, const 
   if (int rc = check_ctx(c)) return rc;
   if (ni < 0) return fail(c, NBX_ERR_ARG, "ni < 0");
   if (ni > c->cfg.ni_max) return fail(c, NBX_ERR_CAPACITY, "ni=%d > ni_max=%d", ni, c->cfg.ni_max);
+  if (c->cfg.order == 8) return fail(c, NBX_ERR_ARG, "explicit sinks are not available at order 8");
   if (ni > 0 && (!id || !x || (!v && c->cfg.order != 2))) return fail(c, NBX_ERR_ARG, "NULL sink array");
   if (ni > 0 && c->cfg.order == 6 && !a) return fail(c, NBX_ERR_ARG, "order 6 needs the sink accelerations");
   if (h2 && c->cfg.nbr_max == 0) return fail(c, NBX_ERR_ARG, "neighbour lists need nbr_max > 0");
@@ -729,7 +755,7 @@ int nbx_force_ext(nbx_ctx *c, int ni, const int64_t *id, const double *x, const 
   out_layout(c, ni);
   int rc = enqueue_force(c, s, ni, nullptr, c->d_ext_self, c->d_ext_id, c->d_ext_x, c->d_ext_v,
                          c->cfg.order == 6 ? c->d_ext_a : nullptr, eps2, h2 ? c->d_h2 : nullptr, c->d_acc,
-                         c->d_jrk, c->d_snp, c->d_pot, c->d_nnid, c->d_nnr2, c->d_nbr_cnt, c->d_nbr_ids);
+                         c->d_jrk, c->d_snp, nullptr, c->d_pot, c->d_nnid, c->d_nnr2, c->d_nbr_cnt, c->d_nbr_ids);
   if (rc < 0) return rc;
   c->last_ni = ni;
   c->last_nbr = h2 != nullptr;
@@ -772,6 +798,18 @@ int nbx_get_force(nbx_ctx *c, double *acc, double *jerk, double *snap, double *p
   if (pot) std::memcpy(pot, from(c->d_pot), n * 8);
   if (nn_id) std::memcpy(nn_id, from(c->d_nnid), n * 8);
   if (nn_r2) std::memcpy(nn_r2, from(c->d_nnr2), n * 8);
+  return rc;
+}
+
+int nbx_get_crackle(nbx_ctx *c, double *crackle) {
+  if (int rc = check_ctx(c)) return rc;
+  if (c->cfg.order != 8) return fail(c, NBX_ERR_ARG, "crackle is computed at order 8 only");
+  if (c->last_ni < 0) return fail(c, NBX_ERR_STATE, "nbx_get_crackle before nbx_force");
+  if (!crackle) return fail(c, NBX_ERR_ARG, "crackle is NULL");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const int rc = collect_errors(c);
+  if (rc < 0) return rc;
+  if (c->last_ni > 0) HIP_TRY(c, hipMemcpy(crackle, c->d_crk, (size_t)c->last_ni * 24, hipMemcpyDeviceToHost));
   return rc;
 }
 
@@ -827,7 +865,7 @@ int nbx_get_j(nbx_ctx *c, int n, const int32_t *addr, int64_t *id, double *m, do
   for (int k = 0; k < n; ++k)
     if (addr[k] < 0 || addr[k] >= c->cfg.nj_max)
       return fail(c, NBX_ERR_ARG, "addr[%d]=%d outside [0, %d)", k, addr[k], c->cfg.nj_max);
-  const bool six = c->cfg.order == 6;
+  const bool six = c->cfg.order >= 6;
   // staging: addr | id | m | t | x v a jerk snap crackle
   const size_t bytes = (size_t)n * (16 + 8 + 8 + 8 + 6 * 24);
   if (int rc = grow(c, c->up, bytes)) return rc;
@@ -867,7 +905,8 @@ int nbx_set_j_dev(nbx_ctx *c, void *stream, int n, const int32_t *d_addr, const 
   if (n > c->cfg.nj_max) return fail(c, NBX_ERR_CAPACITY, "n=%d > nj_max=%d", n, c->cfg.nj_max);
   if (!d_addr || !d_id || !d_m || !d_t || !d_x || (c->cfg.order != 2 && (!d_v || !d_a || !d_jerk)))
     return fail(c, NBX_ERR_ARG, "NULL input array");
-  if (c->cfg.order == 6 && (!d_snap || !d_crackle)) return fail(c, NBX_ERR_ARG, "order 6 needs snap and crackle");
+  if (c->cfg.order >= 6 && (!d_snap || !d_crackle))
+    return fail(c, NBX_ERR_ARG, "orders 6 and 8 need snap and crackle");
   HIP_TRY(c, launch_jupdate(c->cfg.order, c->src, c->cfg.nj_max, n, d_addr, d_id, d_m, d_t, d_x, d_v, d_a, d_jerk,
                             d_snap, d_crackle, c->d_err, static_cast<hipStream_t>(stream)));
   c->bs.ready = false;
@@ -878,17 +917,18 @@ int nbx_force_dev(nbx_ctx *c, void *stream, int ni, const int32_t *d_i_addr, dou
                   double *d_acc, double *d_jerk, double *d_snap, double *d_pot, int64_t *d_nn_id, double *d_nn_r2,
                   int32_t *d_nbr_count, int64_t *d_nbr_ids) {
   if (int rc = check_ctx(c)) return rc;
-  if (ni < 0) return fail(c, NBX_ERR_ARG, "ni < 0");
-  if (ni > c->cfg.ni_max) return fail(c, NBX_ERR_CAPACITY, "ni=%d > ni_max=%d", ni, c->cfg.ni_max);
-  if (ni == 0) return NBX_OK;
-  if (!d_i_addr || !d_acc || (!d_jerk && c->cfg.order != 2) || !d_pot || !d_nn_id || !d_nn_r2)
-    return fail(c, NBX_ERR_ARG, "NULL device array");
-  if (c->cfg.order == 6 && !d_snap) return fail(c, NBX_ERR_ARG, "order 6 needs d_snap");
-  if (d_h2 && (c->cfg.nbr_max == 0 || !d_nbr_count || !d_nbr_ids))
-    return fail(c, NBX_ERR_ARG, "neighbour lists need nbr_max > 0 and count/id arrays");
-  if (c->nj < 1) return fail(c, NBX_ERR_STATE, "no sources in use (nbx_set_nj)");
-  return enqueue_force(c, static_cast<hipStream_t>(stream), ni, d_i_addr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                       eps2, d_h2, d_acc, d_jerk, d_snap, d_pot, d_nn_id, d_nn_r2, d_nbr_count, d_nbr_ids);
+  if (c->cfg.order == 8) return fail(c, NBX_ERR_ARG, "order 8 forces go through nbx_force8_dev");
+  return force_dev(c, stream, ni, d_i_addr, eps2, d_h2, d_acc, d_jerk, d_snap, nullptr, d_pot, d_nn_id, d_nn_r2,
+                   d_nbr_count, d_nbr_ids);
+}
+
+int nbx_force8_dev(nbx_ctx *c, void *stream, int ni, const int32_t *d_i_addr, double eps2, const double *d_h2,
+                   double *d_acc, double *d_jerk, double *d_snap, double *d_crackle, double *d_pot,
+                   int64_t *d_nn_id, double *d_nn_r2, int32_t *d_nbr_count, int64_t *d_nbr_ids) {
+  if (int rc = check_ctx(c)) return rc;
+  if (c->cfg.order != 8) return fail(c, NBX_ERR_ARG, "nbx_force8_dev needs an order-8 context");
+  return force_dev(c, stream, ni, d_i_addr, eps2, d_h2, d_acc, d_jerk, d_snap, d_crackle, d_pot, d_nn_id, d_nn_r2,
+                   d_nbr_count, d_nbr_ids);
 }
 
 int nbx_force_vjp_dev(nbx_ctx *c, void *stream, int n, const double *d_m, const double *d_x, const double *d_v,
@@ -1053,7 +1093,7 @@ int bs_force(nbx_ctx *c, int ni, double t, const BlockStepParams *step = nullptr
   c->predicted = true;
   return enqueue_force(c, c->stream, ni, static_cast<const int32_t *>(c->bs.list.p), nullptr, nullptr, nullptr,
                        nullptr, nullptr, c->bs.p.eps2, nullptr, static_cast<double *>(c->bs.acc.p),
-                       static_cast<double *>(c->bs.jrk.p), static_cast<double *>(c->bs.snp.p),
+                       static_cast<double *>(c->bs.jrk.p), static_cast<double *>(c->bs.snp.p), nullptr,
                        static_cast<double *>(c->bs.pot.p), static_cast<int64_t *>(c->bs.nnid.p),
                        static_cast<double *>(c->bs.nnr2.p), nullptr, nullptr, step, t, fused);
 }
@@ -1341,8 +1381,8 @@ int nbx_tune(nbx_ctx *c, int ni_max, int32_t *shapes_out, int n_classes) {
       c->force_shape = &cand;
       auto launch = [&]() {
         return enqueue_force(c, c->stream, ni, c->d_iaddr, nullptr, nullptr, nullptr, nullptr, nullptr, 0.0, nullptr,
-                             c->d_acc, c->d_jrk ? c->d_jrk : c->d_acc, c->d_snp, c->d_pot, c->d_nnid, c->d_nnr2,
-                             nullptr, nullptr);
+                             c->d_acc, c->d_jrk ? c->d_jrk : c->d_acc, c->d_snp, c->d_crk, c->d_pot, c->d_nnid,
+                             c->d_nnr2, nullptr, nullptr);
       };
       if (int rc = launch()) return rc;  // warm-up, and an estimate of the launch time
       HIP_TRY(c, hipEventRecord(ev.e0, c->stream));

@@ -46,6 +46,7 @@ EXPORTS = (
     "nbx_get_predicted", "nbx_get_j", "nbx_set_j_dev", "nbx_force_dev", "nbx_sync", "nbx_launch_shape",
     "nbx_batch_setup", "nbx_batch_tune", "nbx_batch_force_dev", "nbx_force_vjp_dev",
     "nbx_bs_init", "nbx_bs_step", "nbx_bs_run", "nbx_bs_get_state", "nbx_bs_energy", "nbx_tune",
+    "nbx_get_crackle", "nbx_force8_dev",
 )
 NBX_BATCH_NMAX = 128
 
@@ -137,6 +138,8 @@ def load(path: str = LIB_PATH):
         "nbx_bs_get_state": ([_P, _P, _P, _P, _P, _P, ctypes.POINTER(nbx_bs_stats)], _I),
         "nbx_bs_energy": ([_P, _P, _P], _I),
         "nbx_tune": ([_P, _I, _P, _I], _I),
+        "nbx_get_crackle": ([_P, _P], _I),
+        "nbx_force8_dev": ([_P, _P, _I, _P, _D] + [_P] * 10, _I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -261,11 +264,12 @@ def nbx_force_ext(ctx, id, x, v, a, eps2, h2=None):
 
 
 def nbx_get_force(ctx, ni, order=4):
-    """Results of the last force call on ni sinks, as a dict of numpy arrays (plus 'status')."""
+    """Results of the last force call on ni sinks, as a dict of numpy arrays (plus 'status');
+    order 8 adds 'crackle' (read by nbx_get_crackle)."""
     out = {
         "acc": np.empty((ni, 3)),
         "jerk": np.empty((ni, 3)) if order != 2 else None,
-        "snap": np.empty((ni, 3)) if order == 6 else None,
+        "snap": np.empty((ni, 3)) if order >= 6 else None,
         "pot": np.empty(ni),
         "nn_id": np.empty(ni, dtype=np.int64),
         "nn_r2": np.empty(ni),
@@ -273,7 +277,15 @@ def nbx_get_force(ctx, ni, order=4):
     rc = load().nbx_get_force(ctx, _ptr(out["acc"]), _ptr(out["jerk"]), _ptr(out["snap"]), _ptr(out["pot"]),
                               _ptr(out["nn_id"]), _ptr(out["nn_r2"]))
     out["status"] = _check(ctx, rc)
+    if order == 8:
+        out["crackle"] = nbx_get_crackle(ctx, ni)
     return out
+
+
+def nbx_get_crackle(ctx, ni):
+    crackle = np.empty((ni, 3))
+    _check(ctx, load().nbx_get_crackle(ctx, _ptr(crackle)))
+    return crackle
 
 
 def nbx_get_nbr(ctx, ni, nbr_max):
@@ -295,7 +307,7 @@ def nbx_get_j(ctx, addr, order=4):
     addr = np.ascontiguousarray(addr, dtype=np.int32)
     n = addr.shape[0]
     out = {"id": np.empty(n, dtype=np.int64), "m": np.empty(n), "t": np.empty(n)}
-    for k in ("x", "v", "a", "jerk") + (("snap", "crackle") if order == 6 else ()):
+    for k in ("x", "v", "a", "jerk") + (("snap", "crackle") if order >= 6 else ()):
         out[k] = np.empty((n, 3))
     rc = load().nbx_get_j(ctx, n, _ptr(addr), _ptr(out["id"]), _ptr(out["m"]), _ptr(out["t"]), _ptr(out["x"]),
                           _ptr(out["v"]), _ptr(out["a"]), _ptr(out["jerk"]), _ptr(out.get("snap")),
@@ -315,6 +327,14 @@ def nbx_force_dev(ctx, stream, ni, d_i_addr, eps2, d_h2, d_acc, d_jerk, d_snap, 
     rc = load().nbx_force_dev(ctx, _stream(stream), int(ni), _dptr(d_i_addr), float(eps2), _dptr(d_h2),
                               _dptr(d_acc), _dptr(d_jerk), _dptr(d_snap), _dptr(d_pot), _dptr(d_nn_id),
                               _dptr(d_nn_r2), _dptr(d_nbr_count), _dptr(d_nbr_ids))
+    return _check(ctx, rc)
+
+
+def nbx_force8_dev(ctx, stream, ni, d_i_addr, eps2, d_h2, d_acc, d_jerk, d_snap, d_crackle, d_pot, d_nn_id,
+                   d_nn_r2, d_nbr_count=None, d_nbr_ids=None):
+    rc = load().nbx_force8_dev(ctx, _stream(stream), int(ni), _dptr(d_i_addr), float(eps2), _dptr(d_h2),
+                               _dptr(d_acc), _dptr(d_jerk), _dptr(d_snap), _dptr(d_crackle), _dptr(d_pot),
+                               _dptr(d_nn_id), _dptr(d_nn_r2), _dptr(d_nbr_count), _dptr(d_nbr_ids))
     return _check(ctx, rc)
 
 
@@ -453,7 +473,7 @@ class Context:
         addr = np.arange(src.n, dtype=np.int32) if addr is None else addr
         return nbx_set_j(self.ctx, addr, src.ids, src.m, src.t, src.x, src.v, src.a,
                          src.jerk if self.order != 2 else None,
-                         src.snap if self.order == 6 else None, src.crackle if self.order == 6 else None)
+                         src.snap if self.order >= 6 else None, src.crackle if self.order >= 6 else None)
 
     def predict(self, t):
         return nbx_predict(self.ctx, t)

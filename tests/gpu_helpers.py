@@ -59,9 +59,15 @@ def check_nn(out, ref, xp, sel_addr, prec, ids):
     ok = ~none
     id_to_addr = {int(i): a for a, i in enumerate(ids)}
     addr_nn = np.array([id_to_addr[int(i)] for i in nn[ok]])
-    d = xp[addr_nn] - xp[sel_addr[ok]]
+    xs, xn = xp[sel_addr[ok]], xp[addr_nn]
+    d = xn - xs
     r2_exact = np.sum(d * d, axis=1)
-    np.testing.assert_allclose(out["nn_r2"][ok], r2_exact, rtol=1e-13, atol=0)  # r2 from the GPU predictor vs the oracle's
+    # r2 from the GPU's predicted positions against the oracle's: the two predictors agree to a
+    # few units of rounding in x, and d = x_j - x_i cancels, so the difference scales with
+    # eps |x| |d| rather than with r2
+    scale = np.maximum(np.linalg.norm(xs, axis=1), np.linalg.norm(xn, axis=1)) * np.sqrt(r2_exact)
+    dr2 = np.abs(out["nn_r2"][ok] - r2_exact)
+    assert np.all(dr2 <= 1e-13 * r2_exact + 16 * np.finfo(np.float64).eps * scale), dr2.max()
     if prec == nbx.NBX_FP64:
         assert np.all(r2_exact <= ref["nn_r2"][ok] * (1 + 1e-14))
     else:

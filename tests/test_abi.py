@@ -16,7 +16,7 @@ HEADER = os.path.join(ROOT, "include", "nbx.h")
 def _declared():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(nbx_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(nbx_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_and_binding_agree():
@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_version():
-    assert nbx.nbx_version() == 10100
+    assert nbx.nbx_version() == 10200
 
 
 def test_argument_errors_without_device():
