@@ -95,6 +95,8 @@ def parse():
     ap.add_argument("--order6", action="store_true",
                     help="also time 6th-order forces with neighbour lists on a 1048576-body Plummer/Salpeter "
                          "cluster (eps2=1e-8, h2=1e-4, at most 256 neighbours), N_i in {1024, 65536, 1048576}")
+    ap.add_argument("--order8", action="store_true",
+                    help="also time 8th-order forces (acc, jerk, snap, crackle) on the --order6 workload")
     return ap.parse_args()
 
 
@@ -246,22 +248,23 @@ def cpu_baseline(src, seconds):
                               "sample": "same, %d sinks (%.2e interactions, %.1f s)" % (ns1, ns1 * float(N), dt1)}}
 
 
-def order6(torch, nbx, ics, dev, steps):
-    """Config-3 points: 6th order, Salpeter masses, neighbour lists; kernel time per precision."""
+def order6(torch, nbx, ics, dev, steps, order=6):
+    """Config-3 points: 6th (or 8th) order, Salpeter masses, neighbour lists; kernel time per precision."""
     import numpy as np
 
     n, eps2, h2, nbr_max = 1 << 20, 1e-8, 1e-4, 256
-    src = ics.make_sources(n, seed=3, order=6, masses="salpeter")
+    flops = 128 if order == 8 else 79
+    src = ics.make_sources(n, seed=3, order=order, masses="salpeter")
     stream = torch.cuda.current_stream()
     T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
     f64, i64, i32 = torch.float64, torch.int64, torch.int32
-    ctx = nbx.Context(order=6, precision=nbx.NBX_MIXED, nj_max=n, ni_max=n, nbr_max=nbr_max)
+    ctx = nbx.Context(order=order, precision=nbx.NBX_MIXED, nj_max=n, ni_max=n, nbr_max=nbr_max)
     nbx.nbx_set_j_dev(ctx.ctx, stream, n, T(np.arange(n), i32), T(src.ids, i64), T(src.m, f64), T(src.t, f64),
                       T(src.x, f64), T(src.v, f64), T(src.a, f64), T(src.jerk, f64), T(src.snap, f64),
                       T(src.crackle, f64))
     nbx.nbx_set_nj(ctx.ctx, n)
     nbx.nbx_predict(ctx.ctx, 0.0)
-    out = [torch.empty((n, 3), dtype=f64, device=dev) for _ in range(3)]
+    out = [torch.empty((n, 3), dtype=f64, device=dev) for _ in range(4 if order == 8 else 3)]
     pot, nnr2 = torch.empty(n, dtype=f64, device=dev), torch.empty(n, dtype=f64, device=dev)
     nnid, cnt = torch.empty(n, dtype=i64, device=dev), torch.empty(n, dtype=i32, device=dev)
     ids = torch.empty((n, nbr_max), dtype=i64, device=dev)
@@ -275,8 +278,12 @@ def order6(torch, nbx, ics, dev, steps):
             reps = 1 if ni == n else steps
 
             def go():
-                nbx.nbx_force_dev(ctx.ctx, stream, ni, sel, eps2, d_h2, out[0], out[1], out[2], pot, nnid, nnr2,
-                                  cnt, ids)
+                if order == 8:
+                    nbx.nbx_force8_dev(ctx.ctx, stream, ni, sel, eps2, d_h2, out[0], out[1], out[2], out[3], pot,
+                                       nnid, nnr2, cnt, ids)
+                else:
+                    nbx.nbx_force_dev(ctx.ctx, stream, ni, sel, eps2, d_h2, out[0], out[1], out[2], pot, nnid,
+                                      nnr2, cnt, ids)
 
             go()
             torch.cuda.synchronize()
@@ -289,15 +296,18 @@ def order6(torch, nbx, ics, dev, steps):
             ms = e0.elapsed_time(e1) / reps
             row[name + "_kernel_ms"] = round(ms, 4)
             row[name + "_int_s"] = float("%.4g" % (ni * float(n) / (ms * 1e-3)))
+            peak = PEAK_FP64 if prec == nbx.NBX_FP64 else PEAK_FP32
+            row[name + "_roofline_frac"] = round(flops * ni * float(n) / (ms * 1e-3) / 1e12 / peak, 4)
         row["speedup"] = round(row["fp64_kernel_ms"] / row["mixed_kernel_ms"], 3)
         row["mean_neighbours"] = round(float(cnt[:ni].double().mean().item()), 3)
         rows.append(row)
-        print("bench: order6 %s" % json.dumps(row), file=sys.stderr, flush=True)
+        print("bench: order%d %s" % (order, json.dumps(row)), file=sys.stderr, flush=True)
     status = nbx.nbx_sync(ctx.ctx, stream)
     ctx.close()
+    what = "8th-order acc+jerk+snap+crackle" if order == 8 else "6th-order acc+jerk+snap"
     return {"workload": "Plummer N=1048576, Salpeter masses (slope -2.35, 0.1-100, total 1), eps2=1e-8, "
-                        "6th-order acc+jerk+snap+pot+NN+neighbour lists (h2=1e-4, max 256)",
-            "flops_per_interaction": 79, "rows": rows, "list_status": status}
+                        "%s+pot+NN+neighbour lists (h2=1e-4, max 256)" % what,
+            "flops_per_interaction": flops, "rows": rows, "list_status": status}
 
 
 def order2(torch, nbx, ics, dev, steps):
@@ -616,6 +626,7 @@ def main():
     bs4 = (blockstep(torch, nbx, nbody_ics, [int(k) for k in args.blockstep4.split(",")], tune=not args.no_tune,
                      order=4) if args.blockstep4 else None)
     o6 = order6(torch, nbx, nbody_ics, dev, max(2, args.steps // 10)) if args.order6 else None
+    o8 = order6(torch, nbx, nbody_ics, dev, max(2, args.steps // 10), order=8) if args.order8 else None
     bt = batch(torch, nbx, nbody_ics, dev, max(20, args.steps)) if args.batch else None
     adj = adjoint(torch, nbx, nbody_ics, dev, max(3, args.steps // 5)) if args.adjoint else None
 
@@ -678,6 +689,8 @@ def main():
         line["blockstep4"] = bs4
     if o6 is not None:
         line["order6"] = o6
+    if o8 is not None:
+        line["order8"] = o8
     if bt is not None:
         line["batch"] = bt
     if adj is not None:

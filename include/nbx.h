@@ -32,10 +32,11 @@
  * Sources with the sink's own id are excluded from every output.  Jerk, snap
  * and crackle are the time derivatives of the softened acceleration along the
  * predicted motion, as a 4th/6th/8th-order Hermite integrator needs them
- * (Results; Results > Sixth order performance; order 8 is the next step the
- * Conclusions name for the double-precision storage: it predicts the jerk of
- * every source and sink as well, j + s dt + c dt^2/2).  Order 2 is the GRAPE-5 mode
- * for a 2nd-order leapfrog (Background; Conclusions): acc and pot only, from
+ * (Results; Results > Sixth order performance; order 8 is the expansion that
+ * Methods > Numerical Accuracy and the Conclusion name for the double-precision
+ * storage: it predicts the jerk of every source and sink as well,
+ * j + s dt + c dt^2/2).  Order 2 is the GRAPE-5 mode
+ * for a 2nd-order leapfrog (Background; Conclusion): acc and pot only, from
  * positions and masses; its predictor stops at the acceleration term.
  *
  * Nearest neighbour (Results; Discussion > CPU: particle id and distance):
@@ -172,7 +173,7 @@ int nbx_force_ext(nbx_ctx *ctx, int ni, const int64_t *id, const double *x, cons
 int nbx_get_force(nbx_ctx *ctx, double *acc, double *jerk, double *snap, double *pot,
                   int64_t *nn_id, double *nn_r2);
 
-/* Order 8 (Conclusions: the next expansion of the double-precision storage): wait for the last
+/* Order 8 (Conclusion: the next expansion of the double-precision storage): wait for the last
  * nbx_force and copy its crackle [ni][3] to a caller-owned host array.  NBX_ERR_ARG for another
  * order or NULL; NBX_ERR_STATE before the first force call; error counters as nbx_get_force. */
 int nbx_get_crackle(nbx_ctx *ctx, double *crackle);
@@ -214,7 +215,7 @@ int nbx_force_dev(nbx_ctx *ctx, void *stream, int ni, const int32_t *d_i_addr, d
                   double *d_pot, int64_t *d_nn_id, double *d_nn_r2, int32_t *d_nbr_count,
                   int64_t *d_nbr_ids);
 
-/* Order 8 (Conclusions): as nbx_force_dev, with d_snap and d_crackle [ni][3] both required.
+/* Order 8 (Conclusion): as nbx_force_dev, with d_snap and d_crackle [ni][3] both required.
  * NBX_ERR_ARG on a context of another order. */
 int nbx_force8_dev(nbx_ctx *ctx, void *stream, int ni, const int32_t *d_i_addr, double eps2,
                    const double *d_h2, double *d_acc, double *d_jerk, double *d_snap,
@@ -330,7 +331,7 @@ int nbx_bs_energy(nbx_ctx *ctx, double *ekin, double *epot);
 int nbx_sync(nbx_ctx *ctx, void *stream);
 
 /* Launch-shape tuner.  The paper's library ships tuning runs that pick the block configuration per
- * GPU (Results > Thread-block configuration; Conclusions).  For every N_i class 2^k up to ni_max
+ * GPU (Results > Thread-block configuration; Conclusion).  For every N_i class 2^k up to ni_max
  * (capped at ni_max of the context and the sources in use) this times candidate shapes of the
  * gravity kernel (lanes per sink, sinks per lane, source splits) on the current sources at the
  * current prediction time and precision, with ni evenly strided source addresses as sinks, and

@@ -41,7 +41,7 @@
  *  - oracle_force8, oracle_predict_jerk: the 8th-order mode.  The paper keeps
  *    its data in double precision so that higher-order Hermite integrators,
  *    6th and 8th order (Nitadori & Makino 2008), can be added without
- *    changing the host code (Methods > Numerical Accuracy; Conclusions: the
+ *    changing the host code (Methods > Numerical Accuracy; Conclusion: the
  *    library could be expanded with an 8th-order integrator).  That needs the
  *    third derivative of the pair acceleration (crackle) along the predicted
  *    motion, which also uses the relative jerk j = j_j - j_i:

@@ -172,7 +172,7 @@ hipError_t launch_bs_start(int order, const BlockStepParams &bp, hipStream_t str
 hipError_t launch_iota(int32_t *p, int n, hipStream_t stream);
 
 // Launch-shape rule (defined in nbx_kernels.hip).
-LaunchShape choose_shape(int ni, int nj_pad, int prec);
+LaunchShape choose_shape(int ni, int nj_pad, int prec, int order);
 int values_per_sink(int order);  // doubles per sink in the split-combine scratch
 
 }  // namespace nbx

@@ -1500,6 +1500,7 @@ int values_per_sink(int order) { return order == 8 ? 13 : (order == 6 ? 10 : (or
 //     interactions per tile: Q >= 16 unless there are fewer sinks than that.
 //   * Two sinks per lane (Q = 512) pay off only at large N_i (>= 65536), where each workgroup
 //     sees many tiles; below that the fixed per-workgroup work of the second sink dominates.
+//     Mixed precision and orders 2 to 6 only.
 // Q runs from ni rounded up to a power of two (at most 256, or 512 at large N_i) down to that
 // floor and the first Q that reaches the workgroup target wins (the largest reuse of each staged
 // source); if none does, the floor is used with the largest S allowed.  NBX_SHAPE="L,P,S" in the
@@ -1510,7 +1511,7 @@ static int ilog2(int v) {
   return l;
 }
 
-LaunchShape choose_shape(int ni, int nj_pad, int prec) {
+LaunchShape choose_shape(int ni, int nj_pad, int prec, int order) {
   LaunchShape ls;
   const int ntiles = nj_pad / kTile > 0 ? nj_pad / kTile : 1;
   // workgroups to aim for: few sinks take ~512 (two per CU) so that each staged, predicted source
@@ -1537,8 +1538,10 @@ LaunchShape choose_shape(int ni, int nj_pad, int prec) {
   int qmin = 1;
   while (qmin < ni && qmin < 16) qmin *= 2;
   int qcover = 1;  // never more sink slots than the next power of two of ni
-  // two sinks per lane pay off only in FP32 arithmetic (FP64 accumulators double the registers)
-  const int qtop = ni >= 65536 && prec == NBX_MIXED ? 2 * kThreads : kThreads;
+  // two sinks per lane pay off only in FP32 arithmetic (FP64 accumulators double the registers),
+  // and not at order 8, where the second sink's 13 sums and jerk push the lane past 256 registers
+  // and the launch loses half its waves
+  const int qtop = ni >= 65536 && prec == NBX_MIXED && order <= 6 ? 2 * kThreads : kThreads;
   while (qcover < ni && qcover < qtop) qcover *= 2;
   int Q = qcover > qmin ? qcover : qmin;
   for (; Q >= qmin; Q /= 2) {

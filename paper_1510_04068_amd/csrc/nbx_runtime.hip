@@ -283,7 +283,7 @@ LaunchShape ctx_shape(const nbx_ctx *c, int ni, int nj_pad) {
              c->tuned[c->precision][ni_class(ni)].lanes_log2 >= 0) {
     t = &c->tuned[c->precision][ni_class(ni)];
   }
-  if (!t) return choose_shape(ni, nj_pad, c->precision);
+  if (!t) return choose_shape(ni, nj_pad, c->precision, c->cfg.order);
   LaunchShape ls;
   ls.lanes_log2 = t->lanes_log2;
   ls.sinks_per_lane = t->sinks_per_lane;

@@ -1,4 +1,4 @@
-"""Order 8 (acc, jerk, snap, crackle; Conclusions: the next expansion of the double-precision
+"""Order 8 (acc, jerk, snap, crackle; Conclusion: the next expansion of the double-precision
 storage) against the FP64 oracle, element by element, on seeded inputs.
 
 Bounds per sink (max over sinks): acc and pot relative error as at the other orders (FP64 1e-13,
