@@ -862,8 +862,14 @@ __device__ __forceinline__ int nn_rescan(const ForceParams &fp, const typename T
 // source split w % S (split-fastest, so with S a multiple of 8 every split stays on one XCD and
 // its sources stay in that XCD's L2).
 // ---------------------------------------------------------------------------------------------
+// FP64 order 6 with one sink per lane needs 258-286 registers per lane with neighbour lists, which
+// leaves one wave per SIMD; capped at 256 (two waves) it spills a few values instead.
+template <int Order, int Prec, int P>
+constexpr int kForceWaves = (Order == 6 && Prec == NBX_FP64 && P == 1) ? 2 : 1;
+
 template <int Order, int Prec, int P, bool L1, bool Nbr>
-__global__ __launch_bounds__(kThreads) void k_force(const ForceParams fp) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kForceWaves<Order, Prec, P>)))
+void k_force(const ForceParams fp) {
   using Tr = typename TraitsSel<Order, Prec>::type;
   using T = typename Tr::Real;
   using Key = typename Tr::Key;
