@@ -862,10 +862,13 @@ __device__ __forceinline__ int nn_rescan(const ForceParams &fp, const typename T
 // source split w % S (split-fastest, so with S a multiple of 8 every split stays on one XCD and
 // its sources stay in that XCD's L2).
 // ---------------------------------------------------------------------------------------------
-// FP64 order 6 with one sink per lane needs 258-286 registers per lane with neighbour lists, which
-// leaves one wave per SIMD; capped at 256 (two waves) it spills a few values instead.
+// Waves per SIMD the FP64 gravity kernel with one sink per lane is held to: order 6 with
+// neighbour lists needs 258-286 registers per lane and order 8 326-380, which leaves one wave per
+// SIMD; capped at 256 (two waves) they spill a few values instead.  Order 4 needs 176-204 (two
+// waves); capped at 168 it runs three.  Measured faster in every case (old and new library
+// alternating on one box); the mixed kernels and two sinks per lane keep the compiler's choice.
 template <int Order, int Prec, int P>
-constexpr int kForceWaves = (Order == 6 && Prec == NBX_FP64 && P == 1) ? 2 : 1;
+constexpr int kForceWaves = (Prec != NBX_FP64 || P != 1) ? 1 : (Order >= 6 ? 2 : (Order == 4 ? 3 : 1));
 
 template <int Order, int Prec, int P, bool L1, bool Nbr>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kForceWaves<Order, Prec, P>)))
