@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     ap.add_argument("--sweep-reps", type=int, default=5, help="minimum timed steps per sweep point")
+    ap.add_argument("--sweep-ni", type=str, default="", metavar="N,N,...",
+                    help="time only these N_i in the sweep (default: 2^0 .. 2^17)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the launch-shape tuner (nbx_tune) and its tuned N_i sweep")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -583,8 +585,8 @@ def main():
             nbx.nbx_sync(ctx_t.ctx, stream)
             tune_s = time.perf_counter() - t0
             print("bench: tuned launch shapes in %.1f s" % tune_s, file=sys.stderr, flush=True)
-        for e in range(18):
-            ni = 1 << e
+        sweep_ni = [int(k) for k in args.sweep_ni.split(",")] if args.sweep_ni else [1 << e for e in range(18)]
+        for ni in sweep_ni:
             row = {"ni": ni}
             time_row(ctx, row, ni, "")
             if ctx_t is not None:
