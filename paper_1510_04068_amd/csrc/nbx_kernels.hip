@@ -865,13 +865,17 @@ __device__ __forceinline__ int nn_rescan(const ForceParams &fp, const typename T
 // Waves per SIMD the FP64 gravity kernel with one sink per lane is held to: order 6 with
 // neighbour lists needs 258-286 registers per lane and order 8 326-380, which leaves one wave per
 // SIMD; capped at 256 (two waves) they spill a few values instead.  Order 4 needs 176-204 (two
-// waves); capped at 168 it runs three.  Measured faster in every case (old and new library
-// alternating on one box); the mixed kernels and two sinks per lane keep the compiler's choice.
-template <int Order, int Prec, int P>
-constexpr int kForceWaves = (Prec != NBX_FP64 || P != 1) ? 1 : (Order >= 6 ? 2 : (Order == 4 ? 3 : 1));
+// waves); capped at 168 it runs three.  Measured with old and new library alternating on one box:
+// faster for orders 4 and 6 at every N_i timed; for order 8 faster with one lane per sink (N_i >=
+// 1024) but slower with several lanes per sink at N_i <= 64, where each workgroup runs one tile
+// and the spills of its set-up and reduction are not amortised, so order 8 caps only the former.
+// The mixed kernels and two sinks per lane keep the compiler's choice.
+template <int Order, int Prec, int P, bool L1>
+constexpr int kForceWaves =
+    (Prec != NBX_FP64 || P != 1 || (Order == 8 && !L1)) ? 1 : (Order >= 6 ? 2 : (Order == 4 ? 3 : 1));
 
 template <int Order, int Prec, int P, bool L1, bool Nbr>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kForceWaves<Order, Prec, P>)))
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kForceWaves<Order, Prec, P, L1>)))
 void k_force(const ForceParams fp) {
   using Tr = typename TraitsSel<Order, Prec>::type;
   using T = typename Tr::Real;
