@@ -20,8 +20,10 @@
 //     gfx950 the device-scope fence that would need per workgroup is the expensive part).
 //
 // Orders: 2 (the GRAPE-5 / leapfrog mode of the Background section: acceleration and potential
-// from positions and masses), 4 (adds the jerk) and 6 (adds the snap, from predicted
-// accelerations).  All three share the staging, the loop, the reductions and the combine.
+// from positions and masses), 4 (adds the jerk), 6 (adds the snap, from predicted
+// accelerations) and 8 (adds the crackle, from predicted jerks: the higher-order expansion that
+// Methods > Numerical Accuracy and the Conclusion name).  All four share the staging, the loop,
+// the reductions and the combine.
 //
 // Arithmetic per interaction (the pair terms of nbx.h):
 //   MIXED: dx = (xh_j - xh_i) + (xl_j - xl_i) in FP32 from double-single positions, FP32

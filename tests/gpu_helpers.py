@@ -20,9 +20,14 @@ def oracle_all(src, order, eps2, t, addr=None, h2=None, nbr_max=0):
     """Oracle forces on sinks taken by address from the predicted sources (all if addr is None)."""
     xp, vp, ap = oracle.predict(order, t, src.t, src.x, src.v, src.a, src.jerk, src.snap, src.crackle)
     sel = np.arange(src.n) if addr is None else np.asarray(addr)
-    ref = oracle.force(order, eps2, src.ids, src.m, xp, vp, src.ids[sel], xp[sel], vp[sel],
-                       aj=ap if order == 6 else None, ai=ap[sel] if order == 6 else None,
-                       h2=h2, nbr_max=nbr_max)
+    if order == 8:
+        jp = oracle.predict_jerk(t, src.t, src.jerk, src.snap, src.crackle)
+        ref = oracle.force8(eps2, src.ids, src.m, xp, vp, ap, jp, src.ids[sel], xp[sel], vp[sel], ap[sel], jp[sel],
+                            h2=h2, nbr_max=nbr_max)
+    else:
+        ref = oracle.force(order, eps2, src.ids, src.m, xp, vp, src.ids[sel], xp[sel], vp[sel],
+                           aj=ap if order == 6 else None, ai=ap[sel] if order == 6 else None,
+                           h2=h2, nbr_max=nbr_max)
     ref["xp"], ref["vp"], ref["ap"] = xp, vp, ap
     return ref
 

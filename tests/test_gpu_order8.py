@@ -253,3 +253,24 @@ def test_order8_device_path_and_errors():
                                   d["pot"].data_ptr(), d["nn_id"].data_ptr(), d["nn_r2"].data_ptr(), None,
                                   None) == nbx.NBX_ERR_ARG
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec", [nbx.NBX_FP64, nbx.NBX_MIXED])
+def test_order8_tuned_shapes(prec):
+    """The launch-shape tuner on an order-8 context: the shapes it keeps (which may put two sinks
+    on a lane) keep parity with the oracle."""
+    n, t, eps2 = 3000, 0.0, 1e-6
+    say("order8 tuned prec=%s n=%d seed=129" % (PREC_NAME[prec], n))
+    src = nbody_ics.make_sources(n, seed=129, order=8, masses="salpeter")
+    ref_all = oracle8(src, eps2, t, np.arange(n))
+    with nbx.Context(order=8, precision=prec, nj_max=n, ni_max=n) as ctx:
+        ctx.set_sources(src)
+        ctx.predict(t)
+        tab = ctx.tune(n)
+        say("  table (L, P, S) per class: %s" % tab.tolist())
+        ctx.predict(t)
+        for ni in (1, 300, 3000):
+            sel = nbody_ics.active_set(n, ni, seed=1300 + ni)
+            say("  ni=%d shape=%s" % (ni, ctx.launch_shape(ni)))
+            ctx.force(sel, eps2)
+            _compare(ctx.get_force(), _sub(ref_all, sel), prec, sel, src.ids, "  ni=%d" % ni)

@@ -10,16 +10,17 @@ import pytest
 
 import nbody_ics
 import paper_1510_04068_amd as nbx
-from gpu_helpers import PREC_NAME, check_nn, oracle_all, rel_err_vec, run_gpu, say, subset
+from gpu_helpers import PREC_NAME, check_nn, cond_err_vec, oracle_all, rel_err_vec, run_gpu, say, subset
 
 pytestmark = pytest.mark.gpu
 
 TOL = {nbx.NBX_FP64: 1e-13, nbx.NBX_MIXED: 1e-6}
+CRACKLE_TOL = {nbx.NBX_FP64: 2e-12, nbx.NBX_MIXED: 2e-5}  # condition-normalised, as in test_gpu_order8
 SHAPES = [(1, 1, 1), (1, 2, 1), (1, 2, 5), (2, 1, 3), (4, 1, 12), (16, 1, 7), (64, 1, 13), (256, 1, 12)]
 
 
 @pytest.mark.parametrize("prec", [nbx.NBX_FP64, nbx.NBX_MIXED])
-@pytest.mark.parametrize("order", [4, 6])
+@pytest.mark.parametrize("order", [4, 6, 8])
 def test_forced_shapes_agree(order, prec, monkeypatch):
     n, ni, eps2 = 3000, 700, 1e-4  # 12 tiles, the last one ragged
     say("shapes order=%d prec=%s n=%d ni=%d seed=80" % (order, PREC_NAME[prec], n, ni))
@@ -40,6 +41,10 @@ def test_forced_shapes_agree(order, prec, monkeypatch):
             mism = check_nn(out, ref, ref["xp"], sel, prec, src.ids)
             say("  L=%d P=%d S=%d: max rel acc %.2e pot %.2e nn-mismatch %d" % (L, P, S, e_acc, e_pot, mism))
             assert e_acc <= TOL[prec] and e_pot <= TOL[prec]
+            if order == 8:
+                e_c = cond_err_vec(out["crackle"], ref["crackle"], ref["cond"][:, 3]).max()
+                say("    crackle/cond %.2e" % e_c)
+                assert e_c <= CRACKLE_TOL[prec]
             if prec == nbx.NBX_FP64:
                 assert mism == 0
             outs.append(out)
