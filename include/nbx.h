@@ -160,9 +160,16 @@ int nbx_force(nbx_ctx *ctx, int ni, const int32_t *i_addr, double eps2, const do
 
 /* Forces on ni sinks given explicitly (they need not be sources): id[ni], x, v [ni][3] (v may be
  * NULL for order 2), a [ni][3] for order 6 (else NULL).  A source with the sink's id is excluded.  The sink state is used as
- * given (no prediction).  Otherwise as nbx_force.  Not available at order 8 (NBX_ERR_ARG). */
+ * given (no prediction).  Otherwise as nbx_force.  An order-8 context returns NBX_ERR_ARG: use
+ * nbx_force_ext8. */
 int nbx_force_ext(nbx_ctx *ctx, int ni, const int64_t *id, const double *x, const double *v,
                   const double *a, double eps2, const double *h2);
+
+/* Order 8 (Methods > Numerical Accuracy; Conclusion): as nbx_force_ext, with the sink
+ * accelerations a and jerks jerk [ni][3] both required (the crackle needs the relative jerk).
+ * NBX_ERR_ARG on a context of another order. */
+int nbx_force_ext8(nbx_ctx *ctx, int ni, const int64_t *id, const double *x, const double *v,
+                   const double *a, const double *jerk, double eps2, const double *h2);
 
 /* Wait for the last nbx_force / nbx_force_ext and copy its results to caller-owned host arrays:
  * acc, jerk [ni][3] (orders 4, 6, 8; never written for order 2), snap [ni][3] (orders 6, 8), pot [ni],

@@ -70,7 +70,8 @@ struct ForceParams {
   const int64_t *ext_id;    // explicit sinks: id [ni], x/v/a [ni][3] (ext_x == nullptr: by address)
   const double *ext_x;
   const double *ext_v;
-  const double *ext_a;
+  const double *ext_a;  // order 6 and 8: sink accelerations
+  const double *ext_j;  // order 8: sink jerks
   const double *h2;  // [ni] squared neighbour radii, or nullptr
   int nbr_max;
   // launch shape

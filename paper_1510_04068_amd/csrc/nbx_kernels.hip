@@ -912,14 +912,14 @@ void k_force(const ForceParams fp) {
     q[p] = ib * Q + p * G + grp;
     const bool live = q[p] < fp.ni;
     double xp[3], vp[3], ap[6], m = 0.0;
-    if (fp.ext_x) {  // explicit sink state, used as given (orders 2, 4 and 6)
+    if (fp.ext_x) {  // explicit sink state, used as given
       const int qq = live ? q[p] : 0;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         xp[k] = fp.ext_x[3 * (size_t)qq + k];
         vp[k] = (Order != 2) ? fp.ext_v[3 * (size_t)qq + k] : 0.0;
-        ap[k] = (Order == 6) ? fp.ext_a[3 * (size_t)qq + k] : 0.0;
-        ap[3 + k] = 0.0;
+        ap[k] = (Order >= 6) ? fp.ext_a[3 * (size_t)qq + k] : 0.0;
+        ap[3 + k] = (Order == 8) ? fp.ext_j[3 * (size_t)qq + k] : 0.0;
       }
       self[p] = live ? fp.ext_self[qq] : -1;
     } else {  // by address: the sink's own predicted source state

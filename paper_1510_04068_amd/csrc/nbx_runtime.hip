@@ -62,7 +62,7 @@ struct nbx_ctx {
   int32_t *d_iaddr = nullptr;
   double *d_h2 = nullptr;
   int64_t *d_ext_id = nullptr;
-  double *d_ext_x = nullptr, *d_ext_v = nullptr, *d_ext_a = nullptr;
+  double *d_ext_x = nullptr, *d_ext_v = nullptr, *d_ext_a = nullptr, *d_ext_j = nullptr;
   int32_t *d_ext_self = nullptr;
   // results of the last host-path force call, laid out for its ni in one block behind the error
   // counters (d_out), so that nbx_get_force moves counters and results in one copy
@@ -303,7 +303,8 @@ int enqueue_force(nbx_ctx *c, hipStream_t stream, int ni, const int32_t *d_iaddr
                   const int64_t *ext_id, const double *ext_x, const double *ext_v, const double *ext_a,
                   double eps2, const double *d_h2, double *acc, double *jrk, double *snp, double *crk, double *pot,
                   int64_t *nn_id, double *nn_r2, int32_t *nbr_cnt, int64_t *nbr_ids,
-                  const BlockStepParams *bs = nullptr, double bs_t1 = 0.0, bool *fused = nullptr) {
+                  const BlockStepParams *bs = nullptr, double bs_t1 = 0.0, bool *fused = nullptr,
+                  const double *ext_j = nullptr) {
   if (fused) *fused = false;
   if (!c->predicted) return fail(c, NBX_ERR_STATE, "nbx_force before nbx_predict");
   if (!(eps2 >= 0.0)) return fail(c, NBX_ERR_ARG, "eps2 must be >= 0 (got %g)", eps2);
@@ -325,6 +326,7 @@ int enqueue_force(nbx_ctx *c, hipStream_t stream, int ni, const int32_t *d_iaddr
   fp.ext_x = ext_x;
   fp.ext_v = ext_v;
   fp.ext_a = ext_a;
+  fp.ext_j = ext_j;
   fp.h2 = d_h2;
   fp.nbr_max = c->cfg.nbr_max;
   fp.lanes_log2 = ls.lanes_log2;
@@ -700,37 +702,41 @@ int nbx_force(nbx_ctx *c, int ni, const int32_t *i_addr, double eps2, const doub
   return rc;
 }
 
-int nbx_force_ext(nbx_ctx *c, int ni, const int64_t *id, const double *x, const double *v, const double *a,
-                  double eps2, const double *h2) {
-  if (int rc = check_ctx(c)) return rc;
+// Explicit sinks at every order: a (orders 6 and 8) and jerk (order 8) as the order needs them.
+static int force_ext_impl(nbx_ctx *c, int ni, const int64_t *id, const double *x, const double *v, const double *a,
+                          const double *jerk, double eps2, const double *h2) {
+  const int order = c->cfg.order;
   if (ni < 0) return fail(c, NBX_ERR_ARG, "ni < 0");
   if (ni > c->cfg.ni_max) return fail(c, NBX_ERR_CAPACITY, "ni=%d > ni_max=%d", ni, c->cfg.ni_max);
-  if (c->cfg.order == 8) return fail(c, NBX_ERR_ARG, "explicit sinks are not available at order 8");
-  if (ni > 0 && (!id || !x || (!v && c->cfg.order != 2))) return fail(c, NBX_ERR_ARG, "NULL sink array");
-  if (ni > 0 && c->cfg.order == 6 && !a) return fail(c, NBX_ERR_ARG, "order 6 needs the sink accelerations");
+  if (ni > 0 && (!id || !x || (!v && order != 2))) return fail(c, NBX_ERR_ARG, "NULL sink array");
+  if (ni > 0 && order >= 6 && !a) return fail(c, NBX_ERR_ARG, "orders 6 and 8 need the sink accelerations");
+  if (ni > 0 && order == 8 && !jerk) return fail(c, NBX_ERR_ARG, "order 8 needs the sink jerks");
   if (h2 && c->cfg.nbr_max == 0) return fail(c, NBX_ERR_ARG, "neighbour lists need nbr_max > 0");
   if (!c->d_ext_id) {  // explicit-sink buffers, allocated on first use
     const size_t n = (size_t)c->cfg.ni_max;
     int rc = alloc_n(c, &c->d_ext_id, n);
     rc = rc ? rc : alloc_n(c, &c->d_ext_x, 3 * n);
-    if (c->cfg.order != 2) rc = rc ? rc : alloc_n(c, &c->d_ext_v, 3 * n);
-    if (c->cfg.order == 6) rc = rc ? rc : alloc_n(c, &c->d_ext_a, 3 * n);
+    if (order != 2) rc = rc ? rc : alloc_n(c, &c->d_ext_v, 3 * n);
+    if (order >= 6) rc = rc ? rc : alloc_n(c, &c->d_ext_a, 3 * n);
+    if (order == 8) rc = rc ? rc : alloc_n(c, &c->d_ext_j, 3 * n);
     rc = rc ? rc : alloc_n(c, &c->d_ext_self, n);
     if (rc) return rc;
   }
   const size_t n = (size_t)ni;
   hipStream_t s = c->stream;
-  const bool hv = c->cfg.order != 2, ha = c->cfg.order == 6;
+  const bool hv = order != 2, ha = order >= 6, hj = order == 8;
   const size_t off_x = align16(n * 8), off_v = off_x + align16(n * 24), off_a = off_v + (hv ? align16(n * 24) : 0);
-  const size_t off_h2 = off_a + (ha ? align16(n * 24) : 0), bytes = off_h2 + (h2 ? n * 8 : 0);
+  const size_t off_j = off_a + (ha ? align16(n * 24) : 0);
+  const size_t off_h2 = off_j + (hj ? align16(n * 24) : 0), bytes = off_h2 + (h2 ? n * 8 : 0);
   if (ni > 0 && bytes > kStageMax) {  // large: straight from the caller's arrays
     HIP_TRY(c, hipMemcpyAsync(c->d_ext_id, id, n * 8, hipMemcpyHostToDevice, s));
     HIP_TRY(c, hipMemcpyAsync(c->d_ext_x, x, n * 24, hipMemcpyHostToDevice, s));
     if (hv) HIP_TRY(c, hipMemcpyAsync(c->d_ext_v, v, n * 24, hipMemcpyHostToDevice, s));
     if (ha) HIP_TRY(c, hipMemcpyAsync(c->d_ext_a, a, n * 24, hipMemcpyHostToDevice, s));
+    if (hj) HIP_TRY(c, hipMemcpyAsync(c->d_ext_j, jerk, n * 24, hipMemcpyHostToDevice, s));
     if (h2) HIP_TRY(c, hipMemcpyAsync(c->d_h2, h2, n * 8, hipMemcpyHostToDevice, s));
     if (c->predicted) HIP_TRY(c, launch_selfmap(c->src, c->nj, ni, c->d_ext_id, c->d_ext_self, s));
-  } else if (ni > 0) {  // small: sink states through the pinned staging buffer: id | x | v | a | h2
+  } else if (ni > 0) {  // small: sink states through the pinned staging buffer: id | x | v | a | jerk | h2
     if (int rc = pinned_acquire(c, c->stage_i, bytes)) return rc;
     char *h = static_cast<char *>(c->stage_i.h);
     std::memcpy(h, id, n * 8);
@@ -745,6 +751,10 @@ int nbx_force_ext(nbx_ctx *c, int ni, const int64_t *id, const double *x, const 
       std::memcpy(h + off_a, a, n * 24);
       HIP_TRY(c, hipMemcpyAsync(c->d_ext_a, h + off_a, n * 24, hipMemcpyHostToDevice, s));
     }
+    if (hj) {
+      std::memcpy(h + off_j, jerk, n * 24);
+      HIP_TRY(c, hipMemcpyAsync(c->d_ext_j, h + off_j, n * 24, hipMemcpyHostToDevice, s));
+    }
     if (h2) {
       std::memcpy(h + off_h2, h2, n * 8);
       HIP_TRY(c, hipMemcpyAsync(c->d_h2, h + off_h2, n * 8, hipMemcpyHostToDevice, s));
@@ -754,12 +764,27 @@ int nbx_force_ext(nbx_ctx *c, int ni, const int64_t *id, const double *x, const 
   }
   out_layout(c, ni);
   int rc = enqueue_force(c, s, ni, nullptr, c->d_ext_self, c->d_ext_id, c->d_ext_x, c->d_ext_v,
-                         c->cfg.order == 6 ? c->d_ext_a : nullptr, eps2, h2 ? c->d_h2 : nullptr, c->d_acc,
-                         c->d_jrk, c->d_snp, nullptr, c->d_pot, c->d_nnid, c->d_nnr2, c->d_nbr_cnt, c->d_nbr_ids);
+                         ha ? c->d_ext_a : nullptr, eps2, h2 ? c->d_h2 : nullptr, c->d_acc, c->d_jrk, c->d_snp,
+                         c->d_crk, c->d_pot, c->d_nnid, c->d_nnr2, c->d_nbr_cnt, c->d_nbr_ids, nullptr, 0.0,
+                         nullptr, hj ? c->d_ext_j : nullptr);
   if (rc < 0) return rc;
   c->last_ni = ni;
   c->last_nbr = h2 != nullptr;
   return rc;
+}
+
+int nbx_force_ext(nbx_ctx *c, int ni, const int64_t *id, const double *x, const double *v, const double *a,
+                  double eps2, const double *h2) {
+  if (int rc = check_ctx(c)) return rc;
+  if (c->cfg.order == 8) return fail(c, NBX_ERR_ARG, "order 8 explicit sinks go through nbx_force_ext8");
+  return force_ext_impl(c, ni, id, x, v, a, nullptr, eps2, h2);
+}
+
+int nbx_force_ext8(nbx_ctx *c, int ni, const int64_t *id, const double *x, const double *v, const double *a,
+                   const double *jerk, double eps2, const double *h2) {
+  if (int rc = check_ctx(c)) return rc;
+  if (c->cfg.order != 8) return fail(c, NBX_ERR_ARG, "nbx_force_ext8 needs an order-8 context");
+  return force_ext_impl(c, ni, id, x, v, a, jerk, eps2, h2);
 }
 
 int nbx_get_force(nbx_ctx *c, double *acc, double *jerk, double *snap, double *pot, int64_t *nn_id,

@@ -46,7 +46,7 @@ EXPORTS = (
     "nbx_get_predicted", "nbx_get_j", "nbx_set_j_dev", "nbx_force_dev", "nbx_sync", "nbx_launch_shape",
     "nbx_batch_setup", "nbx_batch_tune", "nbx_batch_force_dev", "nbx_force_vjp_dev",
     "nbx_bs_init", "nbx_bs_step", "nbx_bs_run", "nbx_bs_get_state", "nbx_bs_energy", "nbx_tune",
-    "nbx_get_crackle", "nbx_force8_dev",
+    "nbx_get_crackle", "nbx_force8_dev", "nbx_force_ext8",
 )
 NBX_BATCH_NMAX = 128
 
@@ -140,6 +140,7 @@ def load(path: str = LIB_PATH):
         "nbx_tune": ([_P, _I, _P, _I], _I),
         "nbx_get_crackle": ([_P, _P], _I),
         "nbx_force8_dev": ([_P, _P, _I, _P, _D] + [_P] * 10, _I),
+        "nbx_force_ext8": ([_P, _I, _P, _P, _P, _P, _P, _D, _P], _I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -261,6 +262,16 @@ def nbx_force_ext(ctx, id, x, v, a, eps2, h2=None):
     a = None if a is None else _f64(a, n)
     h2 = None if h2 is None else _f64(np.broadcast_to(np.asarray(h2, dtype=np.float64), (n,)), n, 0)
     return _check(ctx, load().nbx_force_ext(ctx, n, _ptr(id), _ptr(x), _ptr(v), _ptr(a), float(eps2), _ptr(h2)))
+
+
+def nbx_force_ext8(ctx, id, x, v, a, jerk, eps2, h2=None):
+    x = _f64(x)
+    n = x.shape[0]
+    id = np.ascontiguousarray(id, dtype=np.int64)
+    v, a, jerk = _f64(v, n), _f64(a, n), _f64(jerk, n)
+    h2 = None if h2 is None else _f64(np.broadcast_to(np.asarray(h2, dtype=np.float64), (n,)), n, 0)
+    return _check(ctx, load().nbx_force_ext8(ctx, n, _ptr(id), _ptr(x), _ptr(v), _ptr(a), _ptr(jerk), float(eps2),
+                                              _ptr(h2)))
 
 
 def nbx_get_force(ctx, ni, order=4):
@@ -482,8 +493,11 @@ class Context:
         self._ni = len(i_addr)
         return nbx_force(self.ctx, i_addr, eps2, h2)
 
-    def force_ext(self, ids, x, v, a, eps2, h2=None):
+    def force_ext(self, ids, x, v, a, eps2, h2=None, jerk=None):
+        """Explicit sinks; order 8 also takes the sink jerks."""
         self._ni = len(ids)
+        if self.order == 8:
+            return nbx_force_ext8(self.ctx, ids, x, v, a, jerk, eps2, h2)
         return nbx_force_ext(self.ctx, ids, x, v, a, eps2, h2)
 
     def get_force(self):

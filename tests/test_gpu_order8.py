@@ -236,8 +236,12 @@ def test_order8_device_path_and_errors():
         assert lib.nbx_force8_dev(ctx.ctx, None, ni, d_sel.data_ptr(), eps2, None, d["acc"].data_ptr(),
                                   d["jerk"].data_ptr(), d["snap"].data_ptr(), None, d["pot"].data_ptr(),
                                   d["nn_id"].data_ptr(), d["nn_r2"].data_ptr(), None, None) == nbx.NBX_ERR_ARG
-        with pytest.raises(nbx.NbxError) as e:
-            ctx.force_ext(np.arange(10**6, 10**6 + 4), np.zeros((4, 3)), np.zeros((4, 3)), None, eps2)
+        with pytest.raises(nbx.NbxError) as e:  # order 8 explicit sinks go through nbx_force_ext8
+            nbx.nbx_force_ext(ctx.ctx, np.arange(10**6, 10**6 + 4), np.zeros((4, 3)), np.zeros((4, 3)),
+                              np.zeros((4, 3)), eps2)
+        assert e.value.code == nbx.NBX_ERR_ARG
+        with pytest.raises(nbx.NbxError) as e:  # which needs the sink jerks
+            ctx.force_ext(np.arange(10**6, 10**6 + 4), np.zeros((4, 3)), np.zeros((4, 3)), np.zeros((4, 3)), eps2)
         assert e.value.code == nbx.NBX_ERR_ARG
         with pytest.raises(nbx.NbxError) as e:
             nbx.nbx_bs_init(ctx.ctx, src.ids[:100], src.m[:100], src.x[:100], src.v[:100], 1e-4)
@@ -248,6 +252,10 @@ def test_order8_device_path_and_errors():
         ctx6.force(sel, eps2)
         crackle = np.empty((ni, 3))
         assert lib.nbx_get_crackle(ctx6.ctx, crackle.ctypes.data) == nbx.NBX_ERR_ARG
+        with pytest.raises(nbx.NbxError) as e:
+            nbx.nbx_force_ext8(ctx6.ctx, np.arange(10**6, 10**6 + 4), np.zeros((4, 3)), np.zeros((4, 3)),
+                               np.zeros((4, 3)), np.zeros((4, 3)), eps2)
+        assert e.value.code == nbx.NBX_ERR_ARG
         assert lib.nbx_force8_dev(ctx6.ctx, None, ni, d_sel.data_ptr(), eps2, None, d["acc"].data_ptr(),
                                   d["jerk"].data_ptr(), d["snap"].data_ptr(), d["crackle"].data_ptr(),
                                   d["pot"].data_ptr(), d["nn_id"].data_ptr(), d["nn_r2"].data_ptr(), None,
@@ -274,3 +282,49 @@ def test_order8_tuned_shapes(prec):
             say("  ni=%d shape=%s" % (ni, ctx.launch_shape(ni)))
             ctx.force(sel, eps2)
             _compare(ctx.get_force(), _sub(ref_all, sel), prec, sel, src.ids, "  ni=%d" % ni)
+
+
+@pytest.mark.parametrize("prec", [nbx.NBX_FP64, nbx.NBX_MIXED])
+def test_order8_explicit_sinks(prec):
+    """Explicit order-8 sinks (x, v, a, jerk used as given): foreign ids feel every source; sinks
+    carrying a source's id, at a shifted position, exclude exactly that source."""
+    n, t, eps2, ni = 2500, 0.0, 1e-4, 700
+    say("order8 explicit sinks prec=%s" % PREC_NAME[prec])
+    src = nbody_ics.make_sources(n, seed=130, order=8)
+    xp, vp, ap = oracle.predict(8, t, src.t, src.x, src.v, src.a, src.jerk, src.snap, src.crackle)
+    jp = oracle.predict_jerk(t, src.t, src.jerk, src.snap, src.crackle)
+    rng = np.random.default_rng(131)
+    own = rng.choice(n, size=ni // 2, replace=False)
+    ids = np.concatenate([src.ids[own], np.arange(10**6, 10**6 + ni - ni // 2)]).astype(np.int64)
+    x = np.concatenate([xp[own] + rng.normal(0, 1e-3, (ni // 2, 3)), rng.normal(0, 0.5, (ni - ni // 2, 3))])
+    v, a, jerk = rng.normal(0, 0.5, (ni, 3)), rng.normal(0, 0.5, (ni, 3)), rng.normal(0, 2.0, (ni, 3))
+    h2 = np.full(ni, 4e-3)
+    ref = oracle.force8(eps2, src.ids, src.m, xp, vp, ap, jp, ids, x, v, a, jerk, h2=h2, nbr_max=n)
+    with nbx.Context(order=8, precision=prec, nj_max=n, ni_max=ni, nbr_max=32) as ctx:
+        ctx.set_sources(src)
+        ctx.predict(t)
+        ctx.force_ext(ids, x, v, a, eps2, h2, jerk=jerk)
+        out = ctx.get_force()
+        cnt, _, _ = ctx.get_nbr()
+    tol = TOL[prec]
+    e_acc = rel_err_vec(out["acc"], ref["acc"])
+    kappa = ref["cond"][:, 0] / np.linalg.norm(ref["acc"], axis=1)
+    e_pot = np.abs(out["pot"] - ref["pot"]) / np.abs(ref["pot"])
+    e_snap = cond_err_vec(out["snap"], ref["snap"], ref["cond"][:, 2])
+    e_crk = cond_err_vec(out["crackle"], ref["crackle"], ref["cond"][:, 3])
+    say("  ext: max rel acc %.2e (kappa %.1f) pot %.2e snap/cond %.2e crackle/cond %.2e" % (
+        e_acc.max(), kappa[np.argmax(e_acc)], e_pot.max(), e_snap.max(), e_crk.max()))
+    if prec == nbx.NBX_FP64:
+        assert e_acc.max() <= tol["acc"]
+    else:
+        assert e_acc[kappa <= KAPPA_MAX].max(initial=0.0) <= tol["acc"] and (e_acc / kappa).max() <= tol["acc"]
+    assert e_pot.max() <= tol["pot"] and e_snap.max() <= tol["snap_cond"] and e_crk.max() <= tol["crackle_cond"]
+    assert not np.any(out["nn_id"] == ids)  # never the sink's own source
+    d = xp[out["nn_id"]] - x
+    r2 = np.sum(d * d, axis=1)  # two FP64 predictors agree to rounding in x; x_j - x_i cancels
+    scale = np.maximum(np.linalg.norm(x, axis=1), np.linalg.norm(xp[out["nn_id"]], axis=1)) * np.sqrt(r2)
+    assert np.all(np.abs(out["nn_r2"] - r2) <= 1e-13 * r2 + 16 * np.finfo(np.float64).eps * scale)
+    slack = 1e-14 if prec == nbx.NBX_FP64 else 4e-7
+    assert np.all(out["nn_r2"] <= ref["nn_r2"] * (1 + slack))
+    if prec == nbx.NBX_FP64:
+        np.testing.assert_array_equal(cnt, ref["nbr_count"])
