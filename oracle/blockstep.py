@@ -103,6 +103,21 @@ def hermite_correct(order, dt, x0, v0, a0, j0, a1, j1, s0=None, s1=None):
     return x1, v1, d
 
 
+def hermite8_correct(dt, x0, v0, a0, j0, s0, c0, a1, j1, s1, c1):
+    """8th-order Hermite corrector for a shared step (Nitadori & Makino 2008, the integrator the
+    paper's double-precision storage is meant to allow, Methods > Numerical Accuracy): the
+    acceleration on the step is the degree-7 polynomial that matches a, jerk, snap and crackle at
+    both ends; v1 = v0 plus its integral over the step; x1 = x0 plus the integral of the degree-7
+    interpolant of the velocity through v, a, jerk and snap at both ends (with the corrected v1).
+    dt: [n]; returns (x1, v1)."""
+    dt = np.asarray(dt, dtype=np.float64)
+    ba = interpolant(dt, [a0, j0, s0, c0], [a1, j1, s1, c1])
+    v1 = v0 + integral(dt, ba)
+    bv = interpolant(dt, [v0, a0, j0, s0], [v1, a1, j1, s1])
+    x1 = x0 + integral(dt, bv)
+    return x1, v1
+
+
 def _norm(a):
     return np.sqrt(np.sum(np.asarray(a) ** 2, axis=1))
 

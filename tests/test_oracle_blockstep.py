@@ -130,3 +130,58 @@ def test_plummer_block_steps_invariants_and_energy(order):
     assert n_act.min() >= 1 and n_act.max() <= n and len(set(n_act.tolist())) > 1  # really block steps
     de = abs(sum(it.energy()) - e0) / abs(e0)
     assert de < (1e-7 if order == 4 else 1e-9), de
+
+
+def test_hermite8_corrector_exact_on_degree8_motion_only():
+    # the 8th-order corrector integrates degree-7 interpolants (a, jerk, snap, crackle at both ends
+    # for v; v, a, jerk, snap for x): v exact while a(t) has degree <= 7 (x degree <= 9), x exact
+    # while v(t) has degree <= 7 (x degree <= 8); one degree more breaks each
+    rng = np.random.default_rng(62)
+    n = 20
+    for deg, v_exact, x_exact in ((8, True, True), (9, True, False), (10, False, False)):
+        D = _poly_motion(rng, deg, n)
+        t0 = rng.uniform(-1, 1, n)
+        dt = 2.0 ** rng.integers(-1, 1, n)
+        t1 = t0 + dt
+        x1, v1 = bs.hermite8_correct(dt, D(0, t0), D(1, t0), D(2, t0), D(3, t0), D(4, t0), D(5, t0),
+                                     D(2, t1), D(3, t1), D(4, t1), D(5, t1))
+        ev, ex = np.abs(v1 - D(1, t1)).max(), np.abs(x1 - D(0, t1)).max()
+        assert (ev < 1e-12) == v_exact and (ev > 1e-11 or v_exact), (deg, ev)
+        assert (ex < 1e-12) == x_exact and (ex > 1e-11 or x_exact), (deg, ex)
+
+
+def _hermite8_orbit(nsteps, n_ec):
+    # shared-step 8th-order Hermite on the circular equal-mass binary (d = 1, omega = 1) for one
+    # period, forces from the oracle's order-8 mode, n_ec evaluate-correct passes per step
+    import oracle
+
+    m, ids = np.array([0.5, 0.5]), np.arange(2, dtype=np.int64)
+    x, v = np.array([[-0.5, 0, 0], [0.5, 0, 0]]), np.array([[0, -0.5, 0], [0, 0.5, 0]])
+
+    def forces(x, v, a, j):
+        f = oracle.force8(0.0, ids, m, x, v, a, j, ids, x, v, a, j)
+        return f["acc"], f["jerk"], f["snap"], f["crackle"]
+
+    a, j, _, _ = forces(x, v, np.zeros((2, 3)), np.zeros((2, 3)))  # a, j need no a, j
+    a, j, s, c = forces(x, v, a, j)  # snap and crackle with the exact a, j
+    T, t = 2.0 * math.pi, 0.0
+    dt = T / nsteps
+    for _ in range(nsteps):
+        xp, vp, ap = oracle.predict(8, t + dt, np.full(2, t), x, v, a, j, s, c)
+        jp = oracle.predict_jerk(t + dt, np.full(2, t), j, s, c)
+        d1 = forces(xp, vp, ap, jp)
+        for _ in range(n_ec):
+            x1, v1 = bs.hermite8_correct(np.full(2, dt), x, v, a, j, s, c, *d1)
+            d1 = forces(x1, v1, d1[0], d1[1])
+        x, v, (a, j, s, c) = x1, v1, d1
+        t += dt
+    return np.abs(x - np.array([[-0.5, 0, 0], [0.5, 0, 0]])).max()  # back at the start after a period
+
+
+def test_hermite8_circular_orbit_eighth_order():
+    # with two evaluate-correct passes per step the predictor's error (crackle-order Taylor terms)
+    # is corrected away and the global error falls as dt^8 (2^8 = 256 per halving)
+    errs = [_hermite8_orbit(nsteps, 2) for nsteps in (16, 32, 64)]
+    assert errs[-1] < 1e-11
+    for e1, e2 in zip(errs, errs[1:]):
+        assert 180.0 < e1 / e2 < 330.0, errs
