@@ -222,7 +222,8 @@ int nbx_force_dev(nbx_ctx *ctx, void *stream, int ni, const int32_t *d_i_addr, d
                   double *d_pot, int64_t *d_nn_id, double *d_nn_r2, int32_t *d_nbr_count,
                   int64_t *d_nbr_ids);
 
-/* Order 8 (Conclusion): as nbx_force_dev, with d_snap and d_crackle [ni][3] both required.
+/* Order 8 (Methods > Numerical Accuracy; Conclusion): as nbx_force_dev, with d_snap and d_crackle
+ * [ni][3] both required.
  * NBX_ERR_ARG on a context of another order. */
 int nbx_force8_dev(nbx_ctx *ctx, void *stream, int ni, const int32_t *d_i_addr, double eps2,
                    const double *d_h2, double *d_acc, double *d_jerk, double *d_snap,
