@@ -499,8 +499,8 @@ def adjoint(torch, nbx, ics, dev, steps):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the source-sharded multi-GPU design is described, not "
-              "built); run with --gpus 1", file=sys.stderr)
+        print("bench.py: nbx runs on one GPU only (the source-sharded multi-GPU design is described in the "
+              "documentation, not implemented); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
 
