@@ -389,3 +389,31 @@ def test_order8_hermite_steps_match_oracle():
     ev = np.abs(vg - v).max() / np.abs(v).max()
     say("  max rel dx %.2e dv %.2e" % (ex, ev))
     assert ex <= 1e-12 and ev <= 1e-12
+
+
+def test_order8_state_and_capacity_errors():
+    """Order-8 entry points report call-order and capacity errors without touching the device
+    state: crackle before any force call, too many sinks, and an empty sink set."""
+    torch = pytest.importorskip("torch")
+    n = 500
+    say("order8 state and capacity errors")
+    src = nbody_ics.make_sources(n, seed=133, order=8)
+    lib = nbx.load()
+    with nbx.Context(order=8, nj_max=n, ni_max=100) as ctx:
+        crackle = np.empty((100, 3))
+        assert lib.nbx_get_crackle(ctx.ctx, crackle.ctypes.data) == nbx.NBX_ERR_STATE
+        ctx.set_sources(src)
+        ctx.predict(0.0)
+        d = {k: torch.empty((200, 3), dtype=torch.float64, device="cuda:0") for k in ("a", "j", "s", "c")}
+        o = torch.empty(200, dtype=torch.float64, device="cuda:0")
+        i64 = torch.empty(200, dtype=torch.int64, device="cuda:0")
+        addr = torch.arange(200, dtype=torch.int32, device="cuda:0")
+        assert lib.nbx_force8_dev(ctx.ctx, None, 200, addr.data_ptr(), 1e-4, None, d["a"].data_ptr(),
+                                  d["j"].data_ptr(), d["s"].data_ptr(), d["c"].data_ptr(), o.data_ptr(),
+                                  i64.data_ptr(), o.data_ptr(), None, None) == nbx.NBX_ERR_CAPACITY
+        assert lib.nbx_force8_dev(ctx.ctx, None, 0, None, 1e-4, None, None, None, None, None, None, None, None,
+                                  None, None) == nbx.NBX_OK
+        ctx.force(np.arange(0, dtype=np.int32), 1e-4)  # an empty sink set is a valid call
+        out = ctx.get_force()
+        assert out["crackle"].shape == (0, 3)
+        torch.cuda.synchronize()
