@@ -502,3 +502,124 @@ def test_order8_predicted_jerk_exact_on_quintics():
     jerk, snap, crackle = 6 * c[3], 24 * c[4], 120 * c[5]
     exact = 6 * c[3] + 24 * c[4] * dt + 60 * c[5] * dt * dt
     np.testing.assert_allclose(oracle.predict_jerk(t, tj, jerk, snap, crackle), exact, rtol=1e-13, atol=1e-13)
+
+
+# --------------------------------------------------------------------------------------------
+# Condition sums cond_k = sum_j |A_k(i, j)|, the denominators of the condition-normalised error
+# bounds.  With one source per sink the sum has one term, so cond_k equals the magnitude of the
+# exact k-th derivative of the circular orbit; with two sources placed symmetrically it is the
+# sum of two known magnitudes while the signed sum partly cancels.
+# --------------------------------------------------------------------------------------------
+def _binary_derivs(m1, m2, eps2, d=0.7, th=0.37):
+    M = m1 + m2
+    R = math.sqrt(d * d + eps2)
+    w = math.sqrt(M / R**3)
+
+    def body(k):
+        c, s = math.cos(th + k * math.pi / 2), math.sin(th + k * math.pi / 2)
+        r = d * w**k * np.array([c, s, 0.0])
+        return np.array([-(m2 / M) * r, (m1 / M) * r])
+
+    return body, R, w
+
+
+@pytest.mark.parametrize("eps2", [0.0, 1e-2, 0.3])
+@pytest.mark.parametrize("m1,m2", [(0.5, 0.5), (0.9, 0.1), (1e-3, 2.0)])
+def test_cond_single_pair_is_the_term_magnitude(eps2, m1, m2):
+    body, _, _ = _binary_derivs(m1, m2, eps2)
+    m = np.array([m1, m2])
+    mag = lambda k: np.linalg.norm(body(k), axis=1)
+    out6 = _all_pairs(6, eps2, m, body(0), body(1), a=body(2))
+    np.testing.assert_allclose(out6["cond"][:, 0], mag(2), rtol=1e-14)
+    np.testing.assert_allclose(out6["cond"][:, 1], mag(3), rtol=1e-14)
+    np.testing.assert_allclose(out6["cond"][:, 2], mag(4), rtol=1e-13)
+    out4 = _all_pairs(4, eps2, m, body(0), body(1))
+    np.testing.assert_array_equal(out4["cond"][:, :2], out6["cond"][:, :2])
+    assert np.all(out4["cond"][:, 2] == 0.0)
+    out2 = oracle.force(2, eps2, np.arange(2), m, body(0), None, np.arange(2), body(0), None)
+    np.testing.assert_array_equal(out2["cond"][:, 0], out6["cond"][:, 0])
+    assert np.all(out2["cond"][:, 1:] == 0.0)
+    out8 = _all_pairs8(eps2, m, body(0), body(1), body(2), body(3))
+    for k in range(4):
+        np.testing.assert_allclose(out8["cond"][:, k], mag(2 + k), rtol=1e-13)
+
+
+@pytest.mark.parametrize("eps2", [0.0, 0.05])
+def test_cond_three_body_sums_magnitudes(eps2):
+    # a foreign sink at rest at the origin; sources of masses m1, m2 at (+d, 0, 0) and (-d, 0, 0)
+    # moving with (0, +u, 0) and (0, -u, 0), no accelerations or jerks.  Then r.v = 0 for both
+    # pairs (alpha = 0), beta = u^2/R^2 and gamma = 0, so with R^2 = d^2 + eps2:
+    #   A0 = +-m d/R^3 x,  A1 = +-m u/R^3 y,  A2 = -3 (u/R)^2 A0,  A3 = -9 (u/R)^2 A1
+    # and the signed sums carry (m1 - m2) where the condition sums carry (m1 + m2).
+    d, u, m1, m2 = 0.3, 1.7, 0.8, 0.3
+    R = math.sqrt(d * d + eps2)
+    xs = np.array([[d, 0, 0], [-d, 0, 0]])
+    vs = np.array([[0, u, 0], [0, -u, 0]])
+    zs = np.zeros((2, 3))
+    m = np.array([m1, m2])
+    ids = np.array([0, 1], dtype=np.int64)
+    sink = (np.array([7], dtype=np.int64), np.zeros((1, 3)), np.zeros((1, 3)))
+    o6 = oracle.force(6, eps2, ids, m, xs, vs, *sink, aj=zs, ai=np.zeros((1, 3)))
+    o8 = oracle.force8(eps2, ids, m, xs, vs, zs, zs, sink[0], sink[1], sink[2], np.zeros((1, 3)),
+                       np.zeros((1, 3)))
+    b = (u / R) ** 2
+    signed = {"acc": (m1 - m2) * d / R**3 * np.array([1, 0, 0]),
+              "jerk": (m1 - m2) * u / R**3 * np.array([0, 1, 0])}
+    signed["snap"] = -3 * b * signed["acc"]
+    signed["crackle"] = -9 * b * signed["jerk"]
+    cond = [(m1 + m2) * d / R**3, (m1 + m2) * u / R**3, 3 * b * (m1 + m2) * d / R**3,
+            9 * b * (m1 + m2) * u / R**3]
+    for key in ("acc", "jerk", "snap"):
+        np.testing.assert_allclose(o6[key][0], signed[key], rtol=1e-14, atol=1e-15 * np.abs(signed[key]).max())
+    np.testing.assert_allclose(o8["crackle"][0], signed["crackle"], rtol=1e-14,
+                               atol=1e-15 * np.abs(signed["crackle"]).max())
+    np.testing.assert_allclose(o6["cond"][0], cond[:3], rtol=1e-14)
+    np.testing.assert_allclose(o8["cond"][0], cond, rtol=1e-14)
+    np.testing.assert_allclose(o6["pot"][0], -(m1 + m2) / R, rtol=1e-15)
+    # the condition number of the acceleration is the known ratio
+    assert abs(o6["cond"][0, 0] / np.linalg.norm(o6["acc"][0]) - (m1 + m2) / (m1 - m2)) < 1e-13
+
+
+# --------------------------------------------------------------------------------------------
+# Energy helpers against the closed-form energy of the circular softened binary,
+# E = mu (w d)^2 / 2 - m1 m2 / R with mu = m1 m2 / M, and against an explicit pair sum.
+# --------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("eps2", [0.0, 1e-2])
+@pytest.mark.parametrize("m1,m2", [(0.5, 0.5), (0.9, 0.1)])
+def test_total_energy_circular_binary(eps2, m1, m2):
+    body, R, w = _binary_derivs(m1, m2, eps2)
+    d = 0.7
+    m = np.array([m1, m2])
+    out = _all_pairs(4, eps2, m, body(0), body(1))
+    e_kin = 0.5 * (m1 * m2 / (m1 + m2)) * (w * d) ** 2
+    e_pot = -m1 * m2 / R
+    assert abs(oracle.total_energy(m, body(1), out["pot"]) - (e_kin + e_pot)) <= 1e-15 * (e_kin - e_pot)
+    # a cluster: kinetic sum plus the potential energy counted once per pair, written as a pair loop
+    src = nbody_ics.make_sources(40, seed=19, masses="salpeter")
+    eps = 1e-3
+    o = _all_pairs(4, eps, src.m, src.x, src.v)
+    w_pairs = 0.0
+    for i in range(40):
+        for j in range(i + 1, 40):
+            w_pairs -= src.m[i] * src.m[j] / math.sqrt(np.sum((src.x[i] - src.x[j]) ** 2) + eps)
+    k_sum = sum(0.5 * src.m[i] * float(np.dot(src.v[i], src.v[i])) for i in range(40))
+    assert abs(oracle.total_energy(src.m, src.v, o["pot"]) - (k_sum + w_pairs)) <= 1e-14 * (k_sum - w_pairs)
+
+
+@pytest.mark.parametrize("order", [4, 6])
+def test_blockstep_energy_circular_binary(order):
+    from oracle.blockstep import BlockStep
+
+    m1, m2, eps2 = 0.9, 0.1, 1e-2
+    body, R, w = _binary_derivs(m1, m2, eps2)
+    d = 0.7
+    e_kin = 0.5 * (m1 * m2 / (m1 + m2)) * (w * d) ** 2
+    e_pot = -m1 * m2 / R
+    bs = BlockStep(order, np.array([m1, m2]), body(0), body(1), eps2, dt_max=1.0 / 64)
+    ek, ep = bs.energy()
+    assert abs(ek - e_kin) <= 1e-15 * e_kin and abs(ep - e_pot) <= 1e-15 * abs(e_pot)
+    # the orbit is circular, so the energy stays the closed form along the integrated motion
+    bs.run(0.5)
+    ek, ep = bs.energy()
+    assert abs((ek + ep) - (e_kin + e_pot)) <= 1e-9 * abs(e_kin + e_pot)
+    assert abs(ek - e_kin) <= 1e-7 * e_kin
