@@ -172,13 +172,58 @@ def _f64(a, n=None, width=3):
     return a
 
 
-def _dptr(t):
-    """Device pointer of a torch tensor (or an int), None passes through."""
-    if t is None:
-        return None
-    if isinstance(t, int):
-        return t
-    return t.data_ptr()
+# What the binding knows about each open context (keyed by the handle's value): the device and
+# order it was opened with, its neighbour-list capacity, and the particle count of its batch.
+_CTX_INFO = {}
+
+_DTYPE_NAMES = {"f64": "float64", "i32": "int32", "i64": "int64"}
+
+
+def _torch_dtype(kind):
+    import torch
+
+    return {"f64": torch.float64, "i32": torch.int32, "i64": torch.int64}[kind]
+
+
+def _dptr(t, kind=None, numel=0, ctx=None, name="array"):
+    """Device pointer of one torch tensor (see _dptrs); an int passes through as a raw device
+    address, None as NULL."""
+    return _dptrs(ctx, [(name, t, kind, numel)])[0]
+
+
+def _dptrs(ctx, specs):
+    """Device pointers of the tensors in specs, a list of (name, tensor, kind, numel).  A tensor must
+    have the dtype the C ABI reads (kind: "f64", "i32" or "i64"), be contiguous, hold at least numel
+    elements and live on the context's GPU; otherwise ValueError is raised before any library call,
+    because the kernels would read or write past the tensor.  The layout checks run over every
+    tensor before the placement checks.  Ints pass through as raw device addresses, None as NULL."""
+    for name, t, kind, numel in specs:
+        if t is None or isinstance(t, int):
+            continue
+        if kind is not None and t.dtype != _torch_dtype(kind):
+            raise ValueError("%s: dtype %s, the library reads %s" % (name, t.dtype, _DTYPE_NAMES[kind]))
+        if not t.is_contiguous():
+            raise ValueError("%s: tensor is not contiguous" % name)
+        if t.numel() < numel:
+            raise ValueError("%s: %d elements, the call needs %d" % (name, t.numel(), numel))
+    info = _CTX_INFO.get(getattr(ctx, "value", None))
+    out = []
+    for name, t, kind, numel in specs:
+        if t is None or isinstance(t, int):
+            out.append(t)
+            continue
+        if t.device.type != "cuda":
+            raise ValueError("%s: tensor is on %s, not on a GPU" % (name, t.device))
+        if info is not None and t.device.index is not None and t.device.index != info["device"]:
+            raise ValueError("%s: tensor is on cuda:%d, the context on cuda:%d" % (name, t.device.index,
+                                                                                   info["device"]))
+        out.append(t.data_ptr())
+    return out
+
+
+def _ctx_order(ctx, default=4):
+    info = _CTX_INFO.get(getattr(ctx, "value", None))
+    return info["order"] if info is not None else default
 
 
 def _stream(s):
@@ -210,10 +255,12 @@ def nbx_open(device=0, order=4, precision=NBX_FP64, nj_max=1, ni_max=1, nbr_max=
     rc = load().nbx_open(ctypes.byref(ctx), ctypes.byref(cfg))
     if rc < 0:
         raise NbxError(rc, load().nbx_last_error(None).decode())
+    _CTX_INFO[ctx.value] = {"device": int(device), "order": int(order), "nbr_max": int(nbr_max), "batch_n": 0}
     return ctx
 
 
 def nbx_close(ctx):
+    _CTX_INFO.pop(getattr(ctx, "value", None), None)
     return load().nbx_close(ctx)
 
 
@@ -328,24 +375,48 @@ def nbx_get_j(ctx, addr, order=4):
 
 
 def nbx_set_j_dev(ctx, stream, n, d_addr, d_id, d_m, d_t, d_x, d_v, d_a, d_jerk, d_snap=None, d_crackle=None):
-    rc = load().nbx_set_j_dev(ctx, _stream(stream), int(n), _dptr(d_addr), _dptr(d_id), _dptr(d_m), _dptr(d_t),
-                              _dptr(d_x), _dptr(d_v), _dptr(d_a), _dptr(d_jerk), _dptr(d_snap), _dptr(d_crackle))
+    n = int(n)
+    args = _dptrs(ctx, [("d_addr", d_addr, "i32", n), ("d_id", d_id, "i64", n), ("d_m", d_m, "f64", n),
+                        ("d_t", d_t, "f64", n), ("d_x", d_x, "f64", 3 * n), ("d_v", d_v, "f64", 3 * n),
+                        ("d_a", d_a, "f64", 3 * n), ("d_jerk", d_jerk, "f64", 3 * n),
+                        ("d_snap", d_snap, "f64", 3 * n), ("d_crackle", d_crackle, "f64", 3 * n)])
+    rc = load().nbx_set_j_dev(ctx, _stream(stream), n, *args)
     return _check(ctx, rc)
+
+
+def _force_dev_args(ctx, ni, d_i_addr, d_h2, outs, d_nbr_count, d_nbr_ids):
+    """Validated device pointers of the force entry points: sink addresses, radii, the [ni][3] and
+    [ni] outputs (outs: (name, tensor, kind, width) in ABI order) and the neighbour-list arrays."""
+    info = _CTX_INFO.get(getattr(ctx, "value", None))
+    nbr_max = info["nbr_max"] if info is not None else 0
+    lists = d_h2 is not None
+    specs = [("d_i_addr", d_i_addr, "i32", ni), ("d_h2", d_h2, "f64", ni)]
+    specs += [(name, t, kind, width * ni) for name, t, kind, width in outs]
+    specs += [("d_nbr_count", d_nbr_count, "i32", ni if lists else 0),
+              ("d_nbr_ids", d_nbr_ids, "i64", ni * nbr_max if lists else 0)]
+    return _dptrs(ctx, specs)
 
 
 def nbx_force_dev(ctx, stream, ni, d_i_addr, eps2, d_h2, d_acc, d_jerk, d_snap, d_pot, d_nn_id, d_nn_r2,
                   d_nbr_count=None, d_nbr_ids=None):
-    rc = load().nbx_force_dev(ctx, _stream(stream), int(ni), _dptr(d_i_addr), float(eps2), _dptr(d_h2),
-                              _dptr(d_acc), _dptr(d_jerk), _dptr(d_snap), _dptr(d_pot), _dptr(d_nn_id),
-                              _dptr(d_nn_r2), _dptr(d_nbr_count), _dptr(d_nbr_ids))
+    ni = int(ni)
+    p = _force_dev_args(ctx, ni, d_i_addr, d_h2,
+                        (("d_acc", d_acc, "f64", 3), ("d_jerk", d_jerk, "f64", 3), ("d_snap", d_snap, "f64", 3),
+                         ("d_pot", d_pot, "f64", 1), ("d_nn_id", d_nn_id, "i64", 1), ("d_nn_r2", d_nn_r2, "f64", 1)),
+                        d_nbr_count, d_nbr_ids)
+    rc = load().nbx_force_dev(ctx, _stream(stream), ni, p[0], float(eps2), *p[1:])
     return _check(ctx, rc)
 
 
 def nbx_force8_dev(ctx, stream, ni, d_i_addr, eps2, d_h2, d_acc, d_jerk, d_snap, d_crackle, d_pot, d_nn_id,
                    d_nn_r2, d_nbr_count=None, d_nbr_ids=None):
-    rc = load().nbx_force8_dev(ctx, _stream(stream), int(ni), _dptr(d_i_addr), float(eps2), _dptr(d_h2),
-                               _dptr(d_acc), _dptr(d_jerk), _dptr(d_snap), _dptr(d_crackle), _dptr(d_pot),
-                               _dptr(d_nn_id), _dptr(d_nn_r2), _dptr(d_nbr_count), _dptr(d_nbr_ids))
+    ni = int(ni)
+    p = _force_dev_args(ctx, ni, d_i_addr, d_h2,
+                        (("d_acc", d_acc, "f64", 3), ("d_jerk", d_jerk, "f64", 3), ("d_snap", d_snap, "f64", 3),
+                         ("d_crackle", d_crackle, "f64", 3), ("d_pot", d_pot, "f64", 1),
+                         ("d_nn_id", d_nn_id, "i64", 1), ("d_nn_r2", d_nn_r2, "f64", 1)),
+                        d_nbr_count, d_nbr_ids)
+    rc = load().nbx_force8_dev(ctx, _stream(stream), ni, p[0], float(eps2), *p[1:])
     return _check(ctx, rc)
 
 
@@ -374,28 +445,43 @@ def nbx_tune(ctx, ni_max):
 
 def nbx_batch_setup(ctx, offsets):
     offsets = np.ascontiguousarray(offsets, dtype=np.int32)
-    return _check(ctx, load().nbx_batch_setup(ctx, int(offsets.shape[0] - 1), _ptr(offsets)))
+    rc = _check(ctx, load().nbx_batch_setup(ctx, int(offsets.shape[0] - 1), _ptr(offsets)))
+    info = _CTX_INFO.get(getattr(ctx, "value", None))
+    if info is not None:
+        info["batch_n"] = int(offsets[-1])
+    return rc
+
+
+def _batch_args(ctx, d_m, d_x, d_v, d_acc, d_jerk, d_pot):
+    info = _CTX_INFO.get(getattr(ctx, "value", None))
+    n = info["batch_n"] if info is not None else 0
+    return _dptrs(ctx, [("d_m", d_m, "f64", n), ("d_x", d_x, "f64", 3 * n), ("d_v", d_v, "f64", 3 * n),
+                        ("d_acc", d_acc, "f64", 3 * n), ("d_jerk", d_jerk, "f64", 3 * n),
+                        ("d_pot", d_pot, "f64", n)])
 
 
 def nbx_batch_tune(ctx, stream, d_m, d_x, d_v, eps2, d_acc, d_jerk, d_pot):
     """Returns the lanes-per-sink chosen for each of the 8 size classes (0: class absent)."""
+    p = _batch_args(ctx, d_m, d_x, d_v, d_acc, d_jerk, d_pot)
     lanes = np.zeros(8, dtype=np.int32)
-    rc = load().nbx_batch_tune(ctx, _stream(stream), _dptr(d_m), _dptr(d_x), _dptr(d_v), float(eps2),
-                               _dptr(d_acc), _dptr(d_jerk), _dptr(d_pot), _ptr(lanes))
+    rc = load().nbx_batch_tune(ctx, _stream(stream), p[0], p[1], p[2], float(eps2), p[3], p[4], p[5], _ptr(lanes))
     _check(ctx, rc)
     return lanes
 
 
 def nbx_batch_force_dev(ctx, stream, d_m, d_x, d_v, eps2, d_acc, d_jerk, d_pot):
-    rc = load().nbx_batch_force_dev(ctx, _stream(stream), _dptr(d_m), _dptr(d_x), _dptr(d_v), float(eps2),
-                                    _dptr(d_acc), _dptr(d_jerk), _dptr(d_pot))
+    p = _batch_args(ctx, d_m, d_x, d_v, d_acc, d_jerk, d_pot)
+    rc = load().nbx_batch_force_dev(ctx, _stream(stream), p[0], p[1], p[2], float(eps2), p[3], p[4], p[5])
     return _check(ctx, rc)
 
 
 def nbx_force_vjp_dev(ctx, stream, n, d_m, d_x, d_v, eps2, d_g_acc, d_g_jerk, d_g_pot, d_grad_x, d_grad_v, d_grad_m):
-    rc = load().nbx_force_vjp_dev(ctx, _stream(stream), int(n), _dptr(d_m), _dptr(d_x), _dptr(d_v), float(eps2),
-                                  _dptr(d_g_acc), _dptr(d_g_jerk), _dptr(d_g_pot), _dptr(d_grad_x), _dptr(d_grad_v),
-                                  _dptr(d_grad_m))
+    n = int(n)
+    p = _dptrs(ctx, [("d_m", d_m, "f64", n), ("d_x", d_x, "f64", 3 * n), ("d_v", d_v, "f64", 3 * n),
+                     ("d_g_acc", d_g_acc, "f64", 3 * n), ("d_g_jerk", d_g_jerk, "f64", 3 * n),
+                     ("d_g_pot", d_g_pot, "f64", n), ("d_grad_x", d_grad_x, "f64", 3 * n),
+                     ("d_grad_v", d_grad_v, "f64", 3 * n), ("d_grad_m", d_grad_m, "f64", n)])
+    rc = load().nbx_force_vjp_dev(ctx, _stream(stream), n, p[0], p[1], p[2], float(eps2), *p[3:])
     return _check(ctx, rc)
 
 
