@@ -96,12 +96,44 @@ def test_blockstep_mixed_order6_completes():
     assert abs((e1 - e0) / e0) < 1e-6
 
 
-def test_blockstep_collapse_stops_with_warning():
-    """The 6th-order criterion differentiates the interpolated acceleration up to five times, which
-    multiplies force rounding noise by ~dt^-5; with FP32-arithmetic forces (~1e-7 relative) on this
-    700-body sphere the steps can collapse (the paper saw the same with double-single forces).  The
-    integrator must then stop at the first step clamped at dt_min, report NBX_WARN_DT_MIN and leave a
-    valid state."""
+@pytest.mark.parametrize("order", [4, 6])
+def test_blockstep_dt_min_stop_deterministic(order):
+    """A step criterion that must clamp: eta4 = 1e-10 (and eta6 = 1e-6) ask for steps far below
+    dt_min = 2^-10, so every particle of the first block step (t = 2^-10) is clamped.  The FP64
+    integrator stops there exactly as the oracle's does: NBX_WARN_DT_MIN, the same block time,
+    schedule and steps, a second call takes no step, and the state stays finite."""
+    n, eps2, t_end, dt_min = 256, 1e-4, 1.0 / 16, 2.0**-10
+    say("blockstep order=%d fp64 forced dt_min stop n=%d" % (order, n))
+    src = nbody_ics.make_sources(n, seed=63, time_offsets=False)
+    kw = dict(eta4=1e-10, eta6=1e-6, dt_min=dt_min)
+    ref = obs.BlockStep(order, src.m, src.x, src.v, eps2, **kw).run(t_end)
+    assert ref.clamped > 0 and ref.t < t_end  # the oracle integrator stops too
+    with nbx.Context(order=order, precision=nbx.NBX_FP64, nj_max=n, ni_max=n) as ctx:
+        nbx.nbx_bs_init(ctx.ctx, np.arange(n), src.m, src.x, src.v, eps2, **kw)
+        st = nbx.nbx_bs_run(ctx.ctx, t_end)
+        state = nbx.nbx_bs_get_state(ctx.ctx, n)
+        say("  status %d t %.6g blocks %d (oracle t %.6g blocks %d, %d clamped)" % (
+            st["status"], st["t"], st["block_steps"], ref.t, len(ref.log), ref.clamped))
+        assert st["status"] == nbx.NBX_WARN_DT_MIN
+        assert st["t"] == ref.t and st["t"] < t_end
+        assert st["block_steps"] == len(ref.log) and st["particle_steps"] == sum(k for _, k in ref.log)
+        assert state["dt"].min() == dt_min
+        np.testing.assert_array_equal(state["dt"], ref.dt)
+        k, rc = nbx.nbx_bs_step(ctx.ctx, t_end)
+        assert k == 0 and rc == nbx.NBX_WARN_DT_MIN  # stays stopped
+        again = nbx.nbx_bs_get_state(ctx.ctx, n)
+        assert again["t"] == st["t"]
+        np.testing.assert_array_equal(again["x"], state["x"])
+        assert np.all(np.isfinite(state["x"])) and np.all(np.isfinite(state["v"]))
+
+
+def test_blockstep_mixed_order6_collapse_known():
+    """Known limit, stated rather than asserted either way: the 6th-order criterion differentiates
+    the interpolated acceleration up to five times, which multiplies force rounding noise by
+    ~dt^-5; with FP32-arithmetic forces (~1e-7 relative) on this 700-body sphere the steps can
+    collapse (the paper saw the same with double-single forces).  If they do, the integrator must
+    stop at the first step clamped at dt_min, report NBX_WARN_DT_MIN and leave a valid state; the
+    forced, deterministic version of that stop is test_blockstep_dt_min_stop_deterministic."""
     n, eps2, t_end = 700, 1e-4, 1.0 / 16
     say("blockstep order=6 mixed collapse n=%d" % n)
     src = nbody_ics.make_sources(n, seed=63, time_offsets=False)
