@@ -106,6 +106,10 @@ typedef struct nbx_config {
   int nj_max;    /* source capacity (addresses 0 .. nj_max-1) */
   int ni_max;    /* largest number of sinks in one nbx_force call */
   int nbr_max;   /* neighbour-list capacity per sink; 0 disables neighbour lists */
+  int want_nn;   /* nonzero: force calls return the nearest neighbour (nn_id, nn_r2); 0: the gravity
+                    kernels skip the search (the paper makes it a compile-time option of its kernel,
+                    Results) and leave every nearest-neighbour output untouched, which may then be
+                    NULL; acc, jerk, snap, crackle, pot and lists are bit-identical either way */
 } nbx_config;
 
 /* Library ABI version (major * 10000 + minor * 100 + patch). */
@@ -173,7 +177,8 @@ int nbx_force_ext8(nbx_ctx *ctx, int ni, const int64_t *id, const double *x, con
 
 /* Wait for the last nbx_force / nbx_force_ext and copy its results to caller-owned host arrays:
  * acc, jerk [ni][3] (orders 4, 6, 8; never written for order 2), snap [ni][3] (orders 6, 8), pot [ni],
- * nn_id [ni], nn_r2 [ni].  Any pointer may be NULL to skip that output.  The results and the
+ * nn_id [ni], nn_r2 [ni] (not written when the context has want_nn = 0).  Any pointer may be NULL to
+ * skip that output.  The results and the
  * error counters come back in one copy.  Returns NBX_WARN_NBR_OVERFLOW if a neighbour list
  * overflowed, NBX_ERR_ARG if an address was out of range in a copy or force call since the last
  * check. */
@@ -213,7 +218,8 @@ int nbx_set_j_dev(nbx_ctx *ctx, void *stream, int n, const int32_t *d_addr, cons
 /* As nbx_force, with the sink addresses and every output in caller device memory:
  * d_acc, d_jerk [ni][3] (required; d_jerk may be NULL for order 2 and is not written there),
  * d_snap [ni][3] (order 6, else may be NULL), d_pot [ni],
- * d_nn_id [ni], d_nn_r2 [ni] (required); d_nbr_count [ni] and d_nbr_ids [ni][nbr_max] when d_h2
+ * d_nn_id [ni], d_nn_r2 [ni] (required with want_nn; with want_nn = 0 they may be NULL and are never
+ * written); d_nbr_count [ni] and d_nbr_ids [ni][nbr_max] when d_h2
  * is given.  Sink addresses outside [0, nj) make the kernel skip that sink (its outputs are left
  * untouched) and are counted for nbx_sync.  An order-8 context returns NBX_ERR_ARG: use
  * nbx_force8_dev. */
@@ -356,6 +362,20 @@ int nbx_tune(nbx_ctx *ctx, int ni_max, int32_t *shapes_out, int n_classes);
  * benchmarks report it. */
 int nbx_launch_shape(nbx_ctx *ctx, int ni, int *lanes_per_sink, int *sinks_per_lane,
                      int *splits, int *workgroups);
+
+/* ---- measurement ---------------------------------------------------------------------------
+ * Throughput is only comparable with a roofline at a known shader clock, and the clock under load
+ * varies from board to board (Results: the paper states its clocks with every GPU).  Enqueue on
+ * stream one tiny kernel of n_groups >= 1 workgroups; the first lane of workgroup g writes
+ * d_out[3g .. 3g+2] = (XCD the workgroup runs on, shader-clock cycle counter, constant-rate counter).
+ * Two samples around a timed region give the mean shader clock of each XCD over that region:
+ * (cycles after - cycles before) / (constant ticks after - before) * the constant rate.  d_out is
+ * caller device memory of at least 3 n_groups int64.  Enqueue only. */
+int nbx_clock_sample(nbx_ctx *ctx, void *stream, int n_groups, int64_t *d_out);
+
+/* The constant rate of the counter above and the shader clock's nominal maximum, in kHz (either
+ * pointer may be NULL). */
+int nbx_clock_rates(nbx_ctx *ctx, int *wall_khz, int *sclk_max_khz);
 
 #ifdef __cplusplus
 }

@@ -21,11 +21,13 @@ from . import nbx as _nbx
 
 
 class ForceContext:
-    """A library context sized for closed systems of up to n_max particles (4th order)."""
+    """A library context sized for closed systems of up to n_max particles (4th order), with the
+    gravity kernels that skip the nearest-neighbour search (the integrator never uses it)."""
 
     def __init__(self, n_max, precision=_nbx.NBX_FP64, device=0):
         self.n_max = n_max
-        self.ctx = _nbx.Context(order=4, precision=precision, nj_max=n_max, ni_max=n_max, device=device)
+        self.ctx = _nbx.Context(order=4, precision=precision, nj_max=n_max, ni_max=n_max, device=device,
+                                want_nn=False)
         self._addr = torch.arange(n_max, dtype=torch.int32, device="cuda:%d" % device)
         self._ids = torch.arange(n_max, dtype=torch.int64, device="cuda:%d" % device)
 
@@ -50,9 +52,7 @@ class _Forces(torch.autograd.Function):
         acc = torch.empty_like(x)
         jerk = torch.empty_like(x)
         pot = torch.empty(n, dtype=torch.float64, device=x.device)
-        nn_id = torch.empty(n, dtype=torch.int64, device=x.device)
-        nn_r2 = torch.empty(n, dtype=torch.float64, device=x.device)
-        _nbx.nbx_force_dev(c, stream, n, fc._addr[:n], eps2, None, acc, jerk, None, pot, nn_id, nn_r2)
+        _nbx.nbx_force_dev(c, stream, n, fc._addr[:n], eps2, None, acc, jerk, None, pot, None, None)
         fctx.save_for_backward(x, v, m)
         fctx.eps2 = eps2
         fctx.fc = fc

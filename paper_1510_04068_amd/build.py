@@ -10,6 +10,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -43,13 +44,15 @@ def _run(cmd):
 
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
-    for src in SOURCES:
-        obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-        if verbose:
-            print("hipcc", src, flush=True)
-        _run([HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
+    objs = [os.path.join(BUILD, src.replace(".hip", ".o")) for src in SOURCES]
+    if verbose:
+        print("hipcc", " ".join(SOURCES), flush=True)
+    # the translation units compile independently: one hipcc per file, side by side
+    with ThreadPoolExecutor(max_workers=len(SOURCES)) as pool:
+        jobs = [pool.submit(_run, [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+                for src, obj in zip(SOURCES, objs)]
+        for j in jobs:
+            j.result()
     tmp = LIB + ".tmp%d" % os.getpid()
     _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs])
     os.replace(tmp, LIB)

@@ -74,6 +74,7 @@ struct ForceParams {
   const double *ext_j;  // order 8: sink jerks
   const double *h2;  // [ni] squared neighbour radii, or nullptr
   int nbr_max;
+  int nn;  // nonzero: nearest-neighbour search (nn_id, nn_r2 written); 0: skipped, outputs untouched
   // launch shape
   int lanes_log2;  // lanes per sink = 1 << lanes_log2 (1..256)
   int splits;      // source splits S (workgroups per sink block)
@@ -156,6 +157,7 @@ hipError_t launch_gather_j(int order, const SourceArrays &src, int n, const int3
                            int64_t *id, double *m, double *t, double *x, double *v, double *a,
                            double *jerk, double *snap, double *crackle, hipStream_t stream);
 hipError_t launch_fill_i32(int32_t *p, int n, int value, hipStream_t stream);
+hipError_t launch_clock_sample(int n_groups, int64_t *out, hipStream_t stream);
 hipError_t launch_vjp(int precision, const VjpParams &vp, hipStream_t stream);
 hipError_t launch_batch(int precision, const BatchParams &bp, int grid, hipStream_t stream);
 hipError_t launch_selfmap(const SourceArrays &src, int nj, int ni, const int64_t *ext_id, int32_t *self,

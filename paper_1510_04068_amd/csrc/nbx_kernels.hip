@@ -282,8 +282,9 @@ struct Mixed {
     return key_of(diff_r2(j, s, dx, dy, dz));
   }
 
-  // One pair; returns the unsoftened |r|^2 (for the neighbour-list test).
-  template <bool Guard>
+  // One pair; returns the unsoftened |r|^2 (for the neighbour-list test).  NN: keep the
+  // nearest-neighbour group minimum (the kernels without it leave gmin untouched).
+  template <bool Guard, bool NN>
   __device__ static __forceinline__ float interact(const J &j, const Sink &s, float eps2, int jidx, int self,
                                                   Comp<float, kValues<Order>> &A, GKey &gmin) {
     float dx, dy, dz;
@@ -357,9 +358,11 @@ struct Mixed {
         }
       }
     }
-    Key key = key_of(r2);
-    if constexpr (Guard) key = jidx != self ? key : ~Key(0);
-    gmin = key < gmin ? key : gmin;
+    if constexpr (NN) {
+      Key key = key_of(r2);
+      if constexpr (Guard) key = jidx != self ? key : ~Key(0);
+      gmin = key < gmin ? key : gmin;
+    }
     return r2;
   }
 };
@@ -534,8 +537,8 @@ struct F64 {
     return key_of(diff_r2(j, s, dx, dy, dz));
   }
 
-  // One pair; returns the unsoftened |r|^2 (for the neighbour-list test).
-  template <bool Guard>
+  // One pair; returns the unsoftened |r|^2 (for the neighbour-list test).  NN as in Mixed.
+  template <bool Guard, bool NN>
   __device__ static __forceinline__ double interact(const J &j, const Sink &s, double eps2, int jidx, int self,
                                                   Comp<double, kValues<Order>> &A, GKey &gmin) {
     double dx, dy, dz;
@@ -608,7 +611,9 @@ struct F64 {
         }
       }
     }
-    if constexpr (kFloatMin) {
+    if constexpr (!NN) {
+      // no nearest-neighbour search
+    } else if constexpr (kFloatMin) {
       double gk = r2;
       if constexpr (Guard) gk = jidx != self ? gk : __builtin_huge_val();
       gmin = fmin(gk, gmin);
@@ -649,7 +654,7 @@ struct RedLds {
   int i[4][P];
 };
 
-template <int P, int K>
+template <int P, int K, bool NN = true>
 __device__ __forceinline__ void group_reduce(int gs, double (&v)[P][K], uint64_t (&kk)[P], int (&ii)[P],
                                              RedLds<P, K> &red) {
   const int wl = gs < 64 ? gs : 64;
@@ -658,11 +663,13 @@ __device__ __forceinline__ void group_reduce(int gs, double (&v)[P][K], uint64_t
     for (int p = 0; p < P; ++p) {
 #pragma unroll
       for (int k = 0; k < K; ++k) v[p][k] += __shfl_xor(v[p][k], off);
-      const uint64_t ok = __shfl_xor(kk[p], off);
-      const int oi = __shfl_xor(ii[p], off);
-      if (nn_better(ok, oi, kk[p], ii[p])) {
-        kk[p] = ok;
-        ii[p] = oi;
+      if constexpr (NN) {
+        const uint64_t ok = __shfl_xor(kk[p], off);
+        const int oi = __shfl_xor(ii[p], off);
+        if (nn_better(ok, oi, kk[p], ii[p])) {
+          kk[p] = ok;
+          ii[p] = oi;
+        }
       }
     }
   }
@@ -688,16 +695,18 @@ __device__ __forceinline__ void group_reduce(int gs, double (&v)[P][K], uint64_t
         for (int w = 1; w < wpg; ++w) s += red.v[w0 + w][p][k];
         v[p][k] = s;
       }
-      uint64_t bk = red.k[w0][p];
-      int bi = red.i[w0][p];
-      for (int w = 1; w < wpg; ++w) {
-        if (nn_better(red.k[w0 + w][p], red.i[w0 + w][p], bk, bi)) {
-          bk = red.k[w0 + w][p];
-          bi = red.i[w0 + w][p];
+      if constexpr (NN) {
+        uint64_t bk = red.k[w0][p];
+        int bi = red.i[w0][p];
+        for (int w = 1; w < wpg; ++w) {
+          if (nn_better(red.k[w0 + w][p], red.i[w0 + w][p], bk, bi)) {
+            bk = red.k[w0 + w][p];
+            bi = red.i[w0 + w][p];
+          }
         }
+        kk[p] = bk;
+        ii[p] = bi;
       }
-      kk[p] = bk;
-      ii[p] = bi;
     }
     __syncthreads();
   }
@@ -728,7 +737,7 @@ __device__ double nn_exact_r2(const ForceParams &fp, int q, int addr, int idx) {
 
 // Final write of one sink: results, nearest neighbour id and its exact FP64 |r|^2 (r2 given by
 // the split that found the neighbour, or computed here when r2 is null).
-template <int Order>
+template <int Order, bool NN = true>
 __device__ void finalize_sink(const ForceParams &fp, int q, const double *v, int idx, const double *r2) {
   const bool ext = fp.ext_x != nullptr;
   const int addr = ext ? -1 : fp.i_addr[q];
@@ -744,6 +753,7 @@ __device__ void finalize_sink(const ForceParams &fp, int q, const double *v, int
     if constexpr (Order == 8) fp.crk[3 * (size_t)q + k] = v[10 + k];
   }
   fp.pot[q] = v[kPotSlot<Order>];
+  if constexpr (!NN) return;  // the nearest-neighbour outputs are left untouched
   if (idx >= 0 && idx < fp.nj) {
     fp.nn_id[q] = fp.src.id[idx];
     fp.nn_r2[q] = r2 ? *r2 : nn_exact_r2<Order>(fp, q, addr, idx);
@@ -762,13 +772,13 @@ __device__ void finalize_sink(const ForceParams &fp, int q, const double *v, int
 // re-scanning that one group (nn_rescan).  L1: one lane per sink (compile-time offsets).
 // Nbr: neighbour lists; each source with |r|^2 < h2 (strict, never the sink's own source, never
 // padding) is appended to the sink's list through an atomic counter.  Sinks without a list slot
-// carry h2 = -1 and never append.
+// carry h2 = -1 and never append.  NN = false: no nearest-neighbour search (no keys, no groups).
 __device__ __forceinline__ void nbr_append(const ForceParams &fp, int q, int jj) {
   const int k = atomicAdd(&fp.nbr_count[q], 1);
   if (k < fp.nbr_max) fp.nbr_ids[(size_t)q * fp.nbr_max + k] = fp.src.id[jj];
 }
 
-template <class Tr, int P, bool Guard, bool L1, bool Nbr>
+template <class Tr, int P, bool Guard, bool L1, bool Nbr, bool NN>
 __device__ __forceinline__ void tile_compute(const ForceParams &fp, const typename Tr::Tile &tl, int slot, int lg,
                                              int jb, const typename Tr::Sink (&sink)[P], const int (&self)[P],
                                              const int (&q)[P], const typename Tr::Real (&h2)[P],
@@ -789,19 +799,22 @@ __device__ __forceinline__ void tile_compute(const ForceParams &fp, const typena
       const int jidx = L1 ? jb + u : jb + (u << lg);
 #pragma unroll
       for (int p = 0; p < P; ++p) {
-        const typename Tr::Real r2 = Tr::template interact<Guard>(j, sink[p], eps2, jidx, self[p], acc[p], gmin[p]);
+        const typename Tr::Real r2 =
+            Tr::template interact<Guard, NN>(j, sink[p], eps2, jidx, self[p], acc[p], gmin[p]);
         if constexpr (Nbr) {
           if (r2 < h2[p] && jidx < fp.nj && (!Guard || jidx != self[p])) nbr_append(fp, q[p], jidx);
         }
       }
     }
-    const int g0 = L1 ? jb + c : jb + (c << lg);
+    if constexpr (NN) {
+      const int g0 = L1 ? jb + c : jb + (c << lg);
 #pragma unroll
-    for (int p = 0; p < P; ++p) {
-      const Key gk = Tr::group_key(gmin[p]);
-      if (gk < nnk[p]) {
-        nnk[p] = gk;
-        nng[p] = g0;
+      for (int p = 0; p < P; ++p) {
+        const Key gk = Tr::group_key(gmin[p]);
+        if (gk < nnk[p]) {
+          nnk[p] = gk;
+          nng[p] = g0;
+        }
       }
     }
 #pragma unroll
@@ -876,7 +889,7 @@ template <int Order, int Prec, int P, bool L1>
 constexpr int kForceWaves =
     (Prec != NBX_FP64 || P != 1 || (Order == 8 && !L1)) ? 1 : (Order >= 6 ? 2 : (Order == 4 ? 3 : 1));
 
-template <int Order, int Prec, int P, bool L1, bool Nbr>
+template <int Order, int Prec, int P, bool L1, bool Nbr, bool NN>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kForceWaves<Order, Prec, P, L1>)))
 void k_force(const ForceParams fp) {
   using Tr = typename TraitsSel<Order, Prec>::type;
@@ -965,11 +978,11 @@ void k_force(const ForceParams fp) {
 #pragma unroll
     for (int p = 0; p < P; ++p) mine |= (self[p] >> 8) == tile;  // kTile == 256
     if (__any(mine))
-      tile_compute<Tr, P, true, L1, Nbr>(fp, tiles[buf], slot, lg, tile * kTile + slot, sink, self, q, h2, eps2, acc,
-                                         nnk, nng);
+      tile_compute<Tr, P, true, L1, Nbr, NN>(fp, tiles[buf], slot, lg, tile * kTile + slot, sink, self, q, h2, eps2,
+                                             acc, nnk, nng);
     else
-      tile_compute<Tr, P, false, L1, Nbr>(fp, tiles[buf], slot, lg, tile * kTile + slot, sink, self, q, h2, eps2, acc,
-                                          nnk, nng);
+      tile_compute<Tr, P, false, L1, Nbr, NN>(fp, tiles[buf], slot, lg, tile * kTile + slot, sink, self, q, h2, eps2,
+                                              acc, nnk, nng);
     if (tile + 1 < t1) stage(tile + 1, buf ^ 1);
     __syncthreads();
   }
@@ -984,15 +997,16 @@ void k_force(const ForceParams fp) {
 #pragma unroll
     for (int k = 0; k < K; ++k) v[p][k] = acc[p].value(k);
     kk[p] = (uint64_t)nnk[p];
-    ii[p] = nn_rescan<Tr, Order>(fp, tiles[(t1 - 1 - t0) & 1], t1 - 1, sink[p], nnk[p], nng[p], lg, self[p]);
+    ii[p] = NN ? nn_rescan<Tr, Order>(fp, tiles[(t1 - 1 - t0) & 1], t1 - 1, sink[p], nnk[p], nng[p], lg, self[p])
+               : -1;
   }
-  group_reduce<P, K>(L, v, kk, ii, red);
+  group_reduce<P, K, NN>(L, v, kk, ii, red);
 
   if (S == 1) {
     if (slot == 0) {
 #pragma unroll
       for (int p = 0; p < P; ++p)
-        if (q[p] < fp.ni) finalize_sink<Order>(fp, q[p], v[p], ii[p], nullptr);
+        if (q[p] < fp.ni) finalize_sink<Order, NN>(fp, q[p], v[p], ii[p], nullptr);
     }
     return;
   }
@@ -1004,8 +1018,10 @@ void k_force(const ForceParams fp) {
       if (q[p] < fp.ni) {
 #pragma unroll
         for (int k = 0; k < K; ++k) fp.part[((size_t)split * K + k) * fp.ni + q[p]] = v[p][k];
-        fp.part_key[(size_t)split * fp.ni + q[p]] = kk[p];
-        fp.part_idx[(size_t)split * fp.ni + q[p]] = ii[p];
+        if constexpr (NN) {
+          fp.part_key[(size_t)split * fp.ni + q[p]] = kk[p];
+          fp.part_idx[(size_t)split * fp.ni + q[p]] = ii[p];
+        }
       }
     }
   }
@@ -1030,7 +1046,7 @@ struct CombineLds {
   int i[kThreads];
 };
 
-template <int Order>
+template <int Order, bool NN>
 __global__ __launch_bounds__(kThreads) void k_combine(const ForceParams fp, int wlog) {
   constexpr int K = kValues<Order>;
   __shared__ CombineLds<K> red;
@@ -1061,11 +1077,13 @@ __global__ __launch_bounds__(kThreads) void k_combine(const ForceParams fp, int 
     for (int s = r; s < S; s += R) {
 #pragma unroll
       for (int k = 0; k < K; ++k) w[0][k] += fp.part[((size_t)s * K + k) * fp.ni + qg];
-      const uint64_t pk = fp.part_key[(size_t)s * fp.ni + qg];
-      const int pi = fp.part_idx[(size_t)s * fp.ni + qg];
-      if (nn_better(pk, pi, wk[0], wi[0])) {
-        wk[0] = pk;
-        wi[0] = pi;
+      if constexpr (NN) {
+        const uint64_t pk = fp.part_key[(size_t)s * fp.ni + qg];
+        const int pi = fp.part_idx[(size_t)s * fp.ni + qg];
+        if (nn_better(pk, pi, wk[0], wi[0])) {
+          wk[0] = pk;
+          wi[0] = pi;
+        }
       }
     }
   }
@@ -1074,11 +1092,13 @@ __global__ __launch_bounds__(kThreads) void k_combine(const ForceParams fp, int 
   for (int off = 32; off >= W; off >>= 1) {
 #pragma unroll
     for (int k = 0; k < K; ++k) w[0][k] += __shfl_xor(w[0][k], off);
-    const uint64_t ok = __shfl_xor(wk[0], off);
-    const int oi = __shfl_xor(wi[0], off);
-    if (nn_better(ok, oi, wk[0], wi[0])) {
-      wk[0] = ok;
-      wi[0] = oi;
+    if constexpr (NN) {
+      const uint64_t ok = __shfl_xor(wk[0], off);
+      const int oi = __shfl_xor(wi[0], off);
+      if (nn_better(ok, oi, wk[0], wi[0])) {
+        wk[0] = ok;
+        wi[0] = oi;
+      }
     }
   }
   if (R > 1) {
@@ -1096,7 +1116,7 @@ __global__ __launch_bounds__(kThreads) void k_combine(const ForceParams fp, int 
         const int o = j * stride + ql;
 #pragma unroll
         for (int k = 0; k < K; ++k) w[0][k] += red.v[o][k];
-        if (nn_better(red.k[o], red.i[o], wk[0], wi[0])) {
+        if (NN && nn_better(red.k[o], red.i[o], wk[0], wi[0])) {
           wk[0] = red.k[o];
           wi[0] = red.i[o];
         }
@@ -1110,7 +1130,7 @@ __global__ __launch_bounds__(kThreads) void k_combine(const ForceParams fp, int 
       return;
     }
   }
-  finalize_sink<Order>(fp, qg, w[0], wi[0], nullptr);
+  finalize_sink<Order, NN>(fp, qg, w[0], wi[0], nullptr);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1162,7 +1182,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchParams bp) {
       typename Tr::GKey dummy = Tr::gkey_none();
       for (int j0 = slot; j0 < n; j0 += kChunkAcc << lg) {
         const int je = n < j0 + (kChunkAcc << lg) ? n : j0 + (kChunkAcc << lg);
-        for (int j = j0; j < je; j += L) Tr::template interact<true>(lds[j], si, eps2, j, i, acc, dummy);
+        for (int j = j0; j < je; j += L) Tr::template interact<true, false>(lds[j], si, eps2, j, i, acc, dummy);
         acc.template fold<0, K>();
       }
       double w[1][K];
@@ -1170,7 +1190,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchParams bp) {
       int wi[1] = {0};
 #pragma unroll
       for (int k = 0; k < K; ++k) w[0][k] = acc.value(k);
-      group_reduce<1, K>(L, w, wk, wi, red_unused);  // L <= 64: shuffles only
+      group_reduce<1, K, false>(L, w, wk, wi, red_unused);  // L <= 64: shuffles only
       if (slot == 0 && live) {
         const size_t q = (size_t)(b + i);
 #pragma unroll
@@ -1499,6 +1519,17 @@ __global__ __launch_bounds__(256) void k_fill_i32(int32_t *p, int n, int value) 
   if (k < n) p[k] = value;
 }
 
+// Clock sample (measurement): the first lane of workgroup g records the accelerator complex die
+// (XCD) it runs on (hardware register XCC_ID, low 16 bits), the shader-clock cycle counter and the
+// constant-rate counter.  Two samples around a timed region give the mean shader clock per XCD.
+__global__ __launch_bounds__(64) void k_clock_sample(int64_t *out) {
+  if (threadIdx.x != 0) return;
+  const int g = blockIdx.x;
+  out[3 * g + 0] = (int64_t)(__builtin_amdgcn_s_getreg(20 | (15 << 11)) & 0xffff);  // HW_REG_XCC_ID
+  out[3 * g + 1] = (int64_t)clock64();
+  out[3 * g + 2] = (int64_t)wall_clock64();
+}
+
 // ---------------------------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------------------------
@@ -1574,15 +1605,15 @@ LaunchShape choose_shape(int ni, int nj_pad, int prec, int order) {
   return ls;
 }
 
-template <int Order, int Prec, int P, bool L1>
+template <int Order, int Prec, int P, bool L1, bool NN>
 static hipError_t launch_force_t(const ForceParams &fp, const LaunchShape &ls, hipStream_t stream) {
   const dim3 grid(ls.blocks * ls.splits), block(kThreads);
   if (fp.h2) {
     hipError_t e = launch_fill_i32(fp.nbr_count, fp.ni, 0, stream);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_force<Order, Prec, P, L1, true>), grid, block, 0, stream, fp);
+    hipLaunchKernelGGL((k_force<Order, Prec, P, L1, true, NN>), grid, block, 0, stream, fp);
   } else {
-    hipLaunchKernelGGL((k_force<Order, Prec, P, L1, false>), grid, block, 0, stream, fp);
+    hipLaunchKernelGGL((k_force<Order, Prec, P, L1, false, NN>), grid, block, 0, stream, fp);
   }
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && fp.h2) {
@@ -1599,15 +1630,20 @@ static hipError_t launch_force_t(const ForceParams &fp, const LaunchShape &ls, h
   while ((1 << rlog) < ls.splits && (1 << rlog) < kThreads / qmin) ++rlog;
   const int wlog = 8 - rlog;
   const int W = 1 << wlog;
-  hipLaunchKernelGGL(k_combine<Order>, dim3((fp.ni + W - 1) / W), dim3(kThreads), 0, stream, fp, wlog);
+  hipLaunchKernelGGL((k_combine<Order, NN>), dim3((fp.ni + W - 1) / W), dim3(kThreads), 0, stream, fp, wlog);
   return hipGetLastError();
+}
+
+template <int Order, int Prec, bool NN>
+static hipError_t launch_force_nn(const ForceParams &fp, const LaunchShape &ls, hipStream_t stream) {
+  if (ls.sinks_per_lane == 2) return launch_force_t<Order, Prec, 2, true, NN>(fp, ls, stream);
+  if (ls.lanes_log2 == 0) return launch_force_t<Order, Prec, 1, true, NN>(fp, ls, stream);
+  return launch_force_t<Order, Prec, 1, false, NN>(fp, ls, stream);
 }
 
 template <int Order, int Prec>
 static hipError_t launch_force_op(const ForceParams &fp, const LaunchShape &ls, hipStream_t stream) {
-  if (ls.sinks_per_lane == 2) return launch_force_t<Order, Prec, 2, true>(fp, ls, stream);
-  if (ls.lanes_log2 == 0) return launch_force_t<Order, Prec, 1, true>(fp, ls, stream);
-  return launch_force_t<Order, Prec, 1, false>(fp, ls, stream);
+  return fp.nn ? launch_force_nn<Order, Prec, true>(fp, ls, stream) : launch_force_nn<Order, Prec, false>(fp, ls, stream);
 }
 
 hipError_t launch_force(int order, int precision, const ForceParams &fp, const LaunchShape &ls,
@@ -1710,6 +1746,12 @@ hipError_t launch_selfmap(const SourceArrays &src, int nj, int ni, const int64_t
                           hipStream_t stream) {
   if (ni <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_selfmap, dim3(grid_for(ni)), dim3(kThreads), 0, stream, src, nj, ni, ext_id, self);
+  return hipGetLastError();
+}
+
+hipError_t launch_clock_sample(int n_groups, int64_t *out, hipStream_t stream) {
+  if (n_groups <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_clock_sample, dim3(n_groups), dim3(64), 0, stream, out);
   return hipGetLastError();
 }
 

@@ -23,7 +23,7 @@ using namespace nbx;
 
 namespace {
 
-constexpr int kVersion = 10200;  // 1.2.0: order 8 (crackle)
+constexpr int kVersion = 10300;  // 1.3.0: want_nn (kernels without the nearest-neighbour search)
 
 std::string g_open_error;  // message of the last failed nbx_open
 
@@ -94,7 +94,7 @@ struct nbx_ctx {
     nbx_bs_params p{};
     double t = 0.0;
     int64_t blocks = 0, steps = 0;
-    DevBuf dt, tnext, list, acc, jrk, snp, pot, nnid, nnr2, level_count, sched;
+    DevBuf dt, tnext, list, acc, jrk, snp, pot, level_count, sched;
     int parity = 0;  // counter of the next schedule
     BsSched *h_sched = nullptr;  // pinned host copy of the schedule
   } bs;
@@ -109,6 +109,7 @@ struct nbx_ctx {
   // state of the last force call (host path)
   int last_ni = -1;
   bool last_nbr = false;
+  bool last_nn = false;
   std::vector<void *> owned;
   std::string err;
 };
@@ -338,6 +339,7 @@ int enqueue_force(nbx_ctx *c, hipStream_t stream, int ni, const int32_t *d_iaddr
   fp.pot = pot;
   fp.nn_id = nn_id;
   fp.nn_r2 = nn_r2;
+  fp.nn = nn_id != nullptr && nn_r2 != nullptr;  // no outputs: the kernels without the search
   fp.nbr_count = nbr_cnt;
   fp.nbr_ids = nbr_ids;
   fp.part = static_cast<double *>(c->part.p);
@@ -475,15 +477,18 @@ int force_dev(nbx_ctx *c, void *stream, int ni, const int32_t *d_i_addr, double 
   if (ni < 0) return fail(c, NBX_ERR_ARG, "ni < 0");
   if (ni > c->cfg.ni_max) return fail(c, NBX_ERR_CAPACITY, "ni=%d > ni_max=%d", ni, c->cfg.ni_max);
   if (ni == 0) return NBX_OK;
-  if (!d_i_addr || !d_acc || (!d_jerk && c->cfg.order != 2) || !d_pot || !d_nn_id || !d_nn_r2)
+  if (!d_i_addr || !d_acc || (!d_jerk && c->cfg.order != 2) || !d_pot ||
+      (c->cfg.want_nn && (!d_nn_id || !d_nn_r2)))
     return fail(c, NBX_ERR_ARG, "NULL device array");
   if (c->cfg.order >= 6 && !d_snap) return fail(c, NBX_ERR_ARG, "orders 6 and 8 need d_snap");
   if (c->cfg.order == 8 && !d_crackle) return fail(c, NBX_ERR_ARG, "order 8 needs d_crackle");
   if (d_h2 && (c->cfg.nbr_max == 0 || !d_nbr_count || !d_nbr_ids))
     return fail(c, NBX_ERR_ARG, "neighbour lists need nbr_max > 0 and count/id arrays");
   if (c->nj < 1) return fail(c, NBX_ERR_STATE, "no sources in use (nbx_set_nj)");
+  const bool nn = c->cfg.want_nn != 0;
   return enqueue_force(c, static_cast<hipStream_t>(stream), ni, d_i_addr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                       eps2, d_h2, d_acc, d_jerk, d_snap, d_crackle, d_pot, d_nn_id, d_nn_r2, d_nbr_count, d_nbr_ids);
+                       eps2, d_h2, d_acc, d_jerk, d_snap, d_crackle, d_pot, nn ? d_nn_id : nullptr,
+                       nn ? d_nn_r2 : nullptr, d_nbr_count, d_nbr_ids);
 }
 
 }  // namespace
@@ -693,12 +698,14 @@ int nbx_force(nbx_ctx *c, int ni, const int32_t *i_addr, double eps2, const doub
     if (int rc = pinned_release(c, c->stage_i, c->stream)) return rc;
   }
   out_layout(c, ni);
+  const bool nn = c->cfg.want_nn != 0;
   int rc = enqueue_force(c, c->stream, ni, c->d_iaddr, nullptr, nullptr, nullptr, nullptr, nullptr, eps2,
-                         h2 ? c->d_h2 : nullptr, c->d_acc, c->d_jrk, c->d_snp, c->d_crk, c->d_pot, c->d_nnid,
-                         c->d_nnr2, c->d_nbr_cnt, c->d_nbr_ids);
+                         h2 ? c->d_h2 : nullptr, c->d_acc, c->d_jrk, c->d_snp, c->d_crk, c->d_pot,
+                         nn ? c->d_nnid : nullptr, nn ? c->d_nnr2 : nullptr, c->d_nbr_cnt, c->d_nbr_ids);
   if (rc < 0) return rc;
   c->last_ni = ni;
   c->last_nbr = h2 != nullptr;
+  c->last_nn = nn;
   return rc;
 }
 
@@ -763,13 +770,15 @@ static int force_ext_impl(nbx_ctx *c, int ni, const int64_t *id, const double *x
     if (c->predicted) HIP_TRY(c, launch_selfmap(c->src, c->nj, ni, c->d_ext_id, c->d_ext_self, s));
   }
   out_layout(c, ni);
+  const bool nn = c->cfg.want_nn != 0;
   int rc = enqueue_force(c, s, ni, nullptr, c->d_ext_self, c->d_ext_id, c->d_ext_x, c->d_ext_v,
                          ha ? c->d_ext_a : nullptr, eps2, h2 ? c->d_h2 : nullptr, c->d_acc, c->d_jrk, c->d_snp,
-                         c->d_crk, c->d_pot, c->d_nnid, c->d_nnr2, c->d_nbr_cnt, c->d_nbr_ids, nullptr, 0.0,
-                         nullptr, hj ? c->d_ext_j : nullptr);
+                         c->d_crk, c->d_pot, nn ? c->d_nnid : nullptr, nn ? c->d_nnr2 : nullptr, c->d_nbr_cnt,
+                         c->d_nbr_ids, nullptr, 0.0, nullptr, hj ? c->d_ext_j : nullptr);
   if (rc < 0) return rc;
   c->last_ni = ni;
   c->last_nbr = h2 != nullptr;
+  c->last_nn = nn;
   return rc;
 }
 
@@ -801,8 +810,8 @@ int nbx_get_force(nbx_ctx *c, double *acc, double *jerk, double *snap, double *p
     if (jerk && c->d_jrk) HIP_TRY(c, hipMemcpy(jerk, c->d_jrk, n * 24, hipMemcpyDeviceToHost));
     if (snap && c->d_snp) HIP_TRY(c, hipMemcpy(snap, c->d_snp, n * 24, hipMemcpyDeviceToHost));
     if (pot) HIP_TRY(c, hipMemcpy(pot, c->d_pot, n * 8, hipMemcpyDeviceToHost));
-    if (nn_id) HIP_TRY(c, hipMemcpy(nn_id, c->d_nnid, n * 8, hipMemcpyDeviceToHost));
-    if (nn_r2) HIP_TRY(c, hipMemcpy(nn_r2, c->d_nnr2, n * 8, hipMemcpyDeviceToHost));
+    if (nn_id && c->last_nn) HIP_TRY(c, hipMemcpy(nn_id, c->d_nnid, n * 8, hipMemcpyDeviceToHost));
+    if (nn_r2 && c->last_nn) HIP_TRY(c, hipMemcpy(nn_r2, c->d_nnr2, n * 8, hipMemcpyDeviceToHost));
     return rc;
   }
   // small: one copy of the error counters and the results (laid out for last_ni by the force call)
@@ -821,8 +830,8 @@ int nbx_get_force(nbx_ctx *c, double *acc, double *jerk, double *snap, double *p
   if (jerk && c->d_jrk) std::memcpy(jerk, from(c->d_jrk), n * 24);
   if (snap && c->d_snp) std::memcpy(snap, from(c->d_snp), n * 24);
   if (pot) std::memcpy(pot, from(c->d_pot), n * 8);
-  if (nn_id) std::memcpy(nn_id, from(c->d_nnid), n * 8);
-  if (nn_r2) std::memcpy(nn_r2, from(c->d_nnr2), n * 8);
+  if (nn_id && c->last_nn) std::memcpy(nn_id, from(c->d_nnid), n * 8);
+  if (nn_r2 && c->last_nn) std::memcpy(nn_r2, from(c->d_nnr2), n * 8);
   return rc;
 }
 
@@ -1111,7 +1120,8 @@ BlockStepParams bs_params(nbx_ctx *c) {
   return bp;
 }
 
-// Forces on the first ni particles of the list at time t into the integrator's force rows.  With
+// Forces on the first ni particles of the list at time t into the integrator's force rows (the
+// kernels without the nearest-neighbour search: the integrator never uses it).  With
 // step != nullptr (a block step) the corrector may be fused into the combine kernel (*fused).
 int bs_force(nbx_ctx *c, int ni, double t, const BlockStepParams *step = nullptr, bool *fused = nullptr) {
   c->t_pred = t;
@@ -1119,8 +1129,7 @@ int bs_force(nbx_ctx *c, int ni, double t, const BlockStepParams *step = nullptr
   return enqueue_force(c, c->stream, ni, static_cast<const int32_t *>(c->bs.list.p), nullptr, nullptr, nullptr,
                        nullptr, nullptr, c->bs.p.eps2, nullptr, static_cast<double *>(c->bs.acc.p),
                        static_cast<double *>(c->bs.jrk.p), static_cast<double *>(c->bs.snp.p), nullptr,
-                       static_cast<double *>(c->bs.pot.p), static_cast<int64_t *>(c->bs.nnid.p),
-                       static_cast<double *>(c->bs.nnr2.p), nullptr, nullptr, step, t, fused);
+                       static_cast<double *>(c->bs.pot.p), nullptr, nullptr, nullptr, nullptr, step, t, fused);
 }
 
 // Schedule the next block step; returns (t_next, count, clamped so far) through the pinned copy.
@@ -1170,8 +1179,6 @@ int nbx_bs_init(nbx_ctx *c, int n, const int64_t *id, const double *m, const dou
   rc = rc ? rc : grow(c, c->bs.jrk, N * 24);
   if (c->cfg.order == 6) rc = rc ? rc : grow(c, c->bs.snp, N * 24);
   rc = rc ? rc : grow(c, c->bs.pot, N * 8);
-  rc = rc ? rc : grow(c, c->bs.nnid, N * 8);
-  rc = rc ? rc : grow(c, c->bs.nnr2, N * 8);
   rc = rc ? rc : grow(c, c->bs.level_count, kBsLevels * sizeof(int));
   rc = rc ? rc : grow(c, c->bs.sched, sizeof(BsSched));
   rc = rc ? rc : grow(c, c->up, N * (8 + 8 + 24 + 24) + 256);
@@ -1389,6 +1396,9 @@ int nbx_tune(nbx_ctx *c, int ni_max, int32_t *shapes_out, int n_classes) {
     ~Reset() { c->force_shape = nullptr; }
   } reset{c};
   const int pr = c->precision;
+  // the kernels later calls use: without the nearest-neighbour search while the device integrator
+  // runs (it never needs it) or when the context does not want it
+  const bool nn = !c->bs.ready && c->cfg.want_nn != 0;
   c->tune_ntiles[pr] = 0;
   for (auto &t : c->tuned[pr]) t = nbx_ctx::TunedShape{};
   const int kmax = ni_class(ni_max);
@@ -1406,8 +1416,8 @@ int nbx_tune(nbx_ctx *c, int ni_max, int32_t *shapes_out, int n_classes) {
       c->force_shape = &cand;
       auto launch = [&]() {
         return enqueue_force(c, c->stream, ni, c->d_iaddr, nullptr, nullptr, nullptr, nullptr, nullptr, 0.0, nullptr,
-                             c->d_acc, c->d_jrk ? c->d_jrk : c->d_acc, c->d_snp, c->d_crk, c->d_pot, c->d_nnid,
-                             c->d_nnr2, nullptr, nullptr);
+                             c->d_acc, c->d_jrk ? c->d_jrk : c->d_acc, c->d_snp, c->d_crk, c->d_pot,
+                             nn ? c->d_nnid : nullptr, nn ? c->d_nnr2 : nullptr, nullptr, nullptr);
       };
       if (int rc = launch()) return rc;  // warm-up, and an estimate of the launch time
       HIP_TRY(c, hipEventRecord(ev.e0, c->stream));
@@ -1451,6 +1461,23 @@ int nbx_sync(nbx_ctx *c, void *stream) {
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   HIP_TRY(c, hipDeviceSynchronize());
   return collect_errors(c);
+}
+
+int nbx_clock_sample(nbx_ctx *c, void *stream, int n_groups, int64_t *d_out) {
+  if (int rc = check_ctx(c)) return rc;
+  if (n_groups < 1 || !d_out) return fail(c, NBX_ERR_ARG, "need n_groups >= 1 and an output array");
+  HIP_TRY(c, launch_clock_sample(n_groups, d_out, static_cast<hipStream_t>(stream)));
+  return NBX_OK;
+}
+
+int nbx_clock_rates(nbx_ctx *c, int *wall_khz, int *sclk_max_khz) {
+  if (int rc = check_ctx(c)) return rc;
+  int w = 0, s = 0;
+  HIP_TRY(c, hipDeviceGetAttribute(&w, hipDeviceAttributeWallClockRate, c->cfg.device));
+  HIP_TRY(c, hipDeviceGetAttribute(&s, hipDeviceAttributeClockRate, c->cfg.device));
+  if (wall_khz) *wall_khz = w;
+  if (sclk_max_khz) *sclk_max_khz = s;
+  return NBX_OK;
 }
 
 int nbx_launch_shape(nbx_ctx *c, int ni, int *lanes_per_sink, int *sinks_per_lane, int *splits, int *workgroups) {

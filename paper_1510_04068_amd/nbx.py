@@ -46,7 +46,7 @@ EXPORTS = (
     "nbx_get_predicted", "nbx_get_j", "nbx_set_j_dev", "nbx_force_dev", "nbx_sync", "nbx_launch_shape",
     "nbx_batch_setup", "nbx_batch_tune", "nbx_batch_force_dev", "nbx_force_vjp_dev",
     "nbx_bs_init", "nbx_bs_step", "nbx_bs_run", "nbx_bs_get_state", "nbx_bs_energy", "nbx_tune",
-    "nbx_get_crackle", "nbx_force8_dev", "nbx_force_ext8",
+    "nbx_get_crackle", "nbx_force8_dev", "nbx_force_ext8", "nbx_clock_sample", "nbx_clock_rates",
 )
 NBX_BATCH_NMAX = 128
 
@@ -59,6 +59,7 @@ class nbx_config(ctypes.Structure):
         ("nj_max", ctypes.c_int),
         ("ni_max", ctypes.c_int),
         ("nbr_max", ctypes.c_int),
+        ("want_nn", ctypes.c_int),
     ]
 
 
@@ -141,6 +142,8 @@ def load(path: str = LIB_PATH):
         "nbx_get_crackle": ([_P, _P], _I),
         "nbx_force8_dev": ([_P, _P, _I, _P, _D] + [_P] * 10, _I),
         "nbx_force_ext8": ([_P, _I, _P, _P, _P, _P, _P, _D, _P], _I),
+        "nbx_clock_sample": ([_P, _P, _I, _P], _I),
+        "nbx_clock_rates": ([_P, _P, _P], _I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -249,13 +252,14 @@ def nbx_device_count() -> int:
     return n.value if rc == NBX_OK else 0
 
 
-def nbx_open(device=0, order=4, precision=NBX_FP64, nj_max=1, ni_max=1, nbr_max=0):
-    cfg = nbx_config(device, order, precision, nj_max, ni_max, nbr_max)
+def nbx_open(device=0, order=4, precision=NBX_FP64, nj_max=1, ni_max=1, nbr_max=0, want_nn=True):
+    cfg = nbx_config(device, order, precision, nj_max, ni_max, nbr_max, 1 if want_nn else 0)
     ctx = ctypes.c_void_p()
     rc = load().nbx_open(ctypes.byref(ctx), ctypes.byref(cfg))
     if rc < 0:
         raise NbxError(rc, load().nbx_last_error(None).decode())
-    _CTX_INFO[ctx.value] = {"device": int(device), "order": int(order), "nbr_max": int(nbr_max), "batch_n": 0}
+    _CTX_INFO[ctx.value] = {"device": int(device), "order": int(order), "nbr_max": int(nbr_max), "batch_n": 0,
+                            "want_nn": bool(want_nn)}
     return ctx
 
 
@@ -323,14 +327,17 @@ def nbx_force_ext8(ctx, id, x, v, a, jerk, eps2, h2=None):
 
 def nbx_get_force(ctx, ni, order=4):
     """Results of the last force call on ni sinks, as a dict of numpy arrays (plus 'status');
-    order 8 adds 'crackle' (read by nbx_get_crackle)."""
+    order 8 adds 'crackle' (read by nbx_get_crackle).  nn_id and nn_r2 are None for a context
+    opened with want_nn=False."""
+    info = _CTX_INFO.get(getattr(ctx, "value", None))
+    nn = info is None or info.get("want_nn", True)
     out = {
         "acc": np.empty((ni, 3)),
         "jerk": np.empty((ni, 3)) if order != 2 else None,
         "snap": np.empty((ni, 3)) if order >= 6 else None,
         "pot": np.empty(ni),
-        "nn_id": np.empty(ni, dtype=np.int64),
-        "nn_r2": np.empty(ni),
+        "nn_id": np.empty(ni, dtype=np.int64) if nn else None,
+        "nn_r2": np.empty(ni) if nn else None,
     }
     rc = load().nbx_get_force(ctx, _ptr(out["acc"]), _ptr(out["jerk"]), _ptr(out["snap"]), _ptr(out["pot"]),
                               _ptr(out["nn_id"]), _ptr(out["nn_r2"]))
@@ -418,6 +425,20 @@ def nbx_force8_dev(ctx, stream, ni, d_i_addr, eps2, d_h2, d_acc, d_jerk, d_snap,
                         d_nbr_count, d_nbr_ids)
     rc = load().nbx_force8_dev(ctx, _stream(stream), ni, p[0], float(eps2), *p[1:])
     return _check(ctx, rc)
+
+
+def nbx_clock_sample(ctx, stream, n_groups, d_out):
+    """Enqueue a clock sample: d_out (int64 device tensor, >= 3 n_groups) receives per workgroup
+    (XCD, shader-clock cycles, constant-rate ticks)."""
+    p = _dptrs(ctx, [("d_out", d_out, "i64", 3 * int(n_groups))])
+    return _check(ctx, load().nbx_clock_sample(ctx, _stream(stream), int(n_groups), p[0]))
+
+
+def nbx_clock_rates(ctx):
+    """(constant counter rate, nominal maximum shader clock), in kHz."""
+    w, s = ctypes.c_int(0), ctypes.c_int(0)
+    _check(ctx, load().nbx_clock_rates(ctx, ctypes.byref(w), ctypes.byref(s)))
+    return w.value, s.value
 
 
 def nbx_sync(ctx, stream=0):
@@ -536,10 +557,10 @@ def nbx_bs_energy(ctx):
 class Context:
     """Owns one nbx context; thin convenience wrapper over the entry points above."""
 
-    def __init__(self, order=4, precision=NBX_FP64, nj_max=1, ni_max=1, nbr_max=0, device=0):
+    def __init__(self, order=4, precision=NBX_FP64, nj_max=1, ni_max=1, nbr_max=0, device=0, want_nn=True):
         self.order = order
         self.nbr_max = nbr_max
-        self.ctx = nbx_open(device, order, precision, nj_max, ni_max, nbr_max)
+        self.ctx = nbx_open(device, order, precision, nj_max, ni_max, nbr_max, want_nn)
         self._ni = None
 
     def close(self):

@@ -54,8 +54,9 @@ def cond_err_vec(q, r, cond):
 
 
 def check_nn(out, ref, xp, sel_addr, prec, ids):
-    """Nearest neighbour: exact in FP64; in mixed, any source whose exact |r|^2 is within FP32
-    resolution of the true minimum is accepted.  The reported r2 must be that source's exact
+    """Nearest neighbour: exact in FP64; in mixed, any source whose exact |r|^2 is within 2e-6
+    relative of the true minimum is accepted (the choice is made on FP32 |r|^2 from double-single
+    differences, a few FP32 roundings per candidate).  The reported r2 must be that source's exact
     FP64 |r|^2."""
     nn = out["nn_id"]
     none = ref["nn_id"] < 0
@@ -76,7 +77,7 @@ def check_nn(out, ref, xp, sel_addr, prec, ids):
     if prec == nbx.NBX_FP64:
         assert np.all(r2_exact <= ref["nn_r2"][ok] * (1 + 1e-14))
     else:
-        assert np.all(r2_exact <= ref["nn_r2"][ok] * (1 + 4e-7))
+        assert np.all(r2_exact <= ref["nn_r2"][ok] * (1 + 2e-6))
     return int(np.sum(nn[ok] != ref["nn_id"][ok]))
 
 

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_version():
-    assert nbx.nbx_version() == 10200
+    assert nbx.nbx_version() == 10300
 
 
 def test_argument_errors_without_device():

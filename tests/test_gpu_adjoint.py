@@ -154,3 +154,57 @@ def test_hermite_trajectory_gradient():
         say("  direction %d: autograd %.10e fd %.10e" % (k, ad, fd))
         assert abs(ad - fd) <= 1e-6 * abs(fd) + 1e-9
     fc.close()
+
+
+def _oracle_hermite16(x, v, m, eps2, dt, steps):
+    """The same 16 shared 4th-order Hermite steps driven entirely by the oracle: its forces, its
+    predictor (from t = 0 to dt) and its corrector."""
+    n = len(m)
+    ids = np.arange(n, dtype=np.int64)
+    f = oracle.force(4, eps2, ids, m, x, v, ids, x, v)
+    a0, j0 = f["acc"], f["jerk"]
+    zeros_t = np.zeros(n)
+    for _ in range(steps):
+        xp, vp, _ = oracle.predict(4, dt, zeros_t, x, v, a0, j0)
+        f = oracle.force(4, eps2, ids, m, xp, vp, ids, xp, vp)
+        x, v = oracle.hermite4_correct(dt, xp, vp, a0, j0, f["acc"], f["jerk"])
+        a0, j0 = f["acc"], f["jerk"]
+    return x, v
+
+
+def test_hermite_trajectory_gradient_vs_oracle():
+    """The checkpointed gradient through 16 Hermite steps (dt = 1/512, N = 256, FP64) against central
+    finite differences of the oracle-driven trajectory (oracle forces, predictor and corrector), so
+    the gradient is checked against a trajectory the library never computed."""
+    torch = pytest.importorskip("torch")
+    from paper_1510_04068_amd.autograd import hermite4
+
+    n, eps2, dt, steps = 256, 1e-6, 1.0 / 512, 16
+    say("hermite trajectory gradient vs oracle n=%d" % n)
+    src = nbody_ics.make_sources(n, seed=76, time_offsets=False)
+    rng = np.random.default_rng(77)
+    wx_h, wv_h = rng.normal(size=(n, 3)), rng.normal(size=(n, 3))
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    fc = _fc(torch, n, nbx.NBX_FP64)
+    x, v, m = T(src.x).requires_grad_(), T(src.v).requires_grad_(), T(src.m).requires_grad_()
+    x1, v1 = hermite4(x, v, m, eps2, dt, steps, fc, checkpoint=True)
+    ((T(wx_h) * x1).sum() + (T(wv_h) * v1).sum()).backward()
+    gx, gv, gm = x.grad.cpu().numpy(), v.grad.cpu().numpy(), m.grad.cpu().numpy()
+    fc.close()
+    ox, ov = _oracle_hermite16(src.x, src.v, src.m, eps2, dt, steps)
+    np.testing.assert_allclose(x1.detach().cpu().numpy(), ox, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(v1.detach().cpu().numpy(), ov, rtol=0, atol=1e-11)
+
+    def loss(xx, vv, mm):
+        a, b = _oracle_hermite16(xx, vv, mm, eps2, dt, steps)
+        return float(np.sum(wx_h * a) + np.sum(wv_h * b))
+
+    for k in range(3):
+        dx, dv, dm = rng.normal(size=(n, 3)), rng.normal(size=(n, 3)), rng.normal(size=n) * src.m
+        h = 1e-6
+        fd = (loss(src.x + h * dx, src.v + h * dv, src.m + h * dm) -
+              loss(src.x - h * dx, src.v - h * dv, src.m - h * dm)) / (2 * h)
+        ad = float(np.sum(gx * dx) + np.sum(gv * dv) + np.sum(gm * dm))
+        say("  direction %d: library gradient %.10e oracle finite difference %.10e" % (k, ad, fd))
+        assert abs(ad - fd) <= 1e-6 * abs(fd) + 1e-9
