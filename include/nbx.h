@@ -228,6 +228,26 @@ int nbx_force_dev(nbx_ctx *ctx, void *stream, int ni, const int32_t *d_i_addr, d
                   double *d_pot, int64_t *d_nn_id, double *d_nn_r2, int32_t *d_nbr_count,
                   int64_t *d_nbr_ids);
 
+/* For callers that cannot allocate device memory while they run (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): nbx_force_dev without any allocation.
+ * nbx_force_dev grows the context's split-partial buffers with hipMalloc when a call needs more;
+ * this variant keeps the partials in a static device area of NBX_NOALLOC_SCRATCH_BYTES that every
+ * GPU the library runs on holds for the life of the process (its address is looked up once per
+ * device by nbx_open), and calls no hipMalloc, hipFree or allocating library routine.  Same
+ * arguments, orders (2, 4, 6; order 8 is NBX_ERR_ARG), want_nn behaviour and errors as
+ * nbx_force_dev: ni > ni_max is NBX_ERR_CAPACITY.  Sizes: the partials of S source splits take
+ * S * ni * (8 * values + 12) bytes (values: 4, 7 or 10 for orders 2, 4, 6); when the launch shape
+ * nbx_force_dev would use needs more than the area holds, the call lowers S until they fit (down to
+ * one split, which needs none), so results then differ from nbx_force_dev by summation order only,
+ * and are bit-identical where the shape fits.  Every call on one GPU shares its area, which keeps
+ * the last call's partials: calls that overlap on one GPU (other streams, other contexts, other
+ * host threads) race and must be ordered by the caller. */
+#define NBX_NOALLOC_SCRATCH_BYTES (64u << 20)
+int nbx_force_dev_noalloc(nbx_ctx *ctx, void *stream, int ni, const int32_t *d_i_addr, double eps2,
+                          const double *d_h2, double *d_acc, double *d_jerk, double *d_snap,
+                          double *d_pot, int64_t *d_nn_id, double *d_nn_r2, int32_t *d_nbr_count,
+                          int64_t *d_nbr_ids);
+
 /* Order 8 (Methods > Numerical Accuracy; Conclusion): as nbx_force_dev, with d_snap and d_crackle
  * [ni][3] both required.
  * NBX_ERR_ARG on a context of another order. */

@@ -12,6 +12,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -48,6 +49,17 @@ constexpr size_t kErrDoubles = 8;  // the error counters head the output block (
 // better than a host memcpy followed by one DMA.
 constexpr size_t kStageMax = size_t(1) << 20;
 
+// Split partials of the allocation-free entry point (nbx_force_dev_noalloc) live in this
+// file-scope device array, one copy per GPU for the life of the process.  Host code never uses
+// its name as an address: nbx_open looks up its device address once per device (scratch_setup)
+// and every launch takes that pointer.
+constexpr size_t kNoallocScratchBytes = size_t(NBX_NOALLOC_SCRATCH_BYTES);
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};  // device address of `scratch` on each device
+
 }  // namespace
 
 struct nbx_ctx {
@@ -76,6 +88,7 @@ struct nbx_ctx {
   int64_t *d_nbr_ids = nullptr;
   // split-combine scratch
   DevBuf part, part_key, part_idx;
+  void *noalloc_scratch = nullptr;  // this device's static scratch (nbx_force_dev_noalloc)
   int *d_err = nullptr;  // [0] bad sink address, [1] bad source address, [2] nbr overflow, [3] dt clamped
                          // (the first 16 bytes of d_out)
   // set_j staging (host path), grown on demand
@@ -175,6 +188,23 @@ int grow(nbx_ctx *c, DevBuf &b, size_t bytes) {
 
 int set_device(nbx_ctx *c) {
   HIP_TRY(c, hipSetDevice(c->cfg.device));
+  return NBX_OK;
+}
+
+// Device address of the static scratch on the context's device (current): looked up once per
+// device and kept for the life of the process.
+int scratch_setup(nbx_ctx *c) {
+  const int d = c->cfg.device;
+  if (d < 0 || d >= kMaxDevices) return fail(c, NBX_ERR_NO_DEVICE, "device %d beyond %d", d, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[d]) {
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(c, e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(c, NBX_ERR_DEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[d] = ptr;
+  }
+  c->noalloc_scratch = g_scratch_ptr[d];
   return NBX_OK;
 }
 
@@ -305,15 +335,36 @@ int enqueue_force(nbx_ctx *c, hipStream_t stream, int ni, const int32_t *d_iaddr
                   double eps2, const double *d_h2, double *acc, double *jrk, double *snp, double *crk, double *pot,
                   int64_t *nn_id, double *nn_r2, int32_t *nbr_cnt, int64_t *nbr_ids,
                   const BlockStepParams *bs = nullptr, double bs_t1 = 0.0, bool *fused = nullptr,
-                  const double *ext_j = nullptr) {
+                  const double *ext_j = nullptr, void *fixed_scratch = nullptr) {
   if (fused) *fused = false;
   if (!c->predicted) return fail(c, NBX_ERR_STATE, "nbx_force before nbx_predict");
   if (!(eps2 >= 0.0)) return fail(c, NBX_ERR_ARG, "eps2 must be >= 0 (got %g)", eps2);
   if (ni == 0) return NBX_OK;
   const int nj_pad = (c->nj + kTile - 1) / kTile * kTile;
-  const LaunchShape ls = ctx_shape(c, ni, nj_pad);
-  int rc = ensure_scratch(c, ni, ls);
-  if (rc) return rc;
+  LaunchShape ls = ctx_shape(c, ni, nj_pad);
+  double *part = nullptr;
+  uint64_t *part_key = nullptr;
+  int32_t *part_idx = nullptr;
+  if (fixed_scratch) {
+    // the partials go to the fixed area: fewer source splits when the shape needs more room
+    const size_t K = (size_t)values_per_sink(c->cfg.order);
+    const size_t per_split = align16((size_t)ni * K * 8) + align16((size_t)ni * 8) + align16((size_t)ni * 4);
+    const size_t smax = kNoallocScratchBytes / per_split;
+    if ((size_t)ls.splits > smax) ls.splits = smax >= 1 ? (int)smax : 1;
+    if (ls.splits > 1) {
+      char *p = static_cast<char *>(fixed_scratch);
+      part = reinterpret_cast<double *>(p);
+      p += align16((size_t)ls.splits * (size_t)ni * K * 8);
+      part_key = reinterpret_cast<uint64_t *>(p);
+      p += align16((size_t)ls.splits * (size_t)ni * 8);
+      part_idx = reinterpret_cast<int32_t *>(p);
+    }
+  } else {
+    if (int rc = ensure_scratch(c, ni, ls)) return rc;
+    part = static_cast<double *>(c->part.p);
+    part_key = static_cast<uint64_t *>(c->part_key.p);
+    part_idx = static_cast<int32_t *>(c->part_idx.p);
+  }
   ForceParams fp{};
   fp.src = c->src;
   fp.nj = c->nj;
@@ -342,9 +393,9 @@ int enqueue_force(nbx_ctx *c, hipStream_t stream, int ni, const int32_t *d_iaddr
   fp.nn = nn_id != nullptr && nn_r2 != nullptr;  // no outputs: the kernels without the search
   fp.nbr_count = nbr_cnt;
   fp.nbr_ids = nbr_ids;
-  fp.part = static_cast<double *>(c->part.p);
-  fp.part_key = static_cast<uint64_t *>(c->part_key.p);
-  fp.part_idx = static_cast<int32_t *>(c->part_idx.p);
+  fp.part = part;
+  fp.part_key = part_key;
+  fp.part_idx = part_idx;
   fp.err = c->d_err;
   if (bs && ls.splits > 1 && !d_h2) {
     fp.bs_fuse = 1;
@@ -470,10 +521,11 @@ int collect_errors(nbx_ctx *c) {
   return errors_from(c, h);
 }
 
-// Shared by nbx_force_dev and nbx_force8_dev (d_crackle: order 8 only).
+// Shared by nbx_force_dev, nbx_force8_dev (d_crackle: order 8 only) and nbx_force_dev_noalloc
+// (fixed_scratch: the static scratch instead of the context's split buffers).
 int force_dev(nbx_ctx *c, void *stream, int ni, const int32_t *d_i_addr, double eps2, const double *d_h2,
               double *d_acc, double *d_jerk, double *d_snap, double *d_crackle, double *d_pot, int64_t *d_nn_id,
-              double *d_nn_r2, int32_t *d_nbr_count, int64_t *d_nbr_ids) {
+              double *d_nn_r2, int32_t *d_nbr_count, int64_t *d_nbr_ids, void *fixed_scratch = nullptr) {
   if (ni < 0) return fail(c, NBX_ERR_ARG, "ni < 0");
   if (ni > c->cfg.ni_max) return fail(c, NBX_ERR_CAPACITY, "ni=%d > ni_max=%d", ni, c->cfg.ni_max);
   if (ni == 0) return NBX_OK;
@@ -488,7 +540,8 @@ int force_dev(nbx_ctx *c, void *stream, int ni, const int32_t *d_i_addr, double 
   const bool nn = c->cfg.want_nn != 0;
   return enqueue_force(c, static_cast<hipStream_t>(stream), ni, d_i_addr, nullptr, nullptr, nullptr, nullptr, nullptr,
                        eps2, d_h2, d_acc, d_jerk, d_snap, d_crackle, d_pot, nn ? d_nn_id : nullptr,
-                       nn ? d_nn_r2 : nullptr, d_nbr_count, d_nbr_ids);
+                       nn ? d_nn_r2 : nullptr, d_nbr_count, d_nbr_ids, nullptr, 0.0, nullptr, nullptr,
+                       fixed_scratch);
 }
 
 }  // namespace
@@ -534,6 +587,7 @@ int nbx_open(nbx_ctx **out, const nbx_config *cfg) {
     return rc;
   };
   if (int rc = set_device(c)) return bail(rc);
+  if (int rc = scratch_setup(c)) return bail(rc);
   {
     hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
     if (e != hipSuccess) return bail(hip_fail(c, e, "hipStreamCreate"));
@@ -954,6 +1008,16 @@ int nbx_force_dev(nbx_ctx *c, void *stream, int ni, const int32_t *d_i_addr, dou
   if (c->cfg.order == 8) return fail(c, NBX_ERR_ARG, "order 8 forces go through nbx_force8_dev");
   return force_dev(c, stream, ni, d_i_addr, eps2, d_h2, d_acc, d_jerk, d_snap, nullptr, d_pot, d_nn_id, d_nn_r2,
                    d_nbr_count, d_nbr_ids);
+}
+
+int nbx_force_dev_noalloc(nbx_ctx *c, void *stream, int ni, const int32_t *d_i_addr, double eps2,
+                          const double *d_h2, double *d_acc, double *d_jerk, double *d_snap, double *d_pot,
+                          int64_t *d_nn_id, double *d_nn_r2, int32_t *d_nbr_count, int64_t *d_nbr_ids) {
+  if (int rc = check_ctx(c)) return rc;
+  if (c->cfg.order == 8) return fail(c, NBX_ERR_ARG, "order 8 forces go through nbx_force8_dev");
+  if (!c->noalloc_scratch) return fail(c, NBX_ERR_STATE, "static scratch not set up for this device");
+  return force_dev(c, stream, ni, d_i_addr, eps2, d_h2, d_acc, d_jerk, d_snap, nullptr, d_pot, d_nn_id, d_nn_r2,
+                   d_nbr_count, d_nbr_ids, c->noalloc_scratch);
 }
 
 int nbx_force8_dev(nbx_ctx *c, void *stream, int ni, const int32_t *d_i_addr, double eps2, const double *d_h2,

@@ -47,7 +47,9 @@ EXPORTS = (
     "nbx_batch_setup", "nbx_batch_tune", "nbx_batch_force_dev", "nbx_force_vjp_dev",
     "nbx_bs_init", "nbx_bs_step", "nbx_bs_run", "nbx_bs_get_state", "nbx_bs_energy", "nbx_tune",
     "nbx_get_crackle", "nbx_force8_dev", "nbx_force_ext8", "nbx_clock_sample", "nbx_clock_rates",
+    "nbx_force_dev_noalloc",
 )
+NBX_NOALLOC_SCRATCH_BYTES = 64 << 20
 NBX_BATCH_NMAX = 128
 
 
@@ -144,6 +146,7 @@ def load(path: str = LIB_PATH):
         "nbx_force_ext8": ([_P, _I, _P, _P, _P, _P, _P, _D, _P], _I),
         "nbx_clock_sample": ([_P, _P, _I, _P], _I),
         "nbx_clock_rates": ([_P, _P, _P], _I),
+        "nbx_force_dev_noalloc": ([_P, _P, _I, _P, _D] + [_P] * 9, _I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -412,6 +415,17 @@ def nbx_force_dev(ctx, stream, ni, d_i_addr, eps2, d_h2, d_acc, d_jerk, d_snap, 
                          ("d_pot", d_pot, "f64", 1), ("d_nn_id", d_nn_id, "i64", 1), ("d_nn_r2", d_nn_r2, "f64", 1)),
                         d_nbr_count, d_nbr_ids)
     rc = load().nbx_force_dev(ctx, _stream(stream), ni, p[0], float(eps2), *p[1:])
+    return _check(ctx, rc)
+
+
+def nbx_force_dev_noalloc(ctx, stream, ni, d_i_addr, eps2, d_h2, d_acc, d_jerk, d_snap, d_pot, d_nn_id, d_nn_r2,
+                          d_nbr_count=None, d_nbr_ids=None):
+    ni = int(ni)
+    p = _force_dev_args(ctx, ni, d_i_addr, d_h2,
+                        (("d_acc", d_acc, "f64", 3), ("d_jerk", d_jerk, "f64", 3), ("d_snap", d_snap, "f64", 3),
+                         ("d_pot", d_pot, "f64", 1), ("d_nn_id", d_nn_id, "i64", 1), ("d_nn_r2", d_nn_r2, "f64", 1)),
+                        d_nbr_count, d_nbr_ids)
+    rc = load().nbx_force_dev_noalloc(ctx, _stream(stream), ni, p[0], float(eps2), *p[1:])
     return _check(ctx, rc)
 
 
