@@ -256,6 +256,26 @@ def timed(torch, nbx, ctx, w, ni, stream, steps, warmup, times=None, flush=None,
     return (t1 - t0) / steps, sum(ks) / steps
 
 
+def launch_floor(torch, stream, reps=200):
+    """Median time of two dependent minimal kernels on the stream, HIP events around them: the
+    floor under a force launch (gravity kernel + combine kernel) that does no work."""
+    x = torch.zeros(1, dtype=torch.float32, device="cuda")
+    for _ in range(10):
+        x.add_(1.0)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        x.add_(1.0)
+        x.add_(1.0)
+        e1.record(stream)
+        ts.append((e0, e1))
+    torch.cuda.synchronize()
+    us = sorted(a.elapsed_time(b) * 1e3 for a, b in ts)
+    return us[len(us) // 2]
+
+
 def timed_sweep(torch, nbx, ctx, w, ni, stream, min_reps, budget_s=0.02, times=None):
     """timed() for one sweep point: warm up for ~budget/4 (at least 2 steps) so that the clocks have
     settled after the previous point, then time enough steps for ~budget of force-kernel time."""
@@ -813,11 +833,16 @@ def main():
             tune_s = time.perf_counter() - t0
             print("bench: tuned launch shapes in %.1f s" % tune_s, file=sys.stderr, flush=True)
         sweep_ni = [int(k) for k in args.sweep_ni.split(",")] if args.sweep_ni else [1 << e for e in range(18)]
+        floor_us = launch_floor(torch, stream)
+        print("bench: launch floor (two dependent empty-work kernels) %.2f us" % floor_us, file=sys.stderr,
+              flush=True)
         for ni in sweep_ni:
             row = {"ni": ni}
             time_row(ctx, row, ni, "")
             if ctx_t is not None:
                 time_row(ctx_t, row, ni, "_tuned")
+            for name in ("fp64", "mixed"):
+                row[name + "_above_floor_us"] = round(row[name + "_kernel_ms_median"] * 1e3 - floor_us, 3)
             sweep.append(row)
             print("bench: sweep %s" % json.dumps(row), file=sys.stderr, flush=True)
         if ctx_t is not None:
@@ -933,6 +958,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "sweep": sweep,
+        "launch_floor_us": floor_us if sweep else None,
         "tune_seconds": tune_s,
     }
     if o2 is not None:

@@ -54,13 +54,16 @@ namespace nbx {
 
 constexpr int kChunkAcc = 16;  // acceleration terms summed in plain FP32/FP64 before a fold
 constexpr int kChunk = 64;     // same for jerk, pot and snap (a multiple of kChunkAcc)
+// The gravity kernel's long-chunk variant (workgroups that run several source tiles with one lane
+// per sink) sums Tr::kLongChunk acceleration terms per chunk: fewer folds per interaction, while
+// the one-off re-scan of a nearest-neighbour group (one chunk long) stays small next to the loop.
 constexpr int kCombineQ = 16;  // fewest sinks per combine workgroup (when there are that many)
 
 // ---------------------------------------------------------------------------------------------
 // Compensated accumulation: K running values, each a plain chunk sum that is folded every
-// kChunkAcc terms (the acceleration, values 0..2) or kChunk terms (the others) into a running
-// total: the summation error of a chunk grows with its length, and the acceleration carries the
-// tightest bound.  FP64 chunks fold into a (hi, lo) pair with TwoSum (Knuth), i.e. a double-double
+// kChunkAcc terms (the acceleration, values 0..2; Tr::kLongChunk in the gravity kernel's long-chunk
+// variant) or kChunk terms (the others) into a running total: the summation error of a chunk grows
+// with its length, and the acceleration carries the tightest bound.  FP64 chunks fold into a (hi, lo) pair with TwoSum (Knuth), i.e. a double-double
 // total; FP32 chunks fold into an FP64 total (a convert and an FP64 add, cheaper in issue slots
 // than a single-single TwoSum and more accurate).
 // ---------------------------------------------------------------------------------------------
@@ -156,6 +159,9 @@ struct Mixed {
   using Real = float;
   using Key = uint32_t;
   static constexpr int kK = kValues<Order>;
+  // long chunks: acceleration terms per FP32 chunk before the fold into FP64 (the chunk's own
+  // rounding stays a small part of the error: measured 1.8e-8 against ~1e-7 condition-normalised)
+  static constexpr int kLongChunk = 32;
   using Tile = MixedTile<Order>;
   struct Sink {
     float xh[3], xl[3], v[3], a[3], j[3];  // j: order 8
@@ -260,13 +266,19 @@ struct Mixed {
     return j;
   }
 
-  // Position difference and unsoftened |r|^2: the one definition used by the force loop and by
-  // the nearest-neighbour re-scan, so both produce the same bits.
-  __device__ static __forceinline__ float diff_r2(const J &j, const Sink &s, float &dx, float &dy, float &dz) {
+  // Position difference and a squared distance: with Fold (the kernels without neighbour lists)
+  // the softened R^2 = |r|^2 + eps2 in one fma chain that starts from eps2, else the unsoftened
+  // |r|^2.  The nearest-neighbour key is taken on this value (an increasing function of |r|^2), and
+  // the one definition serves the force loop and the nearest-neighbour re-scan, so both produce
+  // the same bits.
+  template <bool Fold>
+  __device__ static __forceinline__ float diff_d2(const J &j, const Sink &s, float eps2, float &dx, float &dy,
+                                                  float &dz) {
     dx = (j.xh[0] - s.xh[0]) + (j.xl[0] - s.xl[0]);
     dy = (j.xh[1] - s.xh[1]) + (j.xl[1] - s.xl[1]);
     dz = (j.xh[2] - s.xh[2]) + (j.xl[2] - s.xl[2]);
-    return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+    if constexpr (Fold) return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
+    else return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
   }
 
   // Nearest-neighbour key: the bit pattern of |r|^2 >= 0, whose unsigned order is the order of
@@ -277,19 +289,21 @@ struct Mixed {
   __device__ static __forceinline__ GKey gkey_none() { return ~Key(0); }
   __device__ static __forceinline__ Key group_key(GKey g) { return g; }
 
-  __device__ static __forceinline__ Key nn_key(const J &j, const Sink &s) {
+  template <bool Nbr>
+  __device__ static __forceinline__ Key nn_key(const J &j, const Sink &s, float eps2) {
     float dx, dy, dz;
-    return key_of(diff_r2(j, s, dx, dy, dz));
+    return key_of(diff_d2<!Nbr>(j, s, eps2, dx, dy, dz));
   }
 
-  // One pair; returns the unsoftened |r|^2 (for the neighbour-list test).  NN: keep the
-  // nearest-neighbour group minimum (the kernels without it leave gmin untouched).
-  template <bool Guard, bool NN>
+  // One pair; returns the unsoftened |r|^2 for the neighbour-list test (Nbr), else R^2.  NN: keep
+  // the nearest-neighbour group minimum (the kernels without it leave gmin untouched), on |r|^2
+  // with lists and on R^2 without.
+  template <bool Guard, bool NN, bool Nbr>
   __device__ static __forceinline__ float interact(const J &j, const Sink &s, float eps2, int jidx, int self,
                                                   Comp<float, kValues<Order>> &A, GKey &gmin) {
     float dx, dy, dz;
-    const float r2 = diff_r2(j, s, dx, dy, dz);
-    const float R2 = r2 + eps2;
+    const float r2 = diff_d2<!Nbr>(j, s, eps2, dx, dy, dz);
+    const float R2 = Nbr ? r2 + eps2 : r2;
     float rinv = __builtin_amdgcn_rsqf(R2);  // v_rsq_f32
     if constexpr (Guard) rinv = jidx != self ? rinv : 0.0f;
     const float rinv2 = rinv * rinv;
@@ -414,6 +428,7 @@ struct F64 {
   using Real = double;
   using Key = uint64_t;
   static constexpr int kK = kValues<Order>;
+  static constexpr int kLongChunk = kChunk;  // long chunks: every FP64 sum folds (TwoSum) every 64 terms
   using Tile = F64Tile<Order>;
   struct Sink {
     double x[3], v[3], a[3], j[3];  // j: order 8
@@ -509,11 +524,15 @@ struct F64 {
     return j;
   }
 
-  __device__ static __forceinline__ double diff_r2(const J &j, const Sink &s, double &dx, double &dy, double &dz) {
+  // As Mixed::diff_d2.
+  template <bool Fold>
+  __device__ static __forceinline__ double diff_d2(const J &j, const Sink &s, double eps2, double &dx, double &dy,
+                                                   double &dz) {
     dx = j.x[0] - s.x[0];
     dy = j.x[1] - s.x[1];
     dz = j.x[2] - s.x[2];
-    return fma(dz, dz, fma(dy, dy, dx * dx));
+    if constexpr (Fold) return fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2)));
+    else return fma(dz, dz, fma(dy, dy, dx * dx));
   }
 
   __device__ static __forceinline__ Key key_of(double r2) { return (Key)__double_as_longlong(r2); }
@@ -532,18 +551,19 @@ struct F64 {
     else return g;
   }
 
-  __device__ static __forceinline__ Key nn_key(const J &j, const Sink &s) {
+  template <bool Nbr>
+  __device__ static __forceinline__ Key nn_key(const J &j, const Sink &s, double eps2) {
     double dx, dy, dz;
-    return key_of(diff_r2(j, s, dx, dy, dz));
+    return key_of(diff_d2<!Nbr>(j, s, eps2, dx, dy, dz));
   }
 
-  // One pair; returns the unsoftened |r|^2 (for the neighbour-list test).  NN as in Mixed.
-  template <bool Guard, bool NN>
+  // One pair; as Mixed::interact.
+  template <bool Guard, bool NN, bool Nbr>
   __device__ static __forceinline__ double interact(const J &j, const Sink &s, double eps2, int jidx, int self,
                                                   Comp<double, kValues<Order>> &A, GKey &gmin) {
     double dx, dy, dz;
-    const double r2 = diff_r2(j, s, dx, dy, dz);
-    const double R2 = r2 + eps2;
+    const double r2 = diff_d2<!Nbr>(j, s, eps2, dx, dy, dz);
+    const double R2 = Nbr ? r2 + eps2 : r2;
     double rinv = rsqrt64(R2);
     if constexpr (Guard) rinv = jidx != self ? rinv : 0.0;
     const double rinv2 = rinv * rinv;
@@ -766,7 +786,8 @@ __device__ void finalize_sink(const ForceParams &fp, int q, const double *v, int
 // One LDS tile against the lane's P sinks.  Guard = true is used only for tiles that hold the
 // own source of some sink of the wave: there R^-1 is forced to 0 for j == self, so the self pair
 // adds exact zeros everywhere and its nearest-neighbour key is the maximum.
-// The lane's sources are taken in groups of kChunkAcc; inside a group only the minimum
+// The lane's sources are taken in groups of one chunk (kChunkAcc, or Tr::kLongChunk with Long);
+// the acceleration sums fold after each group, the others every kChunk.  Inside a group only the minimum
 // nearest-neighbour key is kept, and after the group the (key, first source of the group) pair
 // replaces the running best if the key is smaller.  The exact source is found afterwards by
 // re-scanning that one group (nn_rescan).  L1: one lane per sink (compile-time offsets).
@@ -778,7 +799,7 @@ __device__ __forceinline__ void nbr_append(const ForceParams &fp, int q, int jj)
   if (k < fp.nbr_max) fp.nbr_ids[(size_t)q * fp.nbr_max + k] = fp.src.id[jj];
 }
 
-template <class Tr, int P, bool Guard, bool L1, bool Nbr, bool NN>
+template <class Tr, int P, bool Guard, bool L1, bool Nbr, bool NN, bool Long>
 __device__ __forceinline__ void tile_compute(const ForceParams &fp, const typename Tr::Tile &tl, int slot, int lg,
                                              int jb, const typename Tr::Sink (&sink)[P], const int (&self)[P],
                                              const int (&q)[P], const typename Tr::Real (&h2)[P],
@@ -787,8 +808,9 @@ __device__ __forceinline__ void tile_compute(const ForceParams &fp, const typena
                                              typename Tr::Key (&nnk)[P], int (&nng)[P]) {
   using Key = typename Tr::Key;
   const int per = L1 ? kTile : kTile >> lg;
-  for (int c = 0; c < per; c += kChunkAcc) {
-    const int ce = per < c + kChunkAcc ? per : c + kChunkAcc;
+  constexpr int kCA = Long ? Tr::kLongChunk : kChunkAcc;
+  for (int c = 0; c < per; c += kCA) {
+    const int ce = per < c + kCA ? per : c + kCA;
     typename Tr::GKey gmin[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) gmin[p] = Tr::gkey_none();
@@ -800,7 +822,7 @@ __device__ __forceinline__ void tile_compute(const ForceParams &fp, const typena
 #pragma unroll
       for (int p = 0; p < P; ++p) {
         const typename Tr::Real r2 =
-            Tr::template interact<Guard, NN>(j, sink[p], eps2, jidx, self[p], acc[p], gmin[p]);
+            Tr::template interact<Guard, NN, Nbr>(j, sink[p], eps2, jidx, self[p], acc[p], gmin[p]);
         if constexpr (Nbr) {
           if (r2 < h2[p] && jidx < fp.nj && (!Guard || jidx != self[p])) nbr_append(fp, q[p], jidx);
         }
@@ -846,28 +868,29 @@ __device__ __forceinline__ typename Tr::J staged_j(const ForceParams &fp, int jj
 }
 
 // Find the first source of the winning group whose key equals the best key (the group start g0
-// and lane stride L identify the group; its length is min(kChunkAcc, 256 / L)).
+// and lane stride L identify the group; its length is min(chunk, 256 / L)).
 // When the group lies in the tile still resident in LDS after the loop (the workgroup's last
 // tile: always the case when a workgroup has one tile, i.e. at small and medium N_i), its records
 // are read back from LDS; otherwise they are staged again from global memory.  Either way they are
 // the records the loop used, so the keys match bit for bit.
-template <class Tr, int Order>
+template <class Tr, int Order, bool Nbr, bool Long>
 __device__ __forceinline__ int nn_rescan(const ForceParams &fp, const typename Tr::Tile &last, int last_tile,
                                          const typename Tr::Sink &s, typename Tr::Key key, int g0, int lg,
-                                         int self) {
+                                         int self, typename Tr::Real eps2) {
   if (g0 < 0) return -1;
   const int per = kTile >> lg;
-  const int len = per < kChunkAcc ? per : kChunkAcc;
+  constexpr int kCA = Long ? Tr::kLongChunk : kChunkAcc;
+  const int len = per < kCA ? per : kCA;
   if ((g0 >> 8) == last_tile) {  // kTile == 256
     for (int k = 0; k < len; ++k) {
       const int jj = g0 + (k << lg);
-      if (jj != self && Tr::nn_key(Tr::load(last, jj & (kTile - 1)), s) == key) return jj;
+      if (jj != self && Tr::template nn_key<Nbr>(Tr::load(last, jj & (kTile - 1)), s, eps2) == key) return jj;
     }
     return -1;
   }
   for (int k = 0; k < len; ++k) {
     const int jj = g0 + (k << lg);
-    if (jj != self && Tr::nn_key(staged_j<Tr, Order>(fp, jj), s) == key) return jj;
+    if (jj != self && Tr::template nn_key<Nbr>(staged_j<Tr, Order>(fp, jj), s, eps2) == key) return jj;
   }
   return -1;  // not reached: the group's minimum key comes from one of its sources
 }
@@ -889,7 +912,7 @@ template <int Order, int Prec, int P, bool L1>
 constexpr int kForceWaves =
     (Prec != NBX_FP64 || P != 1 || (Order == 8 && !L1)) ? 1 : (Order >= 6 ? 2 : (Order == 4 ? 3 : 1));
 
-template <int Order, int Prec, int P, bool L1, bool Nbr, bool NN>
+template <int Order, int Prec, int P, bool L1, bool Nbr, bool NN, bool Long>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kForceWaves<Order, Prec, P, L1>)))
 void k_force(const ForceParams fp) {
   using Tr = typename TraitsSel<Order, Prec>::type;
@@ -978,11 +1001,11 @@ void k_force(const ForceParams fp) {
 #pragma unroll
     for (int p = 0; p < P; ++p) mine |= (self[p] >> 8) == tile;  // kTile == 256
     if (__any(mine))
-      tile_compute<Tr, P, true, L1, Nbr, NN>(fp, tiles[buf], slot, lg, tile * kTile + slot, sink, self, q, h2, eps2,
-                                             acc, nnk, nng);
+      tile_compute<Tr, P, true, L1, Nbr, NN, Long>(fp, tiles[buf], slot, lg, tile * kTile + slot, sink, self, q, h2,
+                                                   eps2, acc, nnk, nng);
     else
-      tile_compute<Tr, P, false, L1, Nbr, NN>(fp, tiles[buf], slot, lg, tile * kTile + slot, sink, self, q, h2, eps2,
-                                              acc, nnk, nng);
+      tile_compute<Tr, P, false, L1, Nbr, NN, Long>(fp, tiles[buf], slot, lg, tile * kTile + slot, sink, self, q, h2,
+                                                    eps2, acc, nnk, nng);
     if (tile + 1 < t1) stage(tile + 1, buf ^ 1);
     __syncthreads();
   }
@@ -997,7 +1020,8 @@ void k_force(const ForceParams fp) {
 #pragma unroll
     for (int k = 0; k < K; ++k) v[p][k] = acc[p].value(k);
     kk[p] = (uint64_t)nnk[p];
-    ii[p] = NN ? nn_rescan<Tr, Order>(fp, tiles[(t1 - 1 - t0) & 1], t1 - 1, sink[p], nnk[p], nng[p], lg, self[p])
+    ii[p] = NN ? nn_rescan<Tr, Order, Nbr, Long>(fp, tiles[(t1 - 1 - t0) & 1], t1 - 1, sink[p], nnk[p], nng[p], lg,
+                                                 self[p], eps2)
                : -1;
   }
   group_reduce<P, K, NN>(L, v, kk, ii, red);
@@ -1182,7 +1206,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchParams bp) {
       typename Tr::GKey dummy = Tr::gkey_none();
       for (int j0 = slot; j0 < n; j0 += kChunkAcc << lg) {
         const int je = n < j0 + (kChunkAcc << lg) ? n : j0 + (kChunkAcc << lg);
-        for (int j = j0; j < je; j += L) Tr::template interact<true, false>(lds[j], si, eps2, j, i, acc, dummy);
+        for (int j = j0; j < je; j += L) Tr::template interact<true, false, false>(lds[j], si, eps2, j, i, acc, dummy);
         acc.template fold<0, K>();
       }
       double w[1][K];
@@ -1605,15 +1629,15 @@ LaunchShape choose_shape(int ni, int nj_pad, int prec, int order) {
   return ls;
 }
 
-template <int Order, int Prec, int P, bool L1, bool NN>
+template <int Order, int Prec, int P, bool L1, bool NN, bool Long>
 static hipError_t launch_force_t(const ForceParams &fp, const LaunchShape &ls, hipStream_t stream) {
   const dim3 grid(ls.blocks * ls.splits), block(kThreads);
   if (fp.h2) {
     hipError_t e = launch_fill_i32(fp.nbr_count, fp.ni, 0, stream);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_force<Order, Prec, P, L1, true, NN>), grid, block, 0, stream, fp);
+    hipLaunchKernelGGL((k_force<Order, Prec, P, L1, true, NN, Long>), grid, block, 0, stream, fp);
   } else {
-    hipLaunchKernelGGL((k_force<Order, Prec, P, L1, false, NN>), grid, block, 0, stream, fp);
+    hipLaunchKernelGGL((k_force<Order, Prec, P, L1, false, NN, Long>), grid, block, 0, stream, fp);
   }
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && fp.h2) {
@@ -1634,11 +1658,18 @@ static hipError_t launch_force_t(const ForceParams &fp, const LaunchShape &ls, h
   return hipGetLastError();
 }
 
+// Long chunks where a workgroup runs at least kLongTiles source tiles with one lane per sink (two
+// sinks per lane only occur there); several lanes per sink always take the short chunks.
+constexpr int kLongTiles = 8;
+
 template <int Order, int Prec, bool NN>
 static hipError_t launch_force_nn(const ForceParams &fp, const LaunchShape &ls, hipStream_t stream) {
-  if (ls.sinks_per_lane == 2) return launch_force_t<Order, Prec, 2, true, NN>(fp, ls, stream);
-  if (ls.lanes_log2 == 0) return launch_force_t<Order, Prec, 1, true, NN>(fp, ls, stream);
-  return launch_force_t<Order, Prec, 1, false, NN>(fp, ls, stream);
+  const bool long_chunks = fp.nj_pad / kTile >= kLongTiles * ls.splits;
+  if (ls.sinks_per_lane == 2) return launch_force_t<Order, Prec, 2, true, NN, true>(fp, ls, stream);
+  if (ls.lanes_log2 == 0)
+    return long_chunks ? launch_force_t<Order, Prec, 1, true, NN, true>(fp, ls, stream)
+                       : launch_force_t<Order, Prec, 1, true, NN, false>(fp, ls, stream);
+  return launch_force_t<Order, Prec, 1, false, NN, false>(fp, ls, stream);
 }
 
 template <int Order, int Prec>

@@ -44,11 +44,12 @@ def oracle8(src, eps2, t, addr, h2=None, nbr_max=0):
     ref = oracle.force8(eps2, src.ids, src.m, xp, vp, ap, jp, src.ids[sel], xp[sel], vp[sel], ap[sel], jp[sel],
                         h2=h2, nbr_max=nbr_max)
     ref["xp"] = xp
+    ref["eps2"] = eps2
     return ref
 
 
 def _sub(ref, pick):
-    return {k: (v if k == "xp" or v is None else v[pick]) for k, v in ref.items()}
+    return {k: (v if k in ("xp", "eps2") or v is None else v[pick]) for k, v in ref.items()}
 
 
 KAPPA_MAX = 10.0  # mixed: plain relative acc bound on sinks with kappa = sum_j |a_ij| / |a| up to this
