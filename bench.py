@@ -104,6 +104,9 @@ def parse():
     ap.add_argument("--blockstep", type=str, default="", metavar="N,N,...",
                     help="also run the 6th-order block time-step Hermite integrator for one N-body time unit "
                          "(eta4=0.01, eta6=0.1, eps2=1e-6) on Plummer spheres of these sizes, FP64 and mixed")
+    ap.add_argument("--blockstep-precisions", type=str, default="fp64,mixed", metavar="P,P,...",
+                    help="precisions of the --blockstep / --blockstep4 runs: fp64, mixed and ds (double-single, "
+                         "the paper's DS; about ten times the FP64 pair cost on this GPU)")
     ap.add_argument("--blockstep4", type=str, default="", metavar="N,N,...",
                     help="also run the 4th-order block time-step Hermite integrator (Aarseth criterion, eta4=0.01, "
                          "eps2=1e-6) for one N-body time unit on Plummer spheres of these sizes, FP64 and mixed")
@@ -567,16 +570,17 @@ def order2(torch, nbx, ics, dev, steps):
             "flops_per_interaction": FLOPS_2ND, "rows": rows}
 
 
-def blockstep(torch, nbx, ics, sizes, tune=True, order=6):
+def blockstep(torch, nbx, ics, sizes, tune=True, order=6, precisions=("fp64", "mixed")):
     """Block time-step runs (6th order by default; 4th order with the Aarseth criterion), one N-body
-    time unit, FP64 (DP) and mixed (DS): wall time from the start to the end of the integration,
+    time unit, in the given precisions (fp64: the paper's DP; ds: its double-single DS; mixed: this
+    library's FP32 pair arithmetic): wall time from the start to the end of the integration,
     energy error, block steps and mean N_active."""
-    import numpy as np
-
+    codes = {"fp64": nbx.NBX_FP64, "mixed": nbx.NBX_MIXED, "ds": nbx.NBX_DS}
     rows = []
     for n in sizes:
         m, x, v = ics.plummer(n, seed=7)
-        for prec, name in ((nbx.NBX_FP64, "fp64"), (nbx.NBX_MIXED, "mixed")):
+        for name in precisions:
+            prec = codes[name]
             ctx = nbx.Context(order=order, precision=prec, nj_max=n, ni_max=n)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -875,10 +879,11 @@ def main():
             print("bench: end-to-end %s %s" % (name, json.dumps(e2e["rows"][name])), file=sys.stderr, flush=True)
 
     o2 = order2(torch, nbx, nbody_ics, dev, max(3, args.steps // 2)) if args.order2 else None
-    bsr = (blockstep(torch, nbx, nbody_ics, [int(k) for k in args.blockstep.split(",")], tune=not args.no_tune)
-           if args.blockstep else None)
+    bs_prec = tuple(args.blockstep_precisions.split(","))
+    bsr = (blockstep(torch, nbx, nbody_ics, [int(k) for k in args.blockstep.split(",")], tune=not args.no_tune,
+                     precisions=bs_prec) if args.blockstep else None)
     bs4 = (blockstep(torch, nbx, nbody_ics, [int(k) for k in args.blockstep4.split(",")], tune=not args.no_tune,
-                     order=4) if args.blockstep4 else None)
+                     order=4, precisions=bs_prec) if args.blockstep4 else None)
     extras = not args.no_extras
     o6 = (order6(torch, nbx, nbody_ics, dev, max(2, args.steps // 10),
                  ni_list=(1024, 65536, 1 << 20) if args.order6 else (1024, 65536))

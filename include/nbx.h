@@ -57,6 +57,13 @@
  *              (hi = fl32(x), lo = fl32(x - hi)) and differenced as
  *              (hi_j - hi_i) + (lo_j - lo_i); everything else in FP32, with
  *              FP32 chunk sums folded into FP64 totals.  Results are FP64 arrays.
+ *   NBX_DS     the paper's double-single precision (about 14 significant digits):
+ *              predictor in FP64, then every pair quantity in double-single
+ *              arithmetic (TwoSum / FMA products, R^-1 from the hardware estimate
+ *              and one Newton step in double-single), pair terms summed in FP64.
+ *              Orders 4 and 6 only (nbx_open / nbx_set_precision return
+ *              NBX_ERR_ARG otherwise); the batched and adjoint entry points take
+ *              NBX_FP64 or NBX_MIXED.
  *
  * Conventions shared by every entry point:
  *   - Return value: NBX_OK (0), a negative NBX_ERR_* code, or a positive
@@ -95,6 +102,7 @@ extern "C" {
 
 #define NBX_FP64 0
 #define NBX_MIXED 1
+#define NBX_DS 2 /* double-single arithmetic, orders 4 and 6 (the gravity kernels only) */
 
 typedef struct nbx_ctx nbx_ctx; /* opaque; owns every device buffer it allocates */
 
@@ -102,7 +110,7 @@ typedef struct nbx_config {
   int device;    /* HIP device ordinal */
   int order;     /* 2: acc, pot (GRAPE-5 mode);  4: acc, jerk, pot;  6: also snap (needs snap and
                     crackle of the sources);  8: also crackle (same source data as order 6) */
-  int precision; /* NBX_FP64 or NBX_MIXED; can be changed later with nbx_set_precision */
+  int precision; /* NBX_FP64, NBX_MIXED or (orders 4, 6) NBX_DS; can be changed with nbx_set_precision */
   int nj_max;    /* source capacity (addresses 0 .. nj_max-1) */
   int ni_max;    /* largest number of sinks in one nbx_force call */
   int nbr_max;   /* neighbour-list capacity per sink; 0 disables neighbour lists */
@@ -131,7 +139,7 @@ int nbx_close(nbx_ctx *ctx);
  * next call on the same context.  With ctx NULL: the message of the last failed nbx_open. */
 const char *nbx_last_error(const nbx_ctx *ctx);
 
-/* Switch the arithmetic of later nbx_force calls (NBX_FP64 or NBX_MIXED). */
+/* Switch the arithmetic of later nbx_force calls (NBX_FP64, NBX_MIXED, or NBX_DS at orders 4 and 6). */
 int nbx_set_precision(nbx_ctx *ctx, int precision);
 
 /* Set the number of sources in use: addresses 0 .. nj-1 take part in every force evaluation.

@@ -646,6 +646,245 @@ struct F64 {
   }
 };
 
+
+// ---------------------------------------------------------------------------------------------
+// Double-single arithmetic (the paper's DS precision: a value is an unevaluated sum hi + lo of
+// two FP32 numbers, |lo| <= ulp(hi)/2, about 48 significant bits; Background, footnote on the
+// Yebisu library).  Error-free transformations: Knuth's TwoSum, Dekker's FastTwoSum (|a| >= |b|),
+// and the FMA product error; every operation renormalises.  Contraction is off inside each of
+// them so that the compiler keeps every rounding where it is written.
+// ---------------------------------------------------------------------------------------------
+struct dsf {
+  float hi, lo;
+};
+
+__device__ __forceinline__ dsf ds_of(double x) {
+  const float h = (float)x;
+  return {h, (float)(x - (double)h)};
+}
+__device__ __forceinline__ double ds_to_double(dsf a) { return (double)a.hi + (double)a.lo; }  // exact
+
+__device__ __forceinline__ dsf ds_fast_two_sum(float a, float b) {
+#pragma clang fp contract(off)
+  const float s = a + b;
+  return {s, b - (s - a)};
+}
+__device__ __forceinline__ dsf ds_two_sum(float a, float b) {
+#pragma clang fp contract(off)
+  const float s = a + b;
+  const float bb = s - a;
+  return {s, (a - (s - bb)) + (b - bb)};
+}
+__device__ __forceinline__ dsf ds_add(dsf a, dsf b) {
+#pragma clang fp contract(off)
+  const dsf s = ds_two_sum(a.hi, b.hi);
+  return ds_fast_two_sum(s.hi, s.lo + (a.lo + b.lo));
+}
+__device__ __forceinline__ dsf ds_neg(dsf a) { return {-a.hi, -a.lo}; }
+__device__ __forceinline__ dsf ds_sub(dsf a, dsf b) { return ds_add(a, ds_neg(b)); }
+__device__ __forceinline__ dsf ds_mul(dsf a, dsf b) {
+#pragma clang fp contract(off)
+  const float p = a.hi * b.hi;
+  float e = __builtin_fmaf(a.hi, b.hi, -p);
+  e = __builtin_fmaf(a.hi, b.lo, __builtin_fmaf(a.lo, b.hi, e));
+  return ds_fast_two_sum(p, e);
+}
+__device__ __forceinline__ dsf ds_mulf(dsf a, float f) {  // by an FP32 number (exact small constants)
+#pragma clang fp contract(off)
+  const float p = a.hi * f;
+  const float e = __builtin_fmaf(a.lo, f, __builtin_fmaf(a.hi, f, -p));
+  return ds_fast_two_sum(p, e);
+}
+__device__ __forceinline__ dsf ds_sqr(dsf a) {
+#pragma clang fp contract(off)
+  const float p = a.hi * a.hi;
+  const float e = __builtin_fmaf(a.hi + a.hi, a.lo, __builtin_fmaf(a.hi, a.hi, -p));
+  return ds_fast_two_sum(p, e);
+}
+__device__ __forceinline__ dsf ds_dot3(const dsf a[3], const dsf b[3]) {
+  return ds_add(ds_add(ds_mul(a[0], b[0]), ds_mul(a[1], b[1])), ds_mul(a[2], b[2]));
+}
+// 1/sqrt(x): the hardware estimate y (about 1 ulp of FP32) and one Newton step evaluated in DS,
+// y1 = y + y (1 - x y^2) / 2, whose error is about (3/2) (2^-23)^2, below the DS rounding.
+__device__ __forceinline__ dsf ds_rsqrt(dsf x) {
+#pragma clang fp contract(off)
+  const float y = __builtin_amdgcn_rsqf(x.hi);
+  const dsf yy = ds_fast_two_sum(y * y, __builtin_fmaf(y, y, -(y * y)));
+  const dsf d = ds_sub(dsf{1.0f, 0.0f}, ds_mul(x, yy));  // small: |d| ~ 2^-22
+  const float c = 0.5f * y * d.hi;
+  return ds_add(dsf{y, 0.0f}, ds_fast_two_sum(c, __builtin_fmaf(0.5f * y, d.hi, -c)));
+}
+
+template <int Order>
+struct DSTile;
+template <>
+struct DSTile<4> {   // 56 B per source
+  float4 t0[kTile];  // x.hi m.hi
+  float4 t1[kTile];  // x.lo m.lo
+  float4 t2[kTile];  // v.hi vx.lo
+  float2 t3[kTile];  // vy.lo vz.lo
+};
+template <>
+struct DSTile<6> {   // 80 B per source
+  float4 t0[kTile];  // x.hi m.hi
+  float4 t1[kTile];  // x.lo m.lo
+  float4 t2[kTile];  // v.hi vx.lo
+  float2 t3[kTile];  // vy.lo vz.lo
+  float4 t4[kTile];  // a.hi ax.lo
+  float2 t5[kTile];  // ay.lo az.lo
+};
+
+// DS precision (orders 4 and 6): every pair quantity in double-single arithmetic from the FP64
+// predicted state; the pair terms convert exactly to FP64 and sum in FP64 chunks folded with
+// TwoSum (as the FP64 kernels do).  R^-1 from the hardware estimate refined once in DS.
+template <int Order>
+struct DS {
+  static_assert(Order == 4 || Order == 6, "double-single arithmetic is built for orders 4 and 6");
+  using Real = double;  // sums, eps2 and list radii
+  using Key = uint32_t;
+  static constexpr int kK = kValues<Order>;
+  static constexpr int kLongChunk = kChunk;
+  using Tile = DSTile<Order>;
+  struct Sink {
+    dsf x[3], v[3], a[3];
+    int64_t id;
+  };
+  struct J {
+    dsf x[3], m, v[3], a[3];
+  };
+
+  __device__ static __forceinline__ Sink sink_from_j(const J &j) {
+    Sink s;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      s.x[k] = j.x[k];
+      s.v[k] = j.v[k];
+      s.a[k] = j.a[k];
+    }
+    s.id = -1;
+    return s;
+  }
+  __device__ static __forceinline__ Sink make_sink(const double xp[3], const double vp[3], const double ap[6],
+                                                   double) {
+    Sink s;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      s.x[k] = ds_of(xp[k]);
+      s.v[k] = ds_of(vp[k]);
+      s.a[k] = ds_of(ap[k]);
+    }
+    s.id = -1;
+    return s;
+  }
+  __device__ static __forceinline__ J make_j(const double xp[3], const double vp[3], const double ap[6], double m) {
+    J j;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      j.x[k] = ds_of(xp[k]);
+      j.v[k] = ds_of(vp[k]);
+      j.a[k] = ds_of(ap[k]);
+    }
+    j.m = ds_of(m);
+    return j;
+  }
+  __device__ static __forceinline__ void store(Tile &tl, int e, const double xp[3], const double vp[3],
+                                               const double ap[6], double m) {
+    const J j = make_j(xp, vp, ap, m);
+    tl.t0[e] = make_float4(j.x[0].hi, j.x[1].hi, j.x[2].hi, j.m.hi);
+    tl.t1[e] = make_float4(j.x[0].lo, j.x[1].lo, j.x[2].lo, j.m.lo);
+    tl.t2[e] = make_float4(j.v[0].hi, j.v[1].hi, j.v[2].hi, j.v[0].lo);
+    tl.t3[e] = make_float2(j.v[1].lo, j.v[2].lo);
+    if constexpr (Order == 6) {
+      tl.t4[e] = make_float4(j.a[0].hi, j.a[1].hi, j.a[2].hi, j.a[0].lo);
+      tl.t5[e] = make_float2(j.a[1].lo, j.a[2].lo);
+    }
+  }
+  __device__ static __forceinline__ J load(const Tile &tl, int e) {
+    J j;
+    const float4 a = tl.t0[e], b = tl.t1[e], c = tl.t2[e];
+    const float2 d = tl.t3[e];
+    j.x[0] = {a.x, b.x};
+    j.x[1] = {a.y, b.y};
+    j.x[2] = {a.z, b.z};
+    j.m = {a.w, b.w};
+    j.v[0] = {c.x, c.w};
+    j.v[1] = {c.y, d.x};
+    j.v[2] = {c.z, d.y};
+    if constexpr (Order == 6) {
+      const float4 f = tl.t4[e];
+      const float2 g = tl.t5[e];
+      j.a[0] = {f.x, f.w};
+      j.a[1] = {f.y, g.x};
+      j.a[2] = {f.z, g.y};
+    } else {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) j.a[k] = {0.0f, 0.0f};
+    }
+    return j;
+  }
+
+  // Unsoftened |r|^2 in DS (the nearest-neighbour key is taken on its leading part).
+  __device__ static __forceinline__ dsf diff_r2(const J &j, const Sink &s, dsf (&d)[3]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) d[k] = ds_sub(j.x[k], s.x[k]);
+    return ds_add(ds_add(ds_sqr(d[0]), ds_sqr(d[1])), ds_sqr(d[2]));
+  }
+  __device__ static __forceinline__ Key key_of(float r2) { return __float_as_uint(r2); }
+  using GKey = Key;
+  __device__ static __forceinline__ GKey gkey_none() { return ~Key(0); }
+  __device__ static __forceinline__ Key group_key(GKey g) { return g; }
+  template <bool Nbr>
+  __device__ static __forceinline__ Key nn_key(const J &j, const Sink &s, double) {
+    dsf d[3];
+    return key_of(diff_r2(j, s, d).hi);
+  }
+
+  // One pair; returns the unsoftened |r|^2 (its FP64 value) for the neighbour-list test.
+  template <bool Guard, bool NN, bool Nbr>
+  __device__ static __forceinline__ double interact(const J &j, const Sink &s, double eps2, int jidx, int self,
+                                                  Comp<double, kValues<Order>> &A, GKey &gmin) {
+    dsf d[3], w[3];
+    const dsf r2 = diff_r2(j, s, d);
+    dsf rinv = ds_rsqrt(ds_add(r2, ds_of(eps2)));
+    if constexpr (Guard) {
+      if (jidx == self) rinv = {0.0f, 0.0f};
+    }
+    const dsf rinv2 = ds_sqr(rinv);
+    const dsf mr = ds_mul(j.m, rinv);
+    const dsf mr3 = ds_mul(mr, rinv2);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) w[k] = ds_sub(j.v[k], s.v[k]);
+    const dsf al = ds_mul(ds_dot3(d, w), rinv2);
+    dsf a0[3], a1[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      a0[k] = ds_mul(mr3, d[k]);
+      a1[k] = ds_add(ds_mul(mr3, w[k]), ds_mul(ds_mulf(al, -3.0f), a0[k]));
+      A.part[k] += ds_to_double(a0[k]);
+      A.part[3 + k] += ds_to_double(a1[k]);
+    }
+    A.part[6] -= ds_to_double(mr);
+    if constexpr (Order == 6) {
+      dsf u[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) u[k] = ds_sub(j.a[k], s.a[k]);
+      const dsf be = ds_add(ds_mul(ds_add(ds_dot3(w, w), ds_dot3(d, u)), rinv2), ds_sqr(al));
+      const dsf am6 = ds_mulf(al, -6.0f), bm3 = ds_mulf(be, -3.0f);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const dsf a2 = ds_add(ds_add(ds_mul(mr3, u[k]), ds_mul(am6, a1[k])), ds_mul(bm3, a0[k]));
+        A.part[7 + k] += ds_to_double(a2);
+      }
+    }
+    if constexpr (NN) {
+      Key key = key_of(r2.hi);
+      if constexpr (Guard) key = jidx != self ? key : ~Key(0);
+      gmin = key < gmin ? key : gmin;
+    }
+    return ds_to_double(r2);
+  }
+};
+
 template <int Order, int Prec>
 struct TraitsSel;
 template <int Order>
@@ -655,6 +894,10 @@ struct TraitsSel<Order, NBX_MIXED> {
 template <int Order>
 struct TraitsSel<Order, NBX_FP64> {
   using type = F64<Order>;
+};
+template <int Order>
+struct TraitsSel<Order, NBX_DS> {
+  using type = DS<Order>;
 };
 
 // ---------------------------------------------------------------------------------------------
@@ -1684,9 +1927,11 @@ hipError_t launch_force(int order, int precision, const ForceParams &fp, const L
                                   : launch_force_op<2, NBX_FP64>(fp, ls, stream);
   if (order == 4)
     return precision == NBX_MIXED ? launch_force_op<4, NBX_MIXED>(fp, ls, stream)
+           : precision == NBX_DS  ? launch_force_op<4, NBX_DS>(fp, ls, stream)
                                   : launch_force_op<4, NBX_FP64>(fp, ls, stream);
   if (order == 6)
     return precision == NBX_MIXED ? launch_force_op<6, NBX_MIXED>(fp, ls, stream)
+           : precision == NBX_DS  ? launch_force_op<6, NBX_DS>(fp, ls, stream)
                                   : launch_force_op<6, NBX_FP64>(fp, ls, stream);
   return precision == NBX_MIXED ? launch_force_op<8, NBX_MIXED>(fp, ls, stream)
                                 : launch_force_op<8, NBX_FP64>(fp, ls, stream);

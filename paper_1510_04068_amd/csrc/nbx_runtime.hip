@@ -116,8 +116,8 @@ struct nbx_ctx {
   // everything while tuning
   struct TunedShape {
     int lanes_log2 = -1, sinks_per_lane = 1, splits = 1;
-  } tuned[2][32];
-  int tune_ntiles[2] = {0, 0};
+  } tuned[3][32];
+  int tune_ntiles[3] = {0, 0, 0};
   const LaunchShape *force_shape = nullptr;
   // state of the last force call (host path)
   int last_ni = -1;
@@ -284,7 +284,10 @@ void out_layout(nbx_ctx *c, int ni) {
   c->out_doubles = (size_t)(p - c->d_out);
 }
 
-bool valid_prec(int p) { return p == NBX_FP64 || p == NBX_MIXED; }
+// NBX_DS exists for the gravity kernels of orders 4 and 6.
+bool valid_prec(int p, int order) {
+  return p == NBX_FP64 || p == NBX_MIXED || (p == NBX_DS && (order == 4 || order == 6));
+}
 
 int check_ctx(nbx_ctx *c) {
   if (!c) return NBX_ERR_ARG;
@@ -569,7 +572,8 @@ int nbx_open(nbx_ctx **out, const nbx_config *cfg) {
   if (!cfg) return fail(nullptr, NBX_ERR_ARG, "cfg is NULL");
   if (cfg->order != 2 && cfg->order != 4 && cfg->order != 6 && cfg->order != 8)
     return fail(nullptr, NBX_ERR_ARG, "order must be 2, 4, 6 or 8");
-  if (!valid_prec(cfg->precision)) return fail(nullptr, NBX_ERR_ARG, "precision must be NBX_FP64 or NBX_MIXED");
+  if (!valid_prec(cfg->precision, cfg->order))
+    return fail(nullptr, NBX_ERR_ARG, "precision must be NBX_FP64, NBX_MIXED or (orders 4 and 6) NBX_DS");
   if (cfg->nj_max < 1 || cfg->ni_max < 1 || cfg->nbr_max < 0)
     return fail(nullptr, NBX_ERR_ARG, "nj_max and ni_max must be >= 1, nbr_max >= 0");
   int ndev = 0;
@@ -636,7 +640,8 @@ const char *nbx_last_error(const nbx_ctx *c) { return c ? c->err.c_str() : g_ope
 int nbx_set_precision(nbx_ctx *c, int precision) {
   if (!c) return NBX_ERR_ARG;
   c->err.clear();
-  if (!valid_prec(precision)) return fail(c, NBX_ERR_ARG, "precision must be NBX_FP64 or NBX_MIXED");
+  if (!valid_prec(precision, c->cfg.order))
+    return fail(c, NBX_ERR_ARG, "precision must be NBX_FP64, NBX_MIXED or (orders 4 and 6) NBX_DS");
   c->precision = precision;
   return NBX_OK;
 }
@@ -1033,6 +1038,7 @@ int nbx_force_vjp_dev(nbx_ctx *c, void *stream, int n, const double *d_m, const 
                       double eps2, const double *d_g_acc, const double *d_g_jerk, const double *d_g_pot,
                       double *d_grad_x, double *d_grad_v, double *d_grad_m) {
   if (int rc = check_ctx(c)) return rc;
+  if (c->precision == NBX_DS) return fail(c, NBX_ERR_ARG, "the adjoint runs in NBX_FP64 or NBX_MIXED");
   if (n < 0) return fail(c, NBX_ERR_ARG, "n < 0");
   if (n == 0) return NBX_OK;
   if (!d_m || !d_x || !d_v || !d_g_acc || !d_g_jerk || !d_g_pot || !d_grad_x || !d_grad_v || !d_grad_m)
@@ -1091,6 +1097,7 @@ int nbx_batch_setup(nbx_ctx *c, int n_sys, const int32_t *offsets) {
 int nbx_batch_force_dev(nbx_ctx *c, void *stream, const double *d_m, const double *d_x, const double *d_v,
                         double eps2, double *d_acc, double *d_jerk, double *d_pot) {
   if (int rc = check_ctx(c)) return rc;
+  if (c->precision == NBX_DS) return fail(c, NBX_ERR_ARG, "batched systems run in NBX_FP64 or NBX_MIXED");
   if (c->batch_sizes.empty()) return fail(c, NBX_ERR_STATE, "nbx_batch_force_dev before nbx_batch_setup");
   if (!d_m || !d_x || !d_v || !d_acc || !d_jerk || !d_pot) return fail(c, NBX_ERR_ARG, "NULL device array");
   if (!(eps2 >= 0.0)) return fail(c, NBX_ERR_ARG, "eps2 must be >= 0");
@@ -1100,6 +1107,7 @@ int nbx_batch_force_dev(nbx_ctx *c, void *stream, const double *d_m, const doubl
 int nbx_batch_tune(nbx_ctx *c, void *stream, const double *d_m, const double *d_x, const double *d_v, double eps2,
                    double *d_acc, double *d_jerk, double *d_pot, int32_t *lanes_per_class) {
   if (int rc = check_ctx(c)) return rc;
+  if (c->precision == NBX_DS) return fail(c, NBX_ERR_ARG, "batched systems run in NBX_FP64 or NBX_MIXED");
   if (c->batch_sizes.empty()) return fail(c, NBX_ERR_STATE, "nbx_batch_tune before nbx_batch_setup");
   if (!d_m || !d_x || !d_v || !d_acc || !d_jerk || !d_pot) return fail(c, NBX_ERR_ARG, "NULL device array");
   hipStream_t s = static_cast<hipStream_t>(stream);

@@ -29,6 +29,7 @@ NBX_ERR_NO_DEVICE = -5
 NBX_ERR_OOM = -6
 NBX_FP64 = 0
 NBX_MIXED = 1
+NBX_DS = 2
 
 _ERR_NAMES = {
     NBX_ERR_ARG: "NBX_ERR_ARG",
