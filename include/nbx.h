@@ -355,7 +355,11 @@ int nbx_bs_step(nbx_ctx *ctx, double t_end, int *n_active);
 
 /* Block steps until the next block time would pass t_end; stats (may be NULL) as after the run.
  * Stops early with NBX_WARN_DT_MIN as soon as a step has been clamped at dt_min (stats.t then
- * shows how far it got). */
+ * shows how far it got).  With two or more 256-source tiles the steps are device-driven: the
+ * schedule, gravity and combine kernels of each step read N_active and the block time from device
+ * memory and the host synchronises once per 32 steps (launch shapes per N_active class as
+ * nbx_force would choose them, one sink per lane, at least two source splits); with one tile, or
+ * with NBX_BS_HOST_LOOP set in the environment, it runs nbx_bs_step in a loop. */
 int nbx_bs_run(nbx_ctx *ctx, double t_end, nbx_bs_stats *stats);
 
 /* State at the current block time: x, v [n][3] (predicted for particles between their steps), dt

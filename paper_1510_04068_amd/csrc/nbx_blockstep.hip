@@ -83,10 +83,19 @@ __device__ int block_exclusive_scan(int v, int *red, int *total) {
 // block step depends only on the set of active particles, not on their order, because each sink's
 // sum order is fixed by the launch shape.  Workgroup 0 publishes t_next and zeroes the other
 // counter for the next schedule.
+// DD (device-driven runs): the last block time is sched->tnow[parity] and the schedule itself
+// decides whether the step is taken (not when the run is stopped, a step has clamped, or t_next
+// passes t_end; then the count stays zero and every kernel of the step returns at once).
+// Workgroup 0 also counts the step before this schedule and publishes the new block time.  Every
+// workgroup reaches the same decision from inputs no kernel of this step writes, except stop,
+// which workgroup 0 sets only when the decision is to stop.
+template <bool DD>
 __global__ __launch_bounds__(kThreads) void k_bs_list(BlockStepParams bp, double t_now, int parity) {
   __shared__ int redi[kThreads / 64];
   __shared__ int base;
   __shared__ double tn_sh;
+  __shared__ int go_sh;
+  if (DD) t_now = bp.sched->tnow[parity];
   if (threadIdx.x < 64) {
     const bool occ = bp.level_count[threadIdx.x] > 0;
     const uint64_t m = __ballot(occ);
@@ -97,11 +106,28 @@ __global__ __launch_bounds__(kThreads) void k_bs_list(BlockStepParams bp, double
         const double dt = ldexp(1.0, -kmax);
         tn = (floor(t_now / dt) + 1.0) * dt;
       }
+      bool go = m != 0;
+      if (DD) go = go && bp.sched->stop == 0 && bp.sched->clamped == 0 && tn <= bp.sched->t_end;
       tn_sh = tn;
+      go_sh = go ? 1 : 0;
     }
   }
   __syncthreads();
   const double tn = tn_sh;
+  if (DD) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      const int prev = bp.sched->count[parity ^ 1];  // the step before this schedule, now complete
+      if (prev > 0) {
+        bp.sched->blocks += 1;
+        bp.sched->steps += prev;
+      }
+      bp.sched->count[parity ^ 1] = 0;
+      bp.sched->tnow[parity ^ 1] = go_sh ? tn : t_now;
+      if (go_sh) bp.sched->t_next = tn;
+      else bp.sched->stop = 1;
+    }
+    if (!go_sh) return;
+  }
   // thread t owns the kBsPer consecutive particles b0 + t*kBsPer ... (address order = thread order)
   const int i0 = blockIdx.x * kBsChunk + threadIdx.x * kBsPer;
   bool act[kBsPer];
@@ -116,7 +142,7 @@ __global__ __launch_bounds__(kThreads) void k_bs_list(BlockStepParams bp, double
   const int pos0 = block_exclusive_scan(mine, redi, &total);
   if (threadIdx.x == 0) {
     base = total > 0 ? atomicAdd(&bp.sched->count[parity], total) : 0;
-    if (blockIdx.x == 0) {
+    if (!DD && blockIdx.x == 0) {
       bp.sched->t_next = tn;
       bp.sched->count[parity ^ 1] = 0;
     }
@@ -168,6 +194,10 @@ __global__ __launch_bounds__(kThreads) void k_bs_load(BlockStepParams bp, const 
     bp.sched->t_next = 0.0;
     bp.sched->count[0] = bp.sched->count[1] = 0;
     bp.sched->clamped = 0;
+    bp.sched->stop = 0;
+    bp.sched->tnow[0] = bp.sched->tnow[1] = 0.0;
+    bp.sched->t_end = 0.0;
+    bp.sched->blocks = bp.sched->steps = 0;
   }
 }
 
@@ -235,7 +265,13 @@ int bs_groups(int n) { return (n + kBsChunk - 1) / kBsChunk; }
 
 hipError_t launch_bs_schedule(const BlockStepParams &bp, double t_now, int parity, hipStream_t stream) {
   const int g = bs_groups(bp.n);
-  hipLaunchKernelGGL(k_bs_list, dim3(g), dim3(kThreads), 0, stream, bp, t_now, parity);
+  hipLaunchKernelGGL(k_bs_list<false>, dim3(g), dim3(kThreads), 0, stream, bp, t_now, parity);
+  return hipGetLastError();
+}
+
+hipError_t launch_bs_schedule_dd(const BlockStepParams &bp, int parity, hipStream_t stream) {
+  const int g = bs_groups(bp.n);
+  hipLaunchKernelGGL(k_bs_list<true>, dim3(g), dim3(kThreads), 0, stream, bp, 0.0, parity);
   return hipGetLastError();
 }
 

@@ -41,7 +41,13 @@ struct BsSched {
   double t_next;  // next block time
   int count[2];   // active particles at t_next; schedules alternate between the two counters
   int clamped;    // steps clamped at dt_min (or with a criterion that is not a number) since the start
-  int pad;
+  int stop;       // device-driven runs: set once the next block time passes t_end or a step clamped
+  // device-driven runs: the block time before the schedule of parity p is tnow[p], after it
+  // tnow[p ^ 1]; t_end of the run; block steps and particle steps taken (each schedule counts the
+  // step before it)
+  double tnow[2];
+  double t_end;
+  long long blocks, steps;
 };
 struct BlockStepParams {
   SourceArrays src;
@@ -99,6 +105,11 @@ struct ForceParams {
   int bs_fuse;
   double bs_t1;
   BlockStepParams bs;
+  // device-driven block steps (k_force_dd / k_combine_dd): N_i = *dd_count and the prediction time
+  // *dd_t are read on the device; dd_shape[k] = (lanes_log2, splits) for N_i in (2^(k-1), 2^k]
+  const int *dd_count;
+  const double *dd_t;
+  int2 dd_shape[32];
 };
 
 // Batched few-body systems: particles of system s are [offset[s], offset[s+1]); items[k] =
@@ -135,6 +146,19 @@ struct VjpParams {
   double *part;
 };
 
+// Combine kernel: sinks per workgroup W = 2^wlog, with R = 256 / W threads per sink: R =
+// nextpow2(S) (at most 256), but at least min(nextpow2(N_i), kCombineQ) sinks per workgroup, so
+// that a load instruction covers whole cache lines of partials.  Shared by the host launchers and
+// the device-driven kernel.
+constexpr int kCombineQ = 16;
+__host__ __device__ inline int combine_wlog(int ni, int S) {
+  int qmin = 1;
+  while (qmin < ni && qmin < kCombineQ) qmin *= 2;
+  int rlog = 0;
+  while ((1 << rlog) < S && (1 << rlog) < kThreads / qmin) ++rlog;
+  return 8 - rlog;
+}
+
 struct LaunchShape {
   int lanes_log2;
   int sinks_per_lane;
@@ -145,6 +169,10 @@ struct LaunchShape {
 // Kernel entry points (defined in nbx_kernels.hip).
 hipError_t launch_force(int order, int precision, const ForceParams &fp, const LaunchShape &ls,
                         hipStream_t stream);
+// Device-driven block step (orders 4 and 6): gravity with force_groups workgroups, then the
+// combine + corrector with combine_groups workgroups; both loop over their work.
+hipError_t launch_force_dd(int order, int precision, const ForceParams &fp, int force_groups, int combine_groups,
+                           hipStream_t stream);
 hipError_t launch_jupdate(int order, const SourceArrays &src, int nj_cap, int n, const int32_t *addr,
                           const int64_t *id, const double *m, const double *t, const double *x,
                           const double *v, const double *a, const double *jerk, const double *snap,
@@ -167,6 +195,8 @@ hipError_t launch_selfmap(const SourceArrays &src, int nj, int ni, const int64_t
 int bs_groups(int n);
 // Schedules the block step after the last block time t_now, counting into sched->count[parity].
 hipError_t launch_bs_schedule(const BlockStepParams &bp, double t_now, int parity, hipStream_t stream);
+// Device-driven schedule: the block time and t_end come from bp.sched (see BsSched).
+hipError_t launch_bs_schedule_dd(const BlockStepParams &bp, int parity, hipStream_t stream);
 hipError_t launch_bs_correct(int order, const BlockStepParams &bp, int ni, double t1, hipStream_t stream);
 hipError_t launch_bs_load(int order, const BlockStepParams &bp, const int64_t *id, const double *m, const double *x,
                           const double *v, hipStream_t stream);

@@ -57,7 +57,6 @@ constexpr int kChunk = 64;     // same for jerk, pot and snap (a multiple of kCh
 // The gravity kernel's long-chunk variant (workgroups that run several source tiles with one lane
 // per sink) sums Tr::kLongChunk acceleration terms per chunk: fewer folds per interaction, while
 // the one-off re-scan of a nearest-neighbour group (one chunk long) stays small next to the loop.
-constexpr int kCombineQ = 16;  // fewest sinks per combine workgroup (when there are that many)
 
 // ---------------------------------------------------------------------------------------------
 // Compensated accumulation: K running values, each a plain chunk sum that is folded every
@@ -1155,15 +1154,16 @@ template <int Order, int Prec, int P, bool L1>
 constexpr int kForceWaves =
     (Prec != NBX_FP64 || P != 1 || (Order == 8 && !L1)) ? 1 : (Order >= 6 ? 2 : (Order == 4 ? 3 : 1));
 
+// One work item of the gravity kernel: sink block w / S against source split w % S.  Run by the
+// whole workgroup; tiles and red are its LDS.
 template <int Order, int Prec, int P, bool L1, bool Nbr, bool NN, bool Long>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kForceWaves<Order, Prec, P, L1>)))
-void k_force(const ForceParams fp) {
+__device__ __forceinline__ void force_item(const ForceParams &fp, int w,
+                                           typename TraitsSel<Order, Prec>::type::Tile (&tiles)[2],
+                                           RedLds<P, kValues<Order>> &red) {
   using Tr = typename TraitsSel<Order, Prec>::type;
   using T = typename Tr::Real;
   using Key = typename Tr::Key;
   constexpr int K = kValues<Order>;
-  __shared__ typename Tr::Tile tiles[2];
-  __shared__ RedLds<P, K> red;
 
   const int tid = threadIdx.x;
   const int lg = fp.lanes_log2;
@@ -1172,8 +1172,8 @@ void k_force(const ForceParams fp) {
   const int slot = tid & (L - 1);
   const int grp = tid >> lg;
   const int S = fp.splits;
-  const int split = blockIdx.x % S;
-  const int ib = blockIdx.x / S;
+  const int split = w % S;
+  const int ib = w / S;
   const int Q = G * P;
   const int ntiles = fp.nj_pad / kTile;
   const int t0 = (int)(((int64_t)split * ntiles) / S);
@@ -1294,6 +1294,48 @@ void k_force(const ForceParams fp) {
   }
 }
 
+template <int Order, int Prec, int P, bool L1, bool Nbr, bool NN, bool Long>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kForceWaves<Order, Prec, P, L1>)))
+void k_force(const ForceParams fp) {
+  __shared__ typename TraitsSel<Order, Prec>::type::Tile tiles[2];
+  __shared__ RedLds<P, kValues<Order>> red;
+  force_item<Order, Prec, P, L1, Nbr, NN, Long>(fp, blockIdx.x, tiles, red);
+}
+
+// Launch shape of a device-driven block step for ni sinks: lanes per sink and splits from the
+// per-class table (class k: ni in (2^(k-1), 2^k]), sink blocks of 256 / L sinks.
+__device__ __forceinline__ void dd_shape(const ForceParams &fp, int ni, int &lg, int &S, int &blocks) {
+  int k = 0;
+  while ((1 << k) < ni && k < 31) ++k;
+  lg = fp.dd_shape[k].x;
+  S = fp.dd_shape[k].y;
+  blocks = (ni + (kThreads >> lg) - 1) / (kThreads >> lg);
+}
+
+// Device-driven block step (the integrator's run loop): the number of active sinks and the
+// prediction time are read from device memory, which the scheduling kernel just wrote, so that
+// the host enqueues many block steps without waiting for each schedule.  Several lanes per sink
+// (runtime L, one sink per lane), no lists, no nearest neighbour; the workgroups loop over the
+// work items.
+template <int Order, int Prec>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kForceWaves<Order, Prec, 1, false>)))
+void k_force_dd(const ForceParams fp0) {
+  __shared__ typename TraitsSel<Order, Prec>::type::Tile tiles[2];
+  __shared__ RedLds<1, kValues<Order>> red;
+  const int ni = *fp0.dd_count;
+  if (ni <= 0) return;
+  ForceParams fp = fp0;
+  fp.ni = ni;
+  fp.t = *fp0.dd_t;
+  int blocks = 0;
+  dd_shape(fp0, ni, fp.lanes_log2, fp.splits, blocks);
+  const int items = blocks * fp.splits;
+  for (int w = blockIdx.x; w < items; w += gridDim.x) {
+    force_item<Order, Prec, 1, false, false, false, false>(fp, w, tiles, red);
+    __syncthreads();  // the next item restages the tiles
+  }
+}
+
 // ---------------------------------------------------------------------------------------------
 // Combine kernel for S > 1: a workgroup takes W = 2^wlog consecutive sinks with R = 256 / W threads
 // each; thread t serves sink t mod W as its lane r = t / W, so that neighbouring lanes read
@@ -1313,16 +1355,16 @@ struct CombineLds {
   int i[kThreads];
 };
 
+// One workgroup's share of the combine: sinks blk * W .. blk * W + W - 1.
 template <int Order, bool NN>
-__global__ __launch_bounds__(kThreads) void k_combine(const ForceParams fp, int wlog) {
+__device__ __forceinline__ void combine_block(const ForceParams &fp, int wlog, int blk, CombineLds<kValues<Order>> &red) {
   constexpr int K = kValues<Order>;
-  __shared__ CombineLds<K> red;
   const int t = threadIdx.x;
   const int W = 1 << wlog;
   const int R = kThreads >> wlog;
   const int ql = t & (W - 1);
   const int r = t >> wlog;
-  const int qg = blockIdx.x * W + ql;
+  const int qg = blk * W + ql;
   const int S = fp.splits;
   double w[1][K];
   uint64_t wk[1] = {~0ull};
@@ -1398,6 +1440,32 @@ __global__ __launch_bounds__(kThreads) void k_combine(const ForceParams fp, int 
     }
   }
   finalize_sink<Order, NN>(fp, qg, w[0], wi[0], nullptr);
+}
+
+template <int Order, bool NN>
+__global__ __launch_bounds__(kThreads) void k_combine(const ForceParams fp, int wlog) {
+  __shared__ CombineLds<kValues<Order>> red;
+  combine_block<Order, NN>(fp, wlog, blockIdx.x, red);
+}
+
+// Device-driven block step: the combine and corrector for the sinks of k_force_dd's launch.
+template <int Order>
+__global__ __launch_bounds__(kThreads) void k_combine_dd(const ForceParams fp0) {
+  __shared__ CombineLds<kValues<Order>> red;
+  const int ni = *fp0.dd_count;
+  if (ni <= 0) return;
+  ForceParams fp = fp0;
+  fp.ni = ni;
+  fp.t = *fp0.dd_t;
+  fp.bs_t1 = fp.t;
+  int blocks = 0;
+  dd_shape(fp0, ni, fp.lanes_log2, fp.splits, blocks);
+  const int wlog = combine_wlog(ni, fp.splits);
+  const int nblk = (ni + (1 << wlog) - 1) >> wlog;
+  for (int b = blockIdx.x; b < nblk; b += gridDim.x) {
+    combine_block<Order, false>(fp, wlog, b, red);
+    __syncthreads();  // the next block reuses the LDS
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1889,13 +1957,7 @@ static hipError_t launch_force_t(const ForceParams &fp, const LaunchShape &ls, h
     e = hipGetLastError();
   }
   if (e != hipSuccess || ls.splits <= 1) return e;
-  // threads per sink R = nextpow2(S) (at most 256), but at least min(nextpow2(N_i), kCombineQ)
-  // sinks per workgroup, so that a load instruction covers whole cache lines of partials
-  int qmin = 1;
-  while (qmin < fp.ni && qmin < kCombineQ) qmin *= 2;
-  int rlog = 0;
-  while ((1 << rlog) < ls.splits && (1 << rlog) < kThreads / qmin) ++rlog;
-  const int wlog = 8 - rlog;
+  const int wlog = combine_wlog(fp.ni, ls.splits);
   const int W = 1 << wlog;
   hipLaunchKernelGGL((k_combine<Order, NN>), dim3((fp.ni + W - 1) / W), dim3(kThreads), 0, stream, fp, wlog);
   return hipGetLastError();
@@ -1935,6 +1997,28 @@ hipError_t launch_force(int order, int precision, const ForceParams &fp, const L
                                   : launch_force_op<6, NBX_FP64>(fp, ls, stream);
   return precision == NBX_MIXED ? launch_force_op<8, NBX_MIXED>(fp, ls, stream)
                                 : launch_force_op<8, NBX_FP64>(fp, ls, stream);
+}
+
+template <int Order, int Prec>
+static hipError_t launch_force_dd_t(const ForceParams &fp, int force_groups, int combine_groups, hipStream_t stream) {
+  hipLaunchKernelGGL((k_force_dd<Order, Prec>), dim3(force_groups), dim3(kThreads), 0, stream, fp);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_combine_dd<Order>, dim3(combine_groups), dim3(kThreads), 0, stream, fp);
+  return hipGetLastError();
+}
+
+hipError_t launch_force_dd(int order, int precision, const ForceParams &fp, int force_groups, int combine_groups,
+                           hipStream_t stream) {
+  if (order == 4)
+    return precision == NBX_MIXED ? launch_force_dd_t<4, NBX_MIXED>(fp, force_groups, combine_groups, stream)
+           : precision == NBX_DS  ? launch_force_dd_t<4, NBX_DS>(fp, force_groups, combine_groups, stream)
+                                  : launch_force_dd_t<4, NBX_FP64>(fp, force_groups, combine_groups, stream);
+  if (order == 6)
+    return precision == NBX_MIXED ? launch_force_dd_t<6, NBX_MIXED>(fp, force_groups, combine_groups, stream)
+           : precision == NBX_DS  ? launch_force_dd_t<6, NBX_DS>(fp, force_groups, combine_groups, stream)
+                                  : launch_force_dd_t<6, NBX_FP64>(fp, force_groups, combine_groups, stream);
+  return hipErrorInvalidValue;
 }
 
 static inline int grid_for(int n) { return (n + 255) / 256; }

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -1218,6 +1219,103 @@ int bs_schedule(nbx_ctx *c, double *t_next, int *count, int *clamped) {
   return NBX_OK;
 }
 
+// Device-driven run: the host enqueues kDdBatch block steps at a time (schedule, gravity, combine
+// with the corrector; each kernel reads N_active and the block time from the schedule record) and
+// synchronises once per batch.  Launch shapes per N_i class come from ctx_shape (tuned table or
+// static rule) with one sink per lane and at least two source splits, so that the corrector
+// always runs in the combine kernel.  Needs at least two source tiles; returns NBX_ERR_STATE
+// otherwise (the caller then takes the host loop).
+constexpr int kDdBatch = 32;
+
+int bs_run_dd(nbx_ctx *c, double t_end, int *status) {
+  const int n = c->bs.n;
+  const int nj_pad = (c->nj + kTile - 1) / kTile * kTile;
+  const int ntiles = nj_pad / kTile;
+  if (ntiles < 2) return NBX_ERR_STATE;
+  ForceParams fp{};
+  int kmax = 0;
+  while ((1 << kmax) < n && kmax < 31) ++kmax;
+  size_t part_slots = 0;
+  int force_groups = 1, combine_groups = 1;
+  for (int k = 0; k <= kmax; ++k) {
+    const int ni = std::min(1 << k, n);
+    LaunchShape ls = ctx_shape(c, ni, nj_pad);
+    if (ls.sinks_per_lane == 2) ls.sinks_per_lane = 1;  // one sink per lane: blocks of 256 / L sinks
+    int S = std::max(2, std::min(ls.splits, ntiles));
+    const int64_t scap = ((int64_t)1 << 21) / ni;
+    if (S > scap) S = std::max<int64_t>(2, scap);
+    const int Q = kThreads >> ls.lanes_log2;
+    const int blocks = (ni + Q - 1) / Q;
+    fp.dd_shape[k] = make_int2(ls.lanes_log2, S);
+    part_slots = std::max(part_slots, (size_t)S * (size_t)ni);
+    force_groups = std::max(force_groups, blocks * S);
+    combine_groups = std::max(combine_groups, (ni + (1 << combine_wlog(ni, S)) - 1) >> combine_wlog(ni, S));
+  }
+  for (int k = kmax + 1; k < 32; ++k) fp.dd_shape[k] = fp.dd_shape[kmax];
+  force_groups = std::min(force_groups, 2048);  // 8 per CU; larger steps loop over their work items
+  combine_groups = std::min(combine_groups, 512);
+  {
+    const size_t K = (size_t)values_per_sink(c->cfg.order);
+    if (int rc = grow(c, c->part, part_slots * K * sizeof(double))) return rc;
+    if (int rc = grow(c, c->part_key, part_slots * sizeof(uint64_t))) return rc;
+    if (int rc = grow(c, c->part_idx, part_slots * sizeof(int32_t))) return rc;
+  }
+  const BlockStepParams bp = bs_params(c);
+  fp.src = c->src;
+  fp.nj = c->nj;
+  fp.nj_pad = nj_pad;
+  fp.eps2 = c->bs.p.eps2;
+  fp.i_addr = bp.list;
+  fp.acc = static_cast<double *>(c->bs.acc.p);
+  fp.jrk = static_cast<double *>(c->bs.jrk.p);
+  fp.snp = static_cast<double *>(c->bs.snp.p);
+  fp.pot = static_cast<double *>(c->bs.pot.p);
+  fp.part = static_cast<double *>(c->part.p);
+  fp.part_key = static_cast<uint64_t *>(c->part_key.p);
+  fp.part_idx = static_cast<int32_t *>(c->part_idx.p);
+  fp.err = c->d_err;
+  fp.nn = 0;
+  fp.bs_fuse = 1;
+  fp.bs = bp;
+  ForceParams fpp[2] = {fp, fp};
+  for (int p = 0; p < 2; ++p) {
+    fpp[p].dd_count = &bp.sched->count[p];
+    fpp[p].dd_t = &bp.sched->tnow[p ^ 1];
+  }
+  // the run's fields of the schedule record (stop .. steps) from the host, and the counter of the
+  // step before the first schedule, which the host has already counted, cleared
+  int parity = c->bs.parity;
+  BsSched *h = c->bs.h_sched;
+  h->stop = 0;
+  h->tnow[0] = h->tnow[1] = c->bs.t;
+  h->t_end = t_end;
+  h->blocks = c->bs.blocks;
+  h->steps = c->bs.steps;
+  const size_t off = offsetof(BsSched, stop);
+  hipStream_t s = c->stream;
+  HIP_TRY(c, hipMemcpyAsync(reinterpret_cast<char *>(bp.sched) + off, reinterpret_cast<char *>(h) + off,
+                            sizeof(BsSched) - off, hipMemcpyHostToDevice, s));
+  HIP_TRY(c, launch_fill_i32(&bp.sched->count[parity ^ 1], 1, 0, s));
+  for (;;) {
+    for (int k = 0; k < kDdBatch; ++k) {
+      HIP_TRY(c, launch_bs_schedule_dd(bp, parity, s));
+      HIP_TRY(c, launch_force_dd(c->cfg.order, c->precision, fpp[parity], force_groups, combine_groups, s));
+      parity ^= 1;
+    }
+    HIP_TRY(c, hipMemcpyAsync(h, bp.sched, sizeof(BsSched), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    if (h->stop) break;
+  }
+  c->bs.parity = parity;
+  c->bs.t = h->tnow[parity];
+  c->bs.blocks = h->blocks;
+  c->bs.steps = h->steps;
+  c->t_pred = c->bs.t;
+  c->predicted = true;
+  *status = h->clamped > 0 ? NBX_WARN_DT_MIN : NBX_OK;
+  return NBX_OK;
+}
+
 int bs_check(nbx_ctx *c) {
   if (int rc = check_ctx(c)) return rc;
   if (!c->bs.ready) return fail(c, NBX_ERR_STATE, "no block time-step state (nbx_bs_init, and no nbx_set_j since)");
@@ -1318,10 +1416,18 @@ int nbx_bs_step(nbx_ctx *c, double t_end, int *n_active) {
 int nbx_bs_run(nbx_ctx *c, double t_end, nbx_bs_stats *stats) {
   if (int rc = bs_check(c)) return rc;
   int rc = NBX_OK;
-  for (;;) {
-    int ni = 0;
-    rc = nbx_bs_step(c, t_end, &ni);
-    if (rc != NBX_OK || ni == 0) break;
+  int dd_status = NBX_OK;
+  const int dd = getenv("NBX_BS_HOST_LOOP") ? NBX_ERR_STATE : bs_run_dd(c, t_end, &dd_status);
+  if (dd == NBX_OK) {
+    rc = dd_status;
+  } else if (dd != NBX_ERR_STATE) {
+    return dd;
+  } else {
+    for (;;) {  // one source tile, or the host loop asked for: one synchronised block step at a time
+      int ni = 0;
+      rc = nbx_bs_step(c, t_end, &ni);
+      if (rc != NBX_OK || ni == 0) break;
+    }
   }
   if (rc < 0) return rc;
   HIP_TRY(c, hipStreamSynchronize(c->stream));

@@ -225,3 +225,82 @@ def test_blockstep_large_n_schedule():
     # sanity bound only (a particle dropped from or repeated in a block breaks the invariants above
     # first): 4th order, eta4 = 0.01, eps = 1e-3, steps down to ~2^-15 in the core
     assert de < 1e-6
+
+
+def _dd_run(order, prec, m, x, v, eps2, t_end, host_loop=False, **kw):
+    """nbx_bs_run: device-driven (block steps enqueued in batches, N_active read on the device) or,
+    with host_loop, one host-synchronised block step at a time."""
+    import os
+
+    n = len(m)
+    old = os.environ.pop("NBX_BS_HOST_LOOP", None)
+    if host_loop:
+        os.environ["NBX_BS_HOST_LOOP"] = "1"
+    try:
+        with nbx.Context(order=order, precision=prec, nj_max=n, ni_max=n) as ctx:
+            nbx.nbx_bs_init(ctx.ctx, np.arange(n), m, x, v, eps2, **kw)
+            st = nbx.nbx_bs_run(ctx.ctx, t_end)
+            state = nbx.nbx_bs_get_state(ctx.ctx, n)
+            again = nbx.nbx_bs_run(ctx.ctx, t_end)  # nothing left to do
+    finally:
+        os.environ.pop("NBX_BS_HOST_LOOP", None)
+        if old is not None:
+            os.environ["NBX_BS_HOST_LOOP"] = old
+    return st, state, again
+
+
+@pytest.mark.parametrize("order", [4, 6])
+def test_blockstep_device_driven_matches_oracle(order):
+    """The device-driven run loop (three source tiles, so its kernels are used) against the oracle
+    integrator: the same block steps and particle steps, identical final steps and times, state to
+    1e-10; a second run to the same t_end takes no step."""
+    n, eps2, t_end = 700, 1e-4, 1.0 / 16
+    say("blockstep device-driven order=%d fp64 n=%d" % (order, n))
+    src = nbody_ics.make_sources(n, seed=63, time_offsets=False)
+    ref = obs.BlockStep(order, src.m, src.x, src.v, eps2).run(t_end)
+    xr, vr = ref.state()
+    st, state, again = _dd_run(order, nbx.NBX_FP64, src.m, src.x, src.v, eps2, t_end)
+    say("  status %d t %g blocks %d (oracle %d) steps %d (oracle %d)" % (
+        st["status"], st["t"], st["block_steps"], len(ref.log), st["particle_steps"], sum(k for _, k in ref.log)))
+    assert st["status"] == nbx.NBX_OK and st["t"] == t_end
+    assert st["block_steps"] == len(ref.log) and st["particle_steps"] == sum(k for _, k in ref.log)
+    np.testing.assert_array_equal(state["dt"], ref.dt)
+    np.testing.assert_array_equal(state["t_i"], ref.t_i)
+    assert np.abs(state["x"] - xr).max() <= 1e-10 * np.abs(xr).max()
+    assert np.abs(state["v"] - vr).max() <= 1e-10 * np.abs(vr).max()
+    assert again["block_steps"] == st["block_steps"] and again["t"] == t_end
+
+
+def test_blockstep_device_driven_matches_host_loop():
+    """Device-driven and host-synchronised runs of the same 6th-order FP64 integration (N = 2000):
+    the same schedule; states equal to summation-order rounding."""
+    n, eps2, t_end = 2000, 1e-6, 1.0 / 16
+    say("blockstep device-driven vs host loop n=%d" % n)
+    m, x, v = nbody_ics.plummer(n, seed=7)
+    a, sa, _ = _dd_run(6, nbx.NBX_FP64, m, x, v, eps2, t_end)
+    b, sb, _ = _dd_run(6, nbx.NBX_FP64, m, x, v, eps2, t_end, host_loop=True)
+    say("  device-driven blocks %d steps %d | host loop blocks %d steps %d" % (
+        a["block_steps"], a["particle_steps"], b["block_steps"], b["particle_steps"]))
+    assert (a["block_steps"], a["particle_steps"], a["t"]) == (b["block_steps"], b["particle_steps"], b["t"])
+    np.testing.assert_array_equal(sa["dt"], sb["dt"])
+    assert np.abs(sa["x"] - sb["x"]).max() <= 1e-12 * np.abs(sb["x"]).max()
+
+
+@pytest.mark.parametrize("order", [4, 6])
+def test_blockstep_device_driven_dt_min_stop(order):
+    """The forced dt_min stop (as test_blockstep_dt_min_stop_deterministic) through the
+    device-driven loop (N = 700): NBX_WARN_DT_MIN at the oracle's block time and step counts."""
+    n, eps2, t_end, dt_min = 700, 1e-4, 1.0 / 16, 2.0**-10
+    say("blockstep device-driven forced dt_min stop order=%d n=%d" % (order, n))
+    src = nbody_ics.make_sources(n, seed=63, time_offsets=False)
+    kw = dict(eta4=1e-10, eta6=1e-6, dt_min=dt_min)
+    ref = obs.BlockStep(order, src.m, src.x, src.v, eps2, **kw).run(t_end)
+    assert ref.clamped > 0 and ref.t < t_end
+    st, state, again = _dd_run(order, nbx.NBX_FP64, src.m, src.x, src.v, eps2, t_end, **kw)
+    say("  status %d t %.6g blocks %d (oracle t %.6g blocks %d)" % (st["status"], st["t"], st["block_steps"],
+                                                                     ref.t, len(ref.log)))
+    assert st["status"] == nbx.NBX_WARN_DT_MIN and again["status"] == nbx.NBX_WARN_DT_MIN
+    assert st["t"] == ref.t and again["t"] == ref.t
+    assert st["block_steps"] == len(ref.log) and st["particle_steps"] == sum(k for _, k in ref.log)
+    np.testing.assert_array_equal(state["dt"], ref.dt)
+    assert np.all(np.isfinite(state["x"]))
