@@ -94,8 +94,10 @@ struct ForceParams {
   double *nn_r2;
   int32_t *nbr_count;
   int64_t *nbr_ids;
-  // split-combine scratch (S > 1), written by k_force and read by k_combine:
-  // part[(s*K + k)*ni + q], part_key/part_idx[s*ni + q]
+  // split-combine scratch (S > 1), written by k_force and read by k_combine: split-major
+  // part[(s*K + k)*ni + q], part_key/part_idx[s*ni + q], or with part_sm sink-major
+  // part[(q*K + k)*S + s], part_key/part_idx[q*S + s]
+  int part_sm;
   double *part;
   uint64_t *part_key;
   int32_t *part_idx;
@@ -156,6 +158,16 @@ __host__ __device__ inline int combine_wlog(int ni, int S) {
   while (qmin < ni && qmin < kCombineQ) qmin *= 2;
   int rlog = 0;
   while ((1 << rlog) < S && (1 << rlog) < kThreads / qmin) ++rlog;
+  return 8 - rlog;
+}
+
+// Sink-major partials (small N_i, many splits): one workgroup per sink or few sinks, R =
+// nextpow2(S) threads per sink (at most 256) reading consecutive splits.
+constexpr int kSinkMajorMaxNi = 256;  // largest N_i combined sink-major (A/B: -13% at N_i = 64, -6% at 256, neutral at 512, +4% at 1024)
+constexpr int kSinkMajorMinS = 64;     // fewest splits combined sink-major
+__host__ __device__ inline int combine_wlog_sink_major(int S) {
+  int rlog = 0;
+  while ((1 << rlog) < S && rlog < 8) ++rlog;
   return 8 - rlog;
 }
 

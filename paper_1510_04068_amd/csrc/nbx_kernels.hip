@@ -1154,6 +1154,14 @@ template <int Order, int Prec, int P, bool L1>
 constexpr int kForceWaves =
     (Prec != NBX_FP64 || P != 1 || (Order == 8 && !L1)) ? 1 : (Order >= 6 ? 2 : (Order == 4 ? 3 : 1));
 
+// Index of value k (of nv per sink) of split s for sink q in the split-partial arrays: split-major
+// (the partials of one split and value are contiguous over the sinks: coalesced for many sinks)
+// or, with part_sm, sink-major (the splits of one sink and value are contiguous: coalesced when
+// the combine gives each sink a whole workgroup, at small N_i).
+__device__ __forceinline__ size_t part_at(const ForceParams &fp, int s, int k, int q, int nv) {
+  return fp.part_sm ? ((size_t)q * nv + k) * fp.splits + s : ((size_t)s * nv + k) * fp.ni + q;
+}
+
 // One work item of the gravity kernel: sink block w / S against source split w % S.  Run by the
 // whole workgroup; tiles and red are its LDS.
 template <int Order, int Prec, int P, bool L1, bool Nbr, bool NN, bool Long>
@@ -1179,6 +1187,30 @@ __device__ __forceinline__ void force_item(const ForceParams &fp, int w,
   const int t0 = (int)(((int64_t)split * ntiles) / S);
   const int t1 = (int)(((int64_t)(split + 1) * ntiles) / S);
 
+  // Tile staging with the fused predictor.  Addresses >= nj (the tail of the last tile) get a
+  // padding source: massless, at rest, at (kPadPos, kPadPos, kPadPos); all its terms are exact
+  // zeros in both precisions and its address marks "no neighbour".
+  auto stage = [&](int tile, int buf) {
+    const int jj = tile * kTile + tid;
+    double xp[3], vp[3], ap[6], m;
+    if (jj < fp.nj) {
+      predict_addr<Order>(fp.src, jj, fp.t, xp, vp, ap, m);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        xp[k] = kPadPos;
+        vp[k] = 0.0;
+        ap[k] = 0.0;
+        ap[3 + k] = 0.0;
+      }
+      m = 0.0;
+    }
+    Tr::store(tiles[buf], tid, xp, vp, ap, m);
+  };
+
+  // the first tile's loads go out before the sink set-up's (an address, then the sink's state),
+  // so that the two latencies overlap
+  if (t0 < t1) stage(t0, 0);
   typename Tr::Sink sink[P];
   Comp<T, K> acc[P];
   Key nnk[P];
@@ -1215,28 +1247,6 @@ __device__ __forceinline__ void force_item(const ForceParams &fp, int w,
   }
   const T eps2 = (T)fp.eps2;
 
-  // Tile staging with the fused predictor.  Addresses >= nj (the tail of the last tile) get a
-  // padding source: massless, at rest, at (kPadPos, kPadPos, kPadPos); all its terms are exact
-  // zeros in both precisions and its address marks "no neighbour".
-  auto stage = [&](int tile, int buf) {
-    const int jj = tile * kTile + tid;
-    double xp[3], vp[3], ap[6], m;
-    if (jj < fp.nj) {
-      predict_addr<Order>(fp.src, jj, fp.t, xp, vp, ap, m);
-    } else {
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        xp[k] = kPadPos;
-        vp[k] = 0.0;
-        ap[k] = 0.0;
-        ap[3 + k] = 0.0;
-      }
-      m = 0.0;
-    }
-    Tr::store(tiles[buf], tid, xp, vp, ap, m);
-  };
-
-  if (t0 < t1) stage(t0, 0);
   __syncthreads();
   for (int tile = t0; tile < t1; ++tile) {
     const int buf = (tile - t0) & 1;
@@ -1284,10 +1294,10 @@ __device__ __forceinline__ void force_item(const ForceParams &fp, int w,
     for (int p = 0; p < P; ++p) {
       if (q[p] < fp.ni) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) fp.part[((size_t)split * K + k) * fp.ni + q[p]] = v[p][k];
+        for (int k = 0; k < K; ++k) fp.part[part_at(fp, split, k, q[p], K)] = v[p][k];
         if constexpr (NN) {
-          fp.part_key[(size_t)split * fp.ni + q[p]] = kk[p];
-          fp.part_idx[(size_t)split * fp.ni + q[p]] = ii[p];
+          fp.part_key[part_at(fp, split, 0, q[p], 1)] = kk[p];
+          fp.part_idx[part_at(fp, split, 0, q[p], 1)] = ii[p];
         }
       }
     }
@@ -1385,10 +1395,10 @@ __device__ __forceinline__ void combine_block(const ForceParams &fp, int wlog, i
 #pragma unroll 4
     for (int s = r; s < S; s += R) {
 #pragma unroll
-      for (int k = 0; k < K; ++k) w[0][k] += fp.part[((size_t)s * K + k) * fp.ni + qg];
+      for (int k = 0; k < K; ++k) w[0][k] += fp.part[part_at(fp, s, k, qg, K)];
       if constexpr (NN) {
-        const uint64_t pk = fp.part_key[(size_t)s * fp.ni + qg];
-        const int pi = fp.part_idx[(size_t)s * fp.ni + qg];
+        const uint64_t pk = fp.part_key[part_at(fp, s, 0, qg, 1)];
+        const int pi = fp.part_idx[part_at(fp, s, 0, qg, 1)];
         if (nn_better(pk, pi, wk[0], wi[0])) {
           wk[0] = pk;
           wi[0] = pi;
@@ -1957,7 +1967,7 @@ static hipError_t launch_force_t(const ForceParams &fp, const LaunchShape &ls, h
     e = hipGetLastError();
   }
   if (e != hipSuccess || ls.splits <= 1) return e;
-  const int wlog = combine_wlog(fp.ni, ls.splits);
+  const int wlog = fp.part_sm ? combine_wlog_sink_major(ls.splits) : combine_wlog(fp.ni, ls.splits);
   const int W = 1 << wlog;
   hipLaunchKernelGGL((k_combine<Order, NN>), dim3((fp.ni + W - 1) / W), dim3(kThreads), 0, stream, fp, wlog);
   return hipGetLastError();

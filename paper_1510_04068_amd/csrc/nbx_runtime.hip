@@ -400,6 +400,7 @@ int enqueue_force(nbx_ctx *c, hipStream_t stream, int ni, const int32_t *d_iaddr
   fp.part = part;
   fp.part_key = part_key;
   fp.part_idx = part_idx;
+  fp.part_sm = ls.splits >= kSinkMajorMinS && ni <= kSinkMajorMaxNi ? 1 : 0;
   fp.err = c->d_err;
   if (bs && ls.splits > 1 && !d_h2) {
     fp.bs_fuse = 1;
