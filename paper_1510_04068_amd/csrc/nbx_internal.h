@@ -200,6 +200,8 @@ hipError_t launch_fill_i32(int32_t *p, int n, int value, hipStream_t stream);
 hipError_t launch_clock_sample(int n_groups, int64_t *out, hipStream_t stream);
 hipError_t launch_vjp(int precision, const VjpParams &vp, hipStream_t stream);
 hipError_t launch_batch(int precision, const BatchParams &bp, int grid, hipStream_t stream);
+// Workgroups of the batch kernel resident on the device at once (occupancy x CUs), 0 if unknown.
+int batch_resident_groups(int precision, int device);
 hipError_t launch_selfmap(const SourceArrays &src, int nj, int ni, const int64_t *ext_id, int32_t *self,
                           hipStream_t stream);
 

@@ -1486,16 +1486,74 @@ __global__ __launch_bounds__(kThreads) void k_combine_dd(const ForceParams fp0) 
 // lane summing every L-th source (self excluded by index), and a butterfly over the L lanes.  L
 // comes per item from the schedule (chosen per size class by nbx_batch_tune).
 // ---------------------------------------------------------------------------------------------
+// The batch stages the 4th-order part of each source record only (position, mass, velocity):
+// 40 B (mixed) or 56 B (FP64) per particle instead of the full record, so that more workgroups fit
+// a CU's LDS.
+template <int Prec>
+struct BatchRec;
+template <>
+struct BatchRec<NBX_MIXED> {
+  float xh[3], m, xl[3], v[3];
+  __device__ static __forceinline__ BatchRec of(const Mixed<4>::J &j) {
+    BatchRec r;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      r.xh[c] = j.xh[c];
+      r.xl[c] = j.xl[c];
+      r.v[c] = j.v[c];
+    }
+    r.m = j.m;
+    return r;
+  }
+  __device__ __forceinline__ Mixed<4>::J j() const {
+    Mixed<4>::J o;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      o.xh[c] = xh[c];
+      o.xl[c] = xl[c];
+      o.v[c] = v[c];
+      o.a[c] = o.j[c] = 0.0f;
+    }
+    o.m = m;
+    return o;
+  }
+};
+template <>
+struct BatchRec<NBX_FP64> {
+  double x[3], m, v[3];
+  __device__ static __forceinline__ BatchRec of(const F64<4>::J &j) {
+    BatchRec r;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      r.x[c] = j.x[c];
+      r.v[c] = j.v[c];
+    }
+    r.m = j.m;
+    return r;
+  }
+  __device__ __forceinline__ F64<4>::J j() const {
+    F64<4>::J o;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      o.x[c] = x[c];
+      o.v[c] = v[c];
+      o.a[c] = o.j[c] = 0.0;
+    }
+    o.m = m;
+    return o;
+  }
+};
+
 template <int Prec>
 __global__ __launch_bounds__(kThreads) void k_batch(const BatchParams bp) {
   using Tr = typename TraitsSel<4, Prec>::type;
   using T = typename Tr::Real;
   constexpr int K = kValues<4>;
-  __shared__ typename Tr::J lds_all[kThreads / 64][kBatchMax];
+  __shared__ BatchRec<Prec> lds_all[kThreads / 64][kBatchMax];
   __shared__ RedLds<1, K> red_unused;
   const int lane = threadIdx.x & 63;
   const int wslot = threadIdx.x >> 6;
-  typename Tr::J *lds = lds_all[wslot];
+  BatchRec<Prec> *lds = lds_all[wslot];
   const int nwaves = gridDim.x * (kThreads / 64);
   const T eps2 = (T)bp.eps2;
   for (int it = blockIdx.x * (kThreads / 64) + wslot; it < bp.n_items; it += nwaves) {
@@ -1511,7 +1569,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchParams bp) {
         x[c] = bp.x[3 * (size_t)(b + k) + c];
         v[c] = bp.v[3 * (size_t)(b + k) + c];
       }
-      lds[k] = Tr::make_j(x, v, zero, bp.m[b + k]);
+      lds[k] = BatchRec<Prec>::of(Tr::make_j(x, v, zero, bp.m[b + k]));
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -1521,13 +1579,14 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchParams bp) {
       const int i = base + (lane >> lg);
       const int slot = lane & (L - 1);
       const bool live = i < s_end;
-      const typename Tr::Sink si = Tr::sink_from_j(lds[live ? i : 0]);
+      const typename Tr::Sink si = Tr::sink_from_j(lds[live ? i : 0].j());
       Comp<T, K> acc;
       acc.init();
       typename Tr::GKey dummy = Tr::gkey_none();
       for (int j0 = slot; j0 < n; j0 += kChunkAcc << lg) {
         const int je = n < j0 + (kChunkAcc << lg) ? n : j0 + (kChunkAcc << lg);
-        for (int j = j0; j < je; j += L) Tr::template interact<true, false, false>(lds[j], si, eps2, j, i, acc, dummy);
+        for (int j = j0; j < je; j += L)
+          Tr::template interact<true, false, false>(lds[j].j(), si, eps2, j, i, acc, dummy);
         acc.template fold<0, K>();
       }
       double w[1][K];
@@ -2110,6 +2169,19 @@ hipError_t launch_batch(int precision, const BatchParams &bp, int grid, hipStrea
   else
     hipLaunchKernelGGL(k_batch<NBX_FP64>, dim3(grid), dim3(kThreads), 0, stream, bp);
   return hipGetLastError();
+}
+
+int batch_resident_groups(int precision, int device) {
+  int per_cu = 0, cus = 0;
+  const hipError_t e = precision == NBX_MIXED
+                           ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<NBX_MIXED>, kThreads, 0)
+                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<NBX_FP64>, kThreads, 0);
+  if (e != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+      per_cu < 1 || cus < 1) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return per_cu * cus;
 }
 
 hipError_t launch_selfmap(const SourceArrays &src, int nj, int ni, const int64_t *ext_id, int32_t *self,

@@ -413,6 +413,13 @@ int enqueue_force(nbx_ctx *c, hipStream_t stream, int ni, const int32_t *d_iaddr
   return NBX_OK;
 }
 
+// Workgroups of the persistent batch launch: as many as are resident at once for the context's
+// precision (occupancy times CUs, from the runtime), else 8 per CU.
+int batch_groups(nbx_ctx *c) {
+  const int g = batch_resident_groups(c->precision, c->cfg.device);
+  return g > 0 ? std::min(g, kBatchMaxGroups) : kBatchMaxGroups;
+}
+
 // Size class of a batched system of n particles: smallest c with n <= 2^c.
 int batch_class(int n) {
   int c = 0;
@@ -454,7 +461,7 @@ int batch_upload(nbx_ctx *c, unsigned class_mask, const int *lg_override, hipStr
     total += q.rounds * q.round_cost;
     sys.push_back(q);
   }
-  const int64_t waves = (int64_t)kBatchMaxGroups * (kThreads / 64);
+  const int64_t waves = (int64_t)batch_groups(c) * (kThreads / 64);
   const int64_t target = std::max<int64_t>(1, (total + waves - 1) / waves);
   struct Item {
     int4 v;
@@ -496,7 +503,7 @@ int batch_enqueue(nbx_ctx *c, hipStream_t stream, const double *d_m, const doubl
   bp.pot = d_pot;
   const int waves_per_wg = kThreads / 64;
   int grid = (bp.n_items + waves_per_wg - 1) / waves_per_wg;
-  if (grid > kBatchMaxGroups) grid = kBatchMaxGroups;  // persistent: waves loop over items
+  if (grid > batch_groups(c)) grid = batch_groups(c);  // persistent: waves loop over items
   if (grid < 1) grid = 1;
   hipError_t e = launch_batch(c->precision, bp, grid, stream);
   if (e != hipSuccess) return hip_fail(c, e, "batch kernel launch");
