@@ -1149,10 +1149,15 @@ __device__ __forceinline__ int nn_rescan(const ForceParams &fp, const typename T
 // faster for orders 4 and 6 at every N_i timed; for order 8 faster with one lane per sink (N_i >=
 // 1024) but slower with several lanes per sink at N_i <= 64, where each workgroup runs one tile
 // and the spills of its set-up and reduction are not amortised, so order 8 caps only the former.
-// The mixed kernels and two sinks per lane keep the compiler's choice.
+// The mixed 4th-order kernel with two sinks per lane (the many-sink case) takes 156-176 registers
+// (three waves, two with lists and search); capped at 128 it runs four, its spills stay out of the
+// pair loops, and it ran 5% faster at N_i = 65536 and 131072.  The same cap on the 6th-order one (three waves instead of
+// two) gained nothing.  The other mixed kernels keep the compiler's choice.
 template <int Order, int Prec, int P, bool L1>
 constexpr int kForceWaves =
-    (Prec != NBX_FP64 || P != 1 || (Order == 8 && !L1)) ? 1 : (Order >= 6 ? 2 : (Order == 4 ? 3 : 1));
+    (Prec == NBX_MIXED && P == 2 && Order == 4)
+        ? 4
+        : (Prec != NBX_FP64 || P != 1 || (Order == 8 && !L1)) ? 1 : (Order >= 6 ? 2 : (Order == 4 ? 3 : 1));
 
 // Index of value k (of nv per sink) of split s for sink q in the split-partial arrays: split-major
 // (the partials of one split and value are contiguous over the sinks: coalesced for many sinks)
