@@ -1114,8 +1114,13 @@ __device__ __forceinline__ typename Tr::J staged_j(const ForceParams &fp, int jj
 // When the group lies in the tile still resident in LDS after the loop (the workgroup's last
 // tile: always the case when a workgroup has one tile, i.e. at small and medium N_i), its records
 // are read back from LDS; otherwise they are staged again from global memory.  Either way they are
-// the records the loop used, so the keys match bit for bit.
-template <class Tr, int Order, bool Nbr, bool Long>
+// the records the loop used, so the keys match bit for bit.  With four or more lanes per sink
+// (N_i <= 256: one tile per workgroup, read back from LDS) every source of the group is tested,
+// last to first, and the earliest match survives: no early exit, so the reads of several sources
+// are in flight together.  With fewer lanes per sink the extra bank-conflicted reads of that form
+// slow the waves still in their loops (measured 6% slower at N_i = 512, two lanes per sink), so
+// there, and for groups staged again from global memory, the scan stops at the first match.
+template <class Tr, int Order, bool Nbr, bool Long, bool L1>
 __device__ __forceinline__ int nn_rescan(const ForceParams &fp, const typename Tr::Tile &last, int last_tile,
                                          const typename Tr::Sink &s, typename Tr::Key key, int g0, int lg,
                                          int self, typename Tr::Real eps2) {
@@ -1124,6 +1129,16 @@ __device__ __forceinline__ int nn_rescan(const ForceParams &fp, const typename T
   constexpr int kCA = Long ? Tr::kLongChunk : kChunkAcc;
   const int len = per < kCA ? per : kCA;
   if ((g0 >> 8) == last_tile) {  // kTile == 256
+    if (!L1 && lg >= 2) {
+      int found = -1;
+#pragma unroll 8
+      for (int k = len - 1; k >= 0; --k) {
+        const int jj = g0 + (k << lg);
+        const bool hit = Tr::template nn_key<Nbr>(Tr::load(last, jj & (kTile - 1)), s, eps2) == key;
+        found = (hit && jj != self) ? jj : found;
+      }
+      return found;
+    }
     for (int k = 0; k < len; ++k) {
       const int jj = g0 + (k << lg);
       if (jj != self && Tr::template nn_key<Nbr>(Tr::load(last, jj & (kTile - 1)), s, eps2) == key) return jj;
@@ -1151,8 +1166,8 @@ __device__ __forceinline__ int nn_rescan(const ForceParams &fp, const typename T
 // and the spills of its set-up and reduction are not amortised, so order 8 caps only the former.
 // The mixed 4th-order kernel with two sinks per lane (the many-sink case) takes 156-176 registers
 // (three waves, two with lists and search); capped at 128 it runs four, its spills stay out of the
-// pair loops, and it ran 5% faster at N_i = 65536 and 131072.  The same cap on the 6th-order one (three waves instead of
-// two) gained nothing.  The other mixed kernels keep the compiler's choice.
+// pair loops, and it ran 5% faster at N_i = 65536 and 131072.  The same cap on the 6th-order one
+// (three waves instead of two) gained nothing.  The other mixed kernels keep the compiler's choice.
 template <int Order, int Prec, int P, bool L1>
 constexpr int kForceWaves =
     (Prec == NBX_MIXED && P == 2 && Order == 4)
@@ -1278,8 +1293,8 @@ __device__ __forceinline__ void force_item(const ForceParams &fp, int w,
 #pragma unroll
     for (int k = 0; k < K; ++k) v[p][k] = acc[p].value(k);
     kk[p] = (uint64_t)nnk[p];
-    ii[p] = NN ? nn_rescan<Tr, Order, Nbr, Long>(fp, tiles[(t1 - 1 - t0) & 1], t1 - 1, sink[p], nnk[p], nng[p], lg,
-                                                 self[p], eps2)
+    ii[p] = NN ? nn_rescan<Tr, Order, Nbr, Long, L1>(fp, tiles[(t1 - 1 - t0) & 1], t1 - 1, sink[p], nnk[p], nng[p],
+                                                     lg, self[p], eps2)
                : -1;
   }
   group_reduce<P, K, NN>(L, v, kk, ii, red);
