@@ -1985,8 +1985,9 @@ LaunchShape choose_shape(int ni, int nj_pad, int prec, int order) {
   LaunchShape ls;
   const int ntiles = nj_pad / kTile > 0 ? nj_pad / kTile : 1;
   // workgroups to aim for: few sinks take ~512 (two per CU) so that each staged, predicted source
-  // feeds as many sinks as possible; many sinks take more, to even out the last round
-  const int target = ni >= 16384 ? 4096 : (ni >= 256 ? 2048 : 512);
+  // feeds as many sinks as possible; many sinks take more, to even out the last round.  Between
+  // 128 and 256 sinks 1024 won over 512 and 2048 (4-5% at N_i = 128 and 256, both precisions)
+  const int target = ni >= 16384 ? 4096 : (ni > 256 ? 2048 : (ni >= 128 ? 1024 : 512));
   const int64_t part_cap = (int64_t)1 << 21;
   int scap = (int)(part_cap / (ni > 0 ? ni : 1));
   if (scap > ntiles) scap = ntiles;
