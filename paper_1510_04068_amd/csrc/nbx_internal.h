@@ -101,6 +101,10 @@ struct ForceParams {
   double *part;
   uint64_t *part_key;
   int32_t *part_idx;
+  // with the nearest-neighbour search and S > 1: the FP64 predicted position of each sink,
+  // part_xi[3*q + k], written by the split-0 workgroups during their sink set-up so that the
+  // combine's exact |r|^2 needs no second load of the sink's address and state (null: not kept)
+  double *part_xi;
   int *err;  // device-side error counters: [0] bad sink address, [1] bad source address, [2] list overflow
   // block time-step step (bs_fuse != 0, only with S > 1): the combine kernel corrects particle
   // bs.list[q] at time bs_t1 instead of writing sink q's outputs

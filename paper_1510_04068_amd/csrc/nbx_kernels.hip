@@ -976,14 +976,18 @@ __device__ __forceinline__ void group_reduce(int gs, double (&v)[P][K], uint64_t
 
 // ---------------------------------------------------------------------------------------------
 // Exact FP64 |r|^2 between sink q and source idx (inf when idx is no source): the sink is its own
-// predicted source addr, or its explicit position.  Same predictor as the staging, so the value
-// is the one the oracle computes from the predicted positions.
+// predicted source addr, or its explicit position, or the position xi_pre the caller already has
+// (the same bits: the gravity kernel's set-up predicted it with this predictor).  Same predictor
+// as the staging, so the value is the one the oracle computes from the predicted positions.
 // ---------------------------------------------------------------------------------------------
 template <int Order>
-__device__ double nn_exact_r2(const ForceParams &fp, int q, int addr, int idx) {
+__device__ double nn_exact_r2(const ForceParams &fp, int q, int addr, int idx, const double *xi_pre) {
   if (idx < 0 || idx >= fp.nj) return __builtin_huge_val();
   double xi[3], vi[3], ai[6], mi, xj[3], vj[3], aj[6], mj;
-  if (fp.ext_x) {
+  if (xi_pre) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) xi[k] = xi_pre[k];
+  } else if (fp.ext_x) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) xi[k] = fp.ext_x[3 * (size_t)q + k];
   } else {
@@ -997,10 +1001,10 @@ __device__ double nn_exact_r2(const ForceParams &fp, int q, int addr, int idx) {
   }
 }
 
-// Final write of one sink: results, nearest neighbour id and its exact FP64 |r|^2 (r2 given by
-// the split that found the neighbour, or computed here when r2 is null).
+// Final write of one sink: results, nearest neighbour id and its exact FP64 |r|^2 (xi: the sink's
+// predicted position when the caller has it, else null).
 template <int Order, bool NN = true>
-__device__ void finalize_sink(const ForceParams &fp, int q, const double *v, int idx, const double *r2) {
+__device__ void finalize_sink(const ForceParams &fp, int q, const double *v, int idx, const double *xi) {
   const bool ext = fp.ext_x != nullptr;
   const int addr = ext ? -1 : fp.i_addr[q];
   if (!ext && (addr < 0 || addr >= fp.nj)) {
@@ -1018,7 +1022,7 @@ __device__ void finalize_sink(const ForceParams &fp, int q, const double *v, int
   if constexpr (!NN) return;  // the nearest-neighbour outputs are left untouched
   if (idx >= 0 && idx < fp.nj) {
     fp.nn_id[q] = fp.src.id[idx];
-    fp.nn_r2[q] = r2 ? *r2 : nn_exact_r2<Order>(fp, q, addr, idx);
+    fp.nn_r2[q] = nn_exact_r2<Order>(fp, q, addr, idx, xi);
   } else {
     fp.nn_id[q] = -1;
     fp.nn_r2[q] = __builtin_huge_val();
@@ -1259,6 +1263,12 @@ __device__ __forceinline__ void force_item(const ForceParams &fp, int w,
       self[p] = addr;
       predict_addr<Order>(fp.src, addr < 0 ? 0 : addr, fp.t, xp, vp, ap, m);
     }
+    if constexpr (NN) {  // the combine's exact |r|^2 reads the sink's position from here
+      if (fp.part_xi && split == 0 && slot == 0 && live) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) fp.part_xi[3 * (size_t)q[p] + k] = xp[k];
+      }
+    }
     sink[p] = Tr::make_sink(xp, vp, ap, m);
     h2[p] = (Nbr && live) ? (T)fp.h2[q[p]] : T(-1);
     acc[p].init();
@@ -1411,6 +1421,14 @@ __device__ __forceinline__ void combine_block(const ForceParams &fp, int wlog, i
       bs_load_state<Order>(fp.bs, bs_i, st);
     }
   }
+  // the sink's predicted position for the exact nearest-neighbour |r|^2, likewise loaded first
+  double xi[3] = {0.0, 0.0, 0.0};
+  if constexpr (NN) {
+    if (fp.part_xi && r == 0 && qg < fp.ni) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) xi[k] = fp.part_xi[3 * (size_t)qg + k];
+    }
+  }
   if (qg < fp.ni) {
 #pragma unroll 4
     for (int s = r; s < S; s += R) {
@@ -1469,7 +1487,7 @@ __device__ __forceinline__ void combine_block(const ForceParams &fp, int wlog, i
       return;
     }
   }
-  finalize_sink<Order, NN>(fp, qg, w[0], wi[0], nullptr);
+  finalize_sink<Order, NN>(fp, qg, w[0], wi[0], NN && fp.part_xi ? xi : nullptr);
 }
 
 template <int Order, bool NN>

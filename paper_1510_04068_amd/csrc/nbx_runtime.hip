@@ -88,7 +88,7 @@ struct nbx_ctx {
   int32_t *d_nbr_cnt = nullptr;
   int64_t *d_nbr_ids = nullptr;
   // split-combine scratch
-  DevBuf part, part_key, part_idx;
+  DevBuf part, part_key, part_idx, part_xi;
   void *noalloc_scratch = nullptr;  // this device's static scratch (nbx_force_dev_noalloc)
   int *d_err = nullptr;  // [0] bad sink address, [1] bad source address, [2] nbr overflow, [3] dt clamped
                          // (the first 16 bytes of d_out)
@@ -217,7 +217,9 @@ int ensure_scratch(nbx_ctx *c, int ni, const LaunchShape &ls) {
   if (rc) return rc;
   rc = grow(c, c->part_key, n * sizeof(uint64_t));
   if (rc) return rc;
-  return grow(c, c->part_idx, n * sizeof(int32_t));
+  rc = grow(c, c->part_idx, n * sizeof(int32_t));
+  if (rc) return rc;
+  return grow(c, c->part_xi, (size_t)ni * 3 * sizeof(double));
 }
 
 // Wait until the last copy through the staging buffer has finished, then make it hold `bytes`.
@@ -349,11 +351,13 @@ int enqueue_force(nbx_ctx *c, hipStream_t stream, int ni, const int32_t *d_iaddr
   double *part = nullptr;
   uint64_t *part_key = nullptr;
   int32_t *part_idx = nullptr;
+  double *part_xi = nullptr;
   if (fixed_scratch) {
     // the partials go to the fixed area: fewer source splits when the shape needs more room
     const size_t K = (size_t)values_per_sink(c->cfg.order);
     const size_t per_split = align16((size_t)ni * K * 8) + align16((size_t)ni * 8) + align16((size_t)ni * 4);
-    const size_t smax = kNoallocScratchBytes / per_split;
+    const size_t xi_bytes = align16((size_t)ni * 3 * 8);
+    const size_t smax = kNoallocScratchBytes > xi_bytes ? (kNoallocScratchBytes - xi_bytes) / per_split : 0;
     if ((size_t)ls.splits > smax) ls.splits = smax >= 1 ? (int)smax : 1;
     if (ls.splits > 1) {
       char *p = static_cast<char *>(fixed_scratch);
@@ -362,12 +366,15 @@ int enqueue_force(nbx_ctx *c, hipStream_t stream, int ni, const int32_t *d_iaddr
       part_key = reinterpret_cast<uint64_t *>(p);
       p += align16((size_t)ls.splits * (size_t)ni * 8);
       part_idx = reinterpret_cast<int32_t *>(p);
+      p += align16((size_t)ls.splits * (size_t)ni * 4);
+      part_xi = reinterpret_cast<double *>(p);
     }
   } else {
     if (int rc = ensure_scratch(c, ni, ls)) return rc;
     part = static_cast<double *>(c->part.p);
     part_key = static_cast<uint64_t *>(c->part_key.p);
     part_idx = static_cast<int32_t *>(c->part_idx.p);
+    part_xi = static_cast<double *>(c->part_xi.p);
   }
   ForceParams fp{};
   fp.src = c->src;
@@ -400,6 +407,7 @@ int enqueue_force(nbx_ctx *c, hipStream_t stream, int ni, const int32_t *d_iaddr
   fp.part = part;
   fp.part_key = part_key;
   fp.part_idx = part_idx;
+  fp.part_xi = fp.nn && ls.splits > 1 ? part_xi : nullptr;
   fp.part_sm = ls.splits >= kSinkMajorMinS && ni <= kSinkMajorMaxNi ? 1 : 0;
   fp.err = c->d_err;
   if (bs && ls.splits > 1 && !d_h2) {
