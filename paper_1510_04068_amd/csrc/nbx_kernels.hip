@@ -1981,14 +1981,14 @@ int values_per_sink(int order) { return order == 8 ? 13 : (order == 6 ? 10 : (or
 // workgroup holds Q = (256 / L) * P sinks and one of S source ranges.
 //   * About 8 workgroups per CU (2048) fill the 256 CUs; 16 per CU (4096) from N_i = 16384 on,
 //     where every workgroup runs many tiles and a finer split evens out the last round of
-//     workgroups on the CUs (5-7 are resident per CU).
+//     workgroups on the CUs (5-7 are resident per CU); few sinks take 512 (below 128) or 1024
+//     (128 to 256).
 //   * Partials cost S * ni * 72 bytes of scratch traffic: S * ni <= 2^21, and S <= 512 (more
 //     splits only add partial traffic: measured slower at every N_i).
 //   * Staging a tile costs one FP64 prediction per thread, so a thread should get at least 16
 //     interactions per tile: Q >= 16 unless there are fewer sinks than that.
 //   * Two sinks per lane (Q = 512) pay off only at large N_i (>= 65536), where each workgroup
-//     sees many tiles; below that the fixed per-workgroup work of the second sink dominates.
-//     Mixed precision and orders 2 to 6 only.
+//     sees many tiles: mixed precision at orders 2 to 6, FP64 at order 4.
 // Q runs from ni rounded up to a power of two (at most 256, or 512 at large N_i) down to that
 // floor and the first Q that reaches the workgroup target wins (the largest reuse of each staged
 // source); if none does, the floor is used with the largest S allowed.  NBX_SHAPE="L,P,S" in the
@@ -2027,10 +2027,13 @@ LaunchShape choose_shape(int ni, int nj_pad, int prec, int order) {
   int qmin = 1;
   while (qmin < ni && qmin < 16) qmin *= 2;
   int qcover = 1;  // never more sink slots than the next power of two of ni
-  // two sinks per lane pay off only in FP32 arithmetic (FP64 accumulators double the registers),
-  // and not at order 8, where the second sink's 13 sums and jerk push the lane past 256 registers
-  // and the launch loses half its waves
-  const int qtop = ni >= 65536 && prec == NBX_MIXED && order <= 6 ? 2 * kThreads : kThreads;
+  // two sinks per lane from N_i = 65536: in FP32 arithmetic at orders 2-6, and in FP64 at order 4,
+  // where the long-chunk kernel holds two sinks' FP64 sums at two waves per SIMD (2.4% and 2.8%
+  // faster at N_i = 65536 and 131072; 1-10% slower with this rule's splits from 4096 to 32768);
+  // not at order 8, where the second sink's 13 sums and jerk push the lane past 256 registers and
+  // the launch loses half its waves
+  const bool two = ni >= 65536 && ((prec == NBX_MIXED && order <= 6) || (prec == NBX_FP64 && order == 4));
+  const int qtop = two ? 2 * kThreads : kThreads;
   while (qcover < ni && qcover < qtop) qcover *= 2;
   int Q = qcover > qmin ? qcover : qmin;
   for (; Q >= qmin; Q /= 2) {
