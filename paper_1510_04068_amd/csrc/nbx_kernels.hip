@@ -1979,10 +1979,10 @@ int values_per_sink(int order) { return order == 8 ? 13 : (order == 6 ? 10 : (or
 
 // Launch shape (static rule; nbx_tune replaces it by measured choices per N_i class).  A
 // workgroup holds Q = (256 / L) * P sinks and one of S source ranges.
-//   * About 8 workgroups per CU (2048) fill the 256 CUs; 16 per CU (4096) from N_i = 16384 on,
-//     where every workgroup runs many tiles and a finer split evens out the last round of
-//     workgroups on the CUs (5-7 are resident per CU); few sinks take 512 (below 128) or 1024
-//     (128 to 256).
+//   * About 8 workgroups per CU (2048) fill the 256 CUs; 16 per CU (4096) from N_i = 2048 on,
+//     where every workgroup runs several tiles and a finer split evens out the last round of
+//     workgroups on the CUs (5-7 are resident per CU; 2-3% faster at N_i = 2048 and 8192 than
+//     2048 workgroups); few sinks take 512 (below 128) or 1024 (128 to 256).
 //   * Partials cost S * ni * 72 bytes of scratch traffic: S * ni <= 2^21, and S <= 512 (more
 //     splits only add partial traffic: measured slower at every N_i).
 //   * Staging a tile costs one FP64 prediction per thread, so a thread should get at least 16
@@ -2005,7 +2005,7 @@ LaunchShape choose_shape(int ni, int nj_pad, int prec, int order) {
   // workgroups to aim for: few sinks take ~512 (two per CU) so that each staged, predicted source
   // feeds as many sinks as possible; many sinks take more, to even out the last round.  Between
   // 128 and 256 sinks 1024 won over 512 and 2048 (4-5% at N_i = 128 and 256, both precisions)
-  const int target = ni >= 16384 ? 4096 : (ni > 256 ? 2048 : (ni >= 128 ? 1024 : 512));
+  const int target = ni >= 2048 ? 4096 : (ni > 256 ? 2048 : (ni >= 128 ? 1024 : 512));
   const int64_t part_cap = (int64_t)1 << 21;
   int scap = (int)(part_cap / (ni > 0 ? ni : 1));
   if (scap > ntiles) scap = ntiles;
