@@ -909,6 +909,68 @@ __device__ __forceinline__ bool nn_better(uint64_t k1, int i1, uint64_t k2, int 
   return k1 < k2 || (k1 == k2 && (unsigned)i1 < (unsigned)i2);
 }
 
+// Butterfly exchange in VALU (DPP and the row / half-wave swaps) instead of LDS-routed permutes:
+// stage Off returns the value of the partner lane, lane ^ 1 and lane ^ 2 (quad permutes),
+// lane ^ 7 (half-row mirror), lane ^ 15 (row mirror), lane ^ 16 and lane ^ 32 (swaps).  Stages run
+// in increasing order over aligned groups of contiguous lanes: before stage Off every aligned group
+// of Off lanes holds equal values, so the mirror partners stand for the xor partners, and each pair
+// adds a + b on one side and b + a on the other, which IEEE addition makes the same bits.
+template <int Off>
+__device__ __forceinline__ uint32_t lane_xchg32(uint32_t v) {
+  if constexpr (Off == 1) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  } else if constexpr (Off == 2) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+  } else if constexpr (Off == 4) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  } else if constexpr (Off == 8) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, false);  // row_mirror
+  } else if constexpr (Off == 16) {
+    const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);  // [0]: even rows, [1]: odd
+    return ((threadIdx.x >> 4) & 1) ? p[0] : p[1];
+  } else {
+    static_assert(Off == 32, "butterfly stages are 1, 2, 4, 8, 16, 32");
+    const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);  // [0]: low half, [1]: high
+    return (threadIdx.x & 32) ? p[0] : p[1];
+  }
+}
+
+template <int Off>
+__device__ __forceinline__ uint64_t lane_xchg64(uint64_t v) {
+  return ((uint64_t)lane_xchg32<Off>((uint32_t)(v >> 32)) << 32) | lane_xchg32<Off>((uint32_t)v);
+}
+
+template <int Off, int P, int K, bool NN>
+__device__ __forceinline__ void lane_stage(double (&v)[P][K], uint64_t (&kk)[P], int (&ii)[P]) {
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const uint64_t bits = (uint64_t)__double_as_longlong(v[p][k]);
+      v[p][k] += __longlong_as_double((long long)lane_xchg64<Off>(bits));
+    }
+    if constexpr (NN) {
+      const uint64_t ok = lane_xchg64<Off>(kk[p]);
+      const int oi = (int)lane_xchg32<Off>((uint32_t)ii[p]);
+      if (nn_better(ok, oi, kk[p], ii[p])) {
+        kk[p] = ok;
+        ii[p] = oi;
+      }
+    }
+  }
+}
+
+// Reduction over aligned groups of `width` contiguous lanes (a power of two, <= 64).
+template <int P, int K, bool NN>
+__device__ __forceinline__ void lane_butterfly(int width, double (&v)[P][K], uint64_t (&kk)[P], int (&ii)[P]) {
+  if (width > 1) lane_stage<1, P, K, NN>(v, kk, ii);
+  if (width > 2) lane_stage<2, P, K, NN>(v, kk, ii);
+  if (width > 4) lane_stage<4, P, K, NN>(v, kk, ii);
+  if (width > 8) lane_stage<8, P, K, NN>(v, kk, ii);
+  if (width > 16) lane_stage<16, P, K, NN>(v, kk, ii);
+  if (width > 32) lane_stage<32, P, K, NN>(v, kk, ii);
+}
+
 template <int P, int K>
 struct RedLds {
   double v[4][P][K];
@@ -916,21 +978,25 @@ struct RedLds {
   int i[4][P];
 };
 
-template <int P, int K, bool NN = true>
+template <int P, int K, bool NN = true, bool Valu = true>
 __device__ __forceinline__ void group_reduce(int gs, double (&v)[P][K], uint64_t (&kk)[P], int (&ii)[P],
                                              RedLds<P, K> &red) {
   const int wl = gs < 64 ? gs : 64;
-  for (int off = wl >> 1; off > 0; off >>= 1) {
+  if constexpr (Valu) {
+    lane_butterfly<P, K, NN>(wl, v, kk, ii);
+  } else {  // the same butterfly through LDS-routed permutes, largest offset first
+    for (int off = wl >> 1; off > 0; off >>= 1) {
 #pragma unroll
-    for (int p = 0; p < P; ++p) {
+      for (int p = 0; p < P; ++p) {
 #pragma unroll
-      for (int k = 0; k < K; ++k) v[p][k] += __shfl_xor(v[p][k], off);
-      if constexpr (NN) {
-        const uint64_t ok = __shfl_xor(kk[p], off);
-        const int oi = __shfl_xor(ii[p], off);
-        if (nn_better(ok, oi, kk[p], ii[p])) {
-          kk[p] = ok;
-          ii[p] = oi;
+        for (int k = 0; k < K; ++k) v[p][k] += __shfl_xor(v[p][k], off);
+        if constexpr (NN) {
+          const uint64_t ok = __shfl_xor(kk[p], off);
+          const int oi = __shfl_xor(ii[p], off);
+          if (nn_better(ok, oi, kk[p], ii[p])) {
+            kk[p] = ok;
+            ii[p] = oi;
+          }
         }
       }
     }
@@ -1307,7 +1373,10 @@ __device__ __forceinline__ void force_item(const ForceParams &fp, int w,
                                                      lg, self[p], eps2)
                : -1;
   }
-  group_reduce<P, K, NN>(L, v, kk, ii, red);
+  // the kernels with one lane per sink never combine lanes (L = 1) but keep the permute form of
+  // the call: without it, or with the VALU form, the compiler placed the spills of the 128-register
+  // many-sink kernel differently and that kernel ran 2.7-4.4% slower at N_i = 131072
+  group_reduce<P, K, NN, !L1>(L, v, kk, ii, red);
 
   if (S == 1) {
     if (slot == 0) {
@@ -1445,16 +1514,21 @@ __device__ __forceinline__ void combine_block(const ForceParams &fp, int wlog, i
     }
   }
   // lanes of one sink inside a wave (W < 64): butterfly over offsets W .. 32; every lane ends
-  // with the same bits
-  for (int off = 32; off >= W; off >>= 1) {
+  // with the same bits.  With one sink per workgroup (W = 1) the whole wave is one aligned group
+  // and the exchange runs in VALU; with W > 1 a sink's lanes are strided and use permutes.
+  if (W == 1) {
+    lane_butterfly<1, K, NN>(64, w, wk, wi);
+  } else {
+    for (int off = 32; off >= W; off >>= 1) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) w[0][k] += __shfl_xor(w[0][k], off);
-    if constexpr (NN) {
-      const uint64_t ok = __shfl_xor(wk[0], off);
-      const int oi = __shfl_xor(wi[0], off);
-      if (nn_better(ok, oi, wk[0], wi[0])) {
-        wk[0] = ok;
-        wi[0] = oi;
+      for (int k = 0; k < K; ++k) w[0][k] += __shfl_xor(w[0][k], off);
+      if constexpr (NN) {
+        const uint64_t ok = __shfl_xor(wk[0], off);
+        const int oi = __shfl_xor(wi[0], off);
+        if (nn_better(ok, oi, wk[0], wi[0])) {
+          wk[0] = ok;
+          wi[0] = oi;
+        }
       }
     }
   }
@@ -1632,7 +1706,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchParams bp) {
       int wi[1] = {0};
 #pragma unroll
       for (int k = 0; k < K; ++k) w[0][k] = acc.value(k);
-      group_reduce<1, K, false>(L, w, wk, wi, red_unused);  // L <= 64: shuffles only
+      group_reduce<1, K, false>(L, w, wk, wi, red_unused);  // L <= 64: within the wave
       if (slot == 0 && live) {
         const size_t q = (size_t)(b + i);
 #pragma unroll
