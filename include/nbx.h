@@ -244,7 +244,9 @@ int nbx_force_dev(nbx_ctx *ctx, void *stream, int ni, const int32_t *d_i_addr, d
  * device by nbx_open), and calls no hipMalloc, hipFree or allocating library routine.  Same
  * arguments, orders (2, 4, 6; order 8 is NBX_ERR_ARG), want_nn behaviour and errors as
  * nbx_force_dev: ni > ni_max is NBX_ERR_CAPACITY.  Sizes: the partials of S source splits take
- * S * ni * (8 * values + 12) bytes (values: 4, 7 or 10 for orders 2, 4, 6); when the launch shape
+ * S * ni * (8 * values + 12) bytes (values: 4, 7 or 10 for orders 2, 4, 6; each of the three
+ * arrays rounded up to 16 bytes), after 24 bytes per sink (rounded up to 16) for the sinks'
+ * predicted positions that the split combine reads; when the launch shape
  * nbx_force_dev would use needs more than the area holds, the call lowers S until they fit (down to
  * one split, which needs none), so results then differ from nbx_force_dev by summation order only,
  * and are bit-identical where the shape fits.  Every call on one GPU shares its area, which keeps
