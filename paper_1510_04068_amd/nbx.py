@@ -186,10 +186,15 @@ _CTX_INFO = {}
 _DTYPE_NAMES = {"f64": "float64", "i32": "int32", "i64": "int64"}
 
 
-def _torch_dtype(kind):
-    import torch
+_TORCH_DTYPES = {}
 
-    return {"f64": torch.float64, "i32": torch.int32, "i64": torch.int64}[kind]
+
+def _torch_dtype(kind):
+    if not _TORCH_DTYPES:
+        import torch
+
+        _TORCH_DTYPES.update({"f64": torch.float64, "i32": torch.int32, "i64": torch.int64})
+    return _TORCH_DTYPES[kind]
 
 
 def _dptr(t, kind=None, numel=0, ctx=None, name="array"):
@@ -203,27 +208,29 @@ def _dptrs(ctx, specs):
     have the dtype the C ABI reads (kind: "f64", "i32" or "i64"), be contiguous, hold at least numel
     elements and live on the context's GPU; otherwise ValueError is raised before any library call,
     because the kernels would read or write past the tensor.  The layout checks run over every
-    tensor before the placement checks.  Ints pass through as raw device addresses, None as NULL."""
+    tensor before the placement checks.  Ints pass through as raw device addresses, None as NULL.
+    (The checks use the cheap tensor queries, dtype identity, is_cuda and get_device: at small N_i
+    a force call's host time is on the critical path of the step.)"""
     for name, t, kind, numel in specs:
         if t is None or isinstance(t, int):
             continue
-        if kind is not None and t.dtype != _torch_dtype(kind):
+        if kind is not None and t.dtype is not _torch_dtype(kind):
             raise ValueError("%s: dtype %s, the library reads %s" % (name, t.dtype, _DTYPE_NAMES[kind]))
         if not t.is_contiguous():
             raise ValueError("%s: tensor is not contiguous" % name)
         if t.numel() < numel:
             raise ValueError("%s: %d elements, the call needs %d" % (name, t.numel(), numel))
     info = _CTX_INFO.get(getattr(ctx, "value", None))
+    dev = info["device"] if info is not None else None
     out = []
     for name, t, kind, numel in specs:
         if t is None or isinstance(t, int):
             out.append(t)
             continue
-        if t.device.type != "cuda":
+        if not t.is_cuda:
             raise ValueError("%s: tensor is on %s, not on a GPU" % (name, t.device))
-        if info is not None and t.device.index is not None and t.device.index != info["device"]:
-            raise ValueError("%s: tensor is on cuda:%d, the context on cuda:%d" % (name, t.device.index,
-                                                                                   info["device"]))
+        if dev is not None and t.get_device() != dev:
+            raise ValueError("%s: tensor is on cuda:%d, the context on cuda:%d" % (name, t.get_device(), dev))
         out.append(t.data_ptr())
     return out
 
