@@ -287,11 +287,19 @@ struct Mixed {
   using GKey = Key;
   __device__ static __forceinline__ GKey gkey_none() { return ~Key(0); }
   __device__ static __forceinline__ Key group_key(GKey g) { return g; }
+  // the group minimum as a value (a NaN for an empty group, so that no comparison holds); the
+  // neighbour-list test runs once per group on it (tile_compute)
+  static constexpr bool kChunkLists = true;
+  __device__ static __forceinline__ float group_r2(GKey g) { return __uint_as_float(g); }
 
   template <bool Nbr>
-  __device__ static __forceinline__ Key nn_key(const J &j, const Sink &s, float eps2) {
+  __device__ static __forceinline__ float pair_r2(const J &j, const Sink &s, float eps2) {
     float dx, dy, dz;
-    return key_of(diff_d2<!Nbr>(j, s, eps2, dx, dy, dz));
+    return diff_d2<!Nbr>(j, s, eps2, dx, dy, dz);
+  }
+  template <bool Nbr>
+  __device__ static __forceinline__ Key nn_key(const J &j, const Sink &s, float eps2) {
+    return key_of(pair_r2<Nbr>(j, s, eps2));
   }
 
   // One pair; returns the unsoftened |r|^2 for the neighbour-list test (Nbr), else R^2.  NN: keep
@@ -549,11 +557,22 @@ struct F64 {
     if constexpr (kFloatMin) return g < __builtin_huge_val() ? key_of(g) : ~Key(0);
     else return g;
   }
+  // the group minimum as a value (+inf or a NaN for an empty group, so that no comparison holds);
+  // the neighbour-list test runs once per group on it (tile_compute)
+  static constexpr bool kChunkLists = true;
+  __device__ static __forceinline__ double group_r2(GKey g) {
+    if constexpr (kFloatMin) return g;
+    else return __longlong_as_double((long long)g);
+  }
 
   template <bool Nbr>
-  __device__ static __forceinline__ Key nn_key(const J &j, const Sink &s, double eps2) {
+  __device__ static __forceinline__ double pair_r2(const J &j, const Sink &s, double eps2) {
     double dx, dy, dz;
-    return key_of(diff_d2<!Nbr>(j, s, eps2, dx, dy, dz));
+    return diff_d2<!Nbr>(j, s, eps2, dx, dy, dz);
+  }
+  template <bool Nbr>
+  __device__ static __forceinline__ Key nn_key(const J &j, const Sink &s, double eps2) {
+    return key_of(pair_r2<Nbr>(j, s, eps2));
   }
 
   // One pair; as Mixed::interact.
@@ -832,6 +851,9 @@ struct DS {
   using GKey = Key;
   __device__ static __forceinline__ GKey gkey_none() { return ~Key(0); }
   __device__ static __forceinline__ Key group_key(GKey g) { return g; }
+  // the key is the leading FP32 part of |r|^2 while the list test takes its FP64 value: lists keep
+  // the test per pair
+  static constexpr bool kChunkLists = false;
   template <bool Nbr>
   __device__ static __forceinline__ Key nn_key(const J &j, const Sink &s, double) {
     dsf d[3];
@@ -1119,6 +1141,11 @@ __device__ __forceinline__ void tile_compute(const ForceParams &fp, const typena
                                              Comp<typename Tr::Real, Tr::kK> (&acc)[P],
                                              typename Tr::Key (&nnk)[P], int (&nng)[P]) {
   using Key = typename Tr::Key;
+  // lists: the test r^2 < h^2 runs once per group on the group's minimum |r|^2 (which the search
+  // keeps anyway), and only a group whose minimum passes is scanned again, with the same
+  // arithmetic, for its members; the pair loop carries no branch and no atomic
+  constexpr bool kChunkNbr = Nbr && Tr::kChunkLists;
+  constexpr bool kMin = NN || kChunkNbr;  // the group keeps its minimum
   const int per = L1 ? kTile : kTile >> lg;
   constexpr int kCA = Long ? Tr::kLongChunk : kChunkAcc;
   for (int c = 0; c < per; c += kCA) {
@@ -1134,9 +1161,22 @@ __device__ __forceinline__ void tile_compute(const ForceParams &fp, const typena
 #pragma unroll
       for (int p = 0; p < P; ++p) {
         const typename Tr::Real r2 =
-            Tr::template interact<Guard, NN, Nbr>(j, sink[p], eps2, jidx, self[p], acc[p], gmin[p]);
-        if constexpr (Nbr) {
+            Tr::template interact<Guard, kMin, Nbr>(j, sink[p], eps2, jidx, self[p], acc[p], gmin[p]);
+        if constexpr (Nbr && !kChunkNbr) {
           if (r2 < h2[p] && jidx < fp.nj && (!Guard || jidx != self[p])) nbr_append(fp, q[p], jidx);
+        }
+      }
+    }
+    if constexpr (kChunkNbr) {
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        if (Tr::group_r2(gmin[p]) < h2[p]) {  // some source of the group may lie within h
+          for (int u = c; u < ce; ++u) {
+            const int e = L1 ? u : slot + (u << lg);
+            const int jidx = L1 ? jb + u : jb + (u << lg);
+            const typename Tr::Real r2 = Tr::template pair_r2<true>(Tr::load(tl, e), sink[p], eps2);
+            if (r2 < h2[p] && jidx < fp.nj && (!Guard || jidx != self[p])) nbr_append(fp, q[p], jidx);
+          }
         }
       }
     }
