@@ -589,9 +589,12 @@ def blockstep(torch, nbx, ics, sizes, tune=True, order=6, precisions=("fp64", "m
             tt = time.perf_counter()
             if tune:  # launch shapes per N_i class for these sources (setup, not part of the run)
                 ctx.tune(n)
+                print("bench: blockstep order %d n=%d %s shapes tuned in %.1f s" % (
+                    order, n, name, time.perf_counter() - tt), file=sys.stderr, flush=True)
             t1 = time.perf_counter()
-            for k in range(1, 9):  # one time unit in eighths, with a progress line each
-                st = nbx.nbx_bs_run(ctx.ctx, k / 8.0)
+            parts = 16 if n >= 262144 else 8  # one time unit in parts, with a progress line each
+            for k in range(1, parts + 1):
+                st = nbx.nbx_bs_run(ctx.ctx, k / float(parts))
                 print("bench: blockstep order %d n=%d %s t=%g blocks=%d status=%d" % (
                     order, n, name, st["t"], st["block_steps"], st["status"]), file=sys.stderr, flush=True)
                 if st["status"] != nbx.NBX_OK:
