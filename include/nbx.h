@@ -167,7 +167,9 @@ int nbx_predict(nbx_ctx *ctx, double t);
  * predicted source state, so the self pair has r = 0 exactly and is excluded).
  * i_addr[ni] host array, each in [0, nj); eps2 >= 0; h2[ni] squared neighbour radii or NULL
  * (no lists).  Results stay on the device until nbx_get_force / nbx_get_nbr.  Enqueued on the
- * context's stream; returns without waiting for the GPU. */
+ * context's stream; returns without waiting for the GPU.  ni = 0 is a no-op; with ni > 0 and no
+ * sources in use (nj = 0) every force call, this one and the explicit-sink and device-memory
+ * forms, returns NBX_ERR_STATE. */
 int nbx_force(nbx_ctx *ctx, int ni, const int32_t *i_addr, double eps2, const double *h2);
 
 /* Forces on ni sinks given explicitly (they need not be sources): id[ni], x, v [ni][3] (v may be

@@ -346,6 +346,8 @@ int enqueue_force(nbx_ctx *c, hipStream_t stream, int ni, const int32_t *d_iaddr
   if (!c->predicted) return fail(c, NBX_ERR_STATE, "nbx_force before nbx_predict");
   if (!(eps2 >= 0.0)) return fail(c, NBX_ERR_ARG, "eps2 must be >= 0 (got %g)", eps2);
   if (ni == 0) return NBX_OK;
+  // every force path, explicit sinks included: sinks with no sources are a caller's slip
+  if (c->nj < 1) return fail(c, NBX_ERR_STATE, "no sources in use (nbx_set_nj)");
   const int nj_pad = (c->nj + kTile - 1) / kTile * kTile;
   LaunchShape ls = ctx_shape(c, ni, nj_pad);
   double *part = nullptr;
@@ -753,6 +755,7 @@ int nbx_force(nbx_ctx *c, int ni, const int32_t *i_addr, double eps2, const doub
   if (ni < 0) return fail(c, NBX_ERR_ARG, "ni < 0");
   if (ni > c->cfg.ni_max) return fail(c, NBX_ERR_CAPACITY, "ni=%d > ni_max=%d", ni, c->cfg.ni_max);
   if (ni > 0 && !i_addr) return fail(c, NBX_ERR_ARG, "i_addr is NULL");
+  if (ni > 0 && c->nj < 1) return fail(c, NBX_ERR_STATE, "no sources in use (nbx_set_nj)");
   for (int k = 0; k < ni; ++k)
     if (i_addr[k] < 0 || i_addr[k] >= c->nj)
       return fail(c, NBX_ERR_ARG, "i_addr[%d]=%d outside [0, nj=%d)", k, i_addr[k], c->nj);

@@ -229,6 +229,39 @@ def test_error_paths():
         np.testing.assert_array_equal(back["x"], src.x)
         np.testing.assert_array_equal(back["jerk"], src.jerk)
         np.testing.assert_array_equal(back["id"], src.ids)
+        # the number of sources in use: [0, nj_max], else a capacity error
+        for bad in (-1, n + 1):
+            with pytest.raises(nbx.NbxError) as e:
+                ctx.set_nj(bad)
+            assert e.value.code == nbx.NBX_ERR_CAPACITY
+    # no sources in use: every force form refuses sinks with a state error, zero sinks stay a no-op
+    torch = pytest.importorskip("torch")
+    dev = torch.device("cuda:0")
+    with nbx.Context(order=4, nj_max=n, ni_max=100) as ctx:
+        ctx.predict(0.0)
+        sinks = nbody_ics.make_sources(4, seed=33)
+        with pytest.raises(nbx.NbxError) as e:
+            ctx.force(np.arange(4, dtype=np.int32), 1e-4)
+        assert e.value.code == nbx.NBX_ERR_STATE
+        with pytest.raises(nbx.NbxError) as e:
+            ctx.force_ext(sinks.ids, sinks.x, sinks.v, None, 1e-4)
+        assert e.value.code == nbx.NBX_ERR_STATE
+        f64 = dict(dtype=torch.float64, device=dev)
+        outs = (torch.empty((4, 3), **f64), torch.empty((4, 3), **f64), None, torch.empty(4, **f64),
+                torch.empty(4, dtype=torch.int64, device=dev), torch.empty(4, **f64))
+        d_addr = torch.zeros(4, dtype=torch.int32, device=dev)
+        with pytest.raises(nbx.NbxError) as e:
+            nbx.nbx_force_dev(ctx.ctx, None, 4, d_addr, 1e-4, None, *outs)
+        assert e.value.code == nbx.NBX_ERR_STATE
+        ctx.force(np.zeros(0, dtype=np.int32), 1e-4)
+        ctx.force_ext(sinks.ids[:0], sinks.x[:0], sinks.v[:0], None, 1e-4)
+        # sources loaded afterwards: the same context computes again
+        ctx.set_sources(src)
+        ctx.predict(0.0)
+        sel = np.arange(0, n, 7, dtype=np.int32)[:100]
+        out = run_gpu(ctx, sel, 1e-4)
+        ref = oracle_all(src, 4, 1e-4, 0.0, addr=sel)
+        assert rel_err_vec(out["acc"], ref["acc"]).max() <= 1e-13
 
 
 def test_device_path_matches_host_path():
