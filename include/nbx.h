@@ -80,6 +80,8 @@
  *     has finished it.
  *   - A context is not thread-safe: use one context per host thread.
  *   - NaN and inf in inputs propagate as IEEE values; they are not checked.
+ *   - eps2 = 0 is allowed.  A sink's own source is always excluded, but a distinct source
+ *     at exactly the sink's position then gives inf/NaN (the unsoftened pair force).
  */
 #ifndef NBX_H
 #define NBX_H
