@@ -374,6 +374,51 @@ def test_full_size_same_state(prec):
         assert e_acc[kappa <= 5].max() <= 1e-6 and e_pot.max() <= 1e-6 and e_jc.max() <= 2e-6
 
 
+@pytest.mark.parametrize("prec", [nbx.NBX_FP64, nbx.NBX_MIXED])
+def test_large_n_same_state(prec):
+    """Past the headline sizes: N = 2^22 + 77 Plummer sources (a ragged last tile), every t_j = 0
+    and predicted to t = 0 (identical inputs on both sides), eps2 = 1e-6; 3000 sinks (split sources)
+    and 2^21 + 5 sinks, above the 2^21 cap on sinks x splits of partials, so one split takes every
+    source and writes the outputs itself.  128 seeded sinks of each launch against the oracle.
+    FP64: each pair term carries a few ulps and a 64-term chunk adds at most 63 u in plain FP64 before
+    its compensated fold, so |da| / sum_j |a_ij| <= ~70 u = 7.8e-15 (bound 1e-14), and the plain
+    relative bound 1e-13 holds where kappa <= 10; mixed: the bounds of test_full_size_sampled."""
+    n, eps2, big = (1 << 22) + 77, 1e-6, (1 << 21) + 5
+    say("large n same state prec=%s n=%d" % (PREC_NAME[prec], n))
+    src = nbody_ics.make_sources(n, seed=3, time_offsets=False)
+    assert np.all(src.t == 0.0)
+    rng = np.random.default_rng(79)
+    with nbx.Context(order=4, precision=prec, nj_max=n, ni_max=big) as ctx:
+        ctx.set_sources(src)
+        ctx.predict(0.0)
+        for ni in (3000, big):
+            sel = nbody_ics.active_set(n, ni, seed=1003)
+            shape = ctx.launch_shape(ni)
+            say("  ni=%d shape=%s" % (ni, shape))
+            assert (shape["splits"] == 1) == (ni == big)
+            out = run_gpu(ctx, sel, eps2)
+            pick = np.sort(rng.choice(ni, size=128, replace=False))
+            a = sel[pick]
+            ref = oracle.force(4, eps2, src.ids, src.m, src.x, src.v, src.ids[a], src.x[a], src.v[a])
+            e_acc = rel_err_vec(out["acc"][pick], ref["acc"])
+            kappa = ref["cond"][:, 0] / np.linalg.norm(ref["acc"], axis=1)
+            e_pot = np.abs(out["pot"][pick] - ref["pot"]) / np.abs(ref["pot"])
+            e_jc = cond_err_vec(out["jerk"][pick], ref["jerk"], ref["cond"][:, 1])
+            w = int(np.argmax(e_acc))
+            say("  ni=%d max rel acc %.2e (kappa %.1f there) acc/cond %.2e pot %.2e jerk/cond %.2e" % (
+                ni, e_acc.max(), kappa[w], (e_acc / kappa).max(), e_pot.max(), e_jc.max()))
+            got = {k: (v[pick] if v is not None else None) for k, v in out.items() if k != "status"}
+            mism = check_nn(got, ref, src.x, a, prec, src.ids, eps2=eps2)
+            say("  ni=%d nn-mismatch %d" % (ni, mism))
+            if prec == nbx.NBX_FP64:
+                assert (e_acc / kappa).max() <= 1e-14 and e_acc[kappa <= 10].max() <= 1e-13
+                assert e_pot.max() <= 1e-13 and e_jc.max() <= 1e-13
+                assert mism == 0
+            else:
+                assert (e_acc / kappa).max() <= 5e-7
+                assert e_acc[kappa <= 5].max() <= 1e-6 and e_pot.max() <= 1e-6 and e_jc.max() <= 2e-6
+
+
 def _pair_r2(xp, sink_x):
     d = xp[None, :, :] - sink_x[:, None, :]
     return np.sum(d * d, axis=2)
